@@ -1,0 +1,173 @@
+"""FP64 CPU oracle for the stereo multichannel ray caster.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by the
+benchmark's CPU-baseline leg, never by the product library or its binding.
+It shares no code with the GPU path.  The arithmetic lives in ``oracle.c``;
+this module only marshals numpy arrays into it through ctypes.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+__all__ = ["Volume", "Transfer", "Camera", "sample", "render", "load"]
+
+_lib = None
+
+
+class _Volume(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("channels", C.c_int32), ("bytes_per_voxel", C.c_int32),
+                ("bits", C.c_int32), ("spacing", C.c_double * 3),
+                ("origin", C.c_double * 3), ("data", C.c_void_p)]
+
+
+class _Transfer(C.Structure):
+    _fields_ = [("lo", C.c_double), ("hi", C.c_double), ("curve", C.c_double),
+                ("alpha_mul", C.c_double), ("rgb", C.c_double * 3),
+                ("visible", C.c_int32)]
+
+
+class _Camera(C.Structure):
+    _fields_ = [("projection", C.c_int32), ("center", C.c_double * 3),
+                ("forward", C.c_double * 3), ("up", C.c_double * 3),
+                ("fov_y", C.c_double), ("ortho_height", C.c_double),
+                ("eye_separation", C.c_double), ("convergence", C.c_double)]
+
+
+class _View(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("eye", C.c_int32),
+                ("step", C.c_double), ("term_alpha", C.c_double),
+                ("band_eps", C.c_double), ("background", C.c_double * 4)]
+
+
+def load():
+    """Load liboracle.so, building it first if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        lib = C.CDLL(LIB)
+        lib.orc_sample.argtypes = [C.POINTER(_Volume), C.POINTER(C.c_double),
+                                   C.POINTER(C.c_double)]
+        lib.orc_sample.restype = C.c_int
+        lib.orc_sample_points.argtypes = [C.POINTER(_Volume), C.c_void_p, C.c_int64,
+                                          C.c_void_p]
+        lib.orc_sample_points.restype = C.c_int
+        P = C.c_void_p
+        lib.orc_render.argtypes = [C.POINTER(_Volume), C.POINTER(_Transfer),
+                                   C.POINTER(_Camera), C.POINTER(_View), P,
+                                   C.c_int64, P, P, P, P, P, P, P, C.c_int]
+        lib.orc_render.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+class Volume:
+    """One frame of a multichannel volume: ``data`` is [C][Z][Y][X] uint8/uint16."""
+
+    def __init__(self, data, bits=None, spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0)):
+        data = np.ascontiguousarray(data)
+        if data.ndim == 3:
+            data = data[None]
+        if data.dtype not in (np.uint8, np.uint16):
+            raise TypeError("voxels must be uint8 or uint16")
+        self.data = data
+        self.bits = int(bits if bits is not None else 8 * data.dtype.itemsize)
+        self.spacing = tuple(float(s) for s in spacing)
+        self.origin = tuple(float(o) for o in origin)
+
+    def _c(self):
+        c, nz, ny, nx = self.data.shape
+        return _Volume(nx, ny, nz, c, self.data.dtype.itemsize, self.bits,
+                       (C.c_double * 3)(*self.spacing), (C.c_double * 3)(*self.origin),
+                       self.data.ctypes.data)
+
+
+class Transfer:
+    def __init__(self, lo=0.0, hi=1.0, curve=0.0, alpha_mul=1.0, rgb=(1.0, 1.0, 1.0),
+                 visible=True):
+        self.lo, self.hi, self.curve, self.alpha_mul = float(lo), float(hi), float(curve), float(alpha_mul)
+        self.rgb = tuple(float(x) for x in rgb)
+        self.visible = bool(visible)
+
+    def _c(self):
+        return _Transfer(self.lo, self.hi, self.curve, self.alpha_mul,
+                         (C.c_double * 3)(*self.rgb), int(self.visible))
+
+
+class Camera:
+    def __init__(self, projection="perspective", center=(0, 0, 0), forward=(0, 0, 1),
+                 up=(0, -1, 0), fov_y=0.785398, ortho_height=1.0, eye_separation=0.0,
+                 convergence=1.0):
+        self.projection = 1 if projection in ("perspective", 1) else 0
+        self.center = tuple(float(x) for x in center)
+        self.forward = tuple(float(x) for x in forward)
+        self.up = tuple(float(x) for x in up)
+        self.fov_y = float(fov_y)
+        self.ortho_height = float(ortho_height)
+        self.eye_separation = float(eye_separation)
+        self.convergence = float(convergence)
+
+    def _c(self):
+        d3 = C.c_double * 3
+        return _Camera(self.projection, d3(*self.center), d3(*self.forward), d3(*self.up),
+                       self.fov_y, self.ortho_height, self.eye_separation, self.convergence)
+
+
+def sample(vol: Volume, points):
+    """Trilinear field (raw intensity units) of every channel at index-space
+    points [n][3] (x, y, z).  Returns float64 [n][C]."""
+    lib = load()
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    cv = vol._c()
+    out = np.zeros((pts.shape[0], vol.data.shape[0]), dtype=np.float64)
+    lib.orc_sample_points(C.byref(cv), pts.ctypes.data, pts.shape[0], out.ctypes.data)
+    return out
+
+
+def render(vol: Volume, transfers, cam: Camera, width, height, eye=0, step=1.0,
+           term_alpha=1.0, band_eps=1e-3, background=(0, 0, 0, 0), pixels=None,
+           nthreads=None):
+    """Render one eye (-1 left, 0 mono, +1 right).  ``pixels`` is an optional
+    int64 array of linear pixel indices j * width + i.  Returns a dict of
+    float64 / int32 numpy arrays keyed rgba, samples, nominal, count_margin,
+    band_lo, band_hi, band_k."""
+    lib = load()
+    if len(transfers) != vol.data.shape[0]:
+        raise ValueError("one transfer function per channel is required")
+    tfs = (_Transfer * len(transfers))(*[t._c() for t in transfers])
+    view = _View(int(width), int(height), int(eye), float(step), float(term_alpha),
+                 float(band_eps), (C.c_double * 4)(*[float(b) for b in background]))
+    if pixels is None:
+        npix = int(width) * int(height)
+        pix_ptr = None
+    else:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        npix = pixels.size
+        pix_ptr = pixels.ctypes.data
+    res = {
+        "rgba": np.zeros((npix, 4), np.float64),
+        "samples": np.zeros(npix, np.int32),
+        "nominal": np.zeros(npix, np.int32),
+        "count_margin": np.zeros(npix, np.float64),
+        "band_lo": np.zeros((npix, 4), np.float64),
+        "band_hi": np.zeros((npix, 4), np.float64),
+        "band_k": np.zeros((npix, 2), np.int32),
+    }
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    cv, cc = vol._c(), cam._c()
+    rc = lib.orc_render(C.byref(cv), tfs, C.byref(cc), C.byref(view), pix_ptr, npix,
+                        res["rgba"].ctypes.data, res["samples"].ctypes.data,
+                        res["nominal"].ctypes.data, res["count_margin"].ctypes.data,
+                        res["band_lo"].ctypes.data, res["band_hi"].ctypes.data,
+                        res["band_k"].ctypes.data, int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_render rejected its arguments")
+    if pixels is None:
+        for key in res:
+            res[key] = res[key].reshape((int(height), int(width)) + res[key].shape[1:])
+    return res

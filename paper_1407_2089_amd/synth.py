@@ -1,0 +1,254 @@
+"""Seeded synthetic inputs: volumes, transfer functions and cameras.
+
+These stand in for the paper's confocal sequences (Methods: adult mouse SVZ
+explants, one channel of stem cells and one of ependyma / vasculature, 512 x
+512 x 25 stacks every 20 minutes, low-SNR fluorescence).  The recordings are
+not available, so each workload is drawn from a seed with the same shapes,
+channel roles and intensity character: Gaussian blobs, ellipsoidal cells,
+spline-shaped vessels and shot noise.
+
+This module holds no rendering arithmetic.  It produces the voxel arrays and
+the parameter records that both the GPU path and the CPU oracle consume.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# --------------------------------------------------------------- parameters
+
+
+@dataclass
+class TF:
+    """Transfer-function sliders for one channel (floor, ceiling, curve,
+    alpha multiplier, colour, visibility)."""
+    lo: float = 0.0
+    hi: float = 1.0
+    curve: float = 0.0
+    alpha_mul: float = 1.0
+    rgb: tuple = (1.0, 1.0, 1.0)
+    visible: bool = True
+
+
+@dataclass
+class Cam:
+    projection: str = "perspective"  # or "ortho"
+    center: tuple = (0.0, 0.0, 0.0)
+    forward: tuple = (0.0, 0.0, 1.0)
+    up: tuple = (0.0, -1.0, 0.0)
+    fov_y: float = math.radians(45.0)
+    ortho_height: float = 1.0
+    eye_separation: float = 0.0
+    convergence: float = 1.0
+
+
+@dataclass
+class Scene:
+    """One frame of one workload: voxels [C][Z][Y][X] plus everything a render
+    request needs."""
+    name: str
+    volume: np.ndarray
+    bits: int
+    tfs: list
+    cam: Cam
+    width: int
+    height: int
+    stereo: bool
+    step: float
+    term_alpha: float
+    background: tuple = (0.0, 0.0, 0.0, 0.0)
+    spacing: tuple = (1.0, 1.0, 1.0)
+    origin: tuple = (0.0, 0.0, 0.0)
+    extra: dict = field(default_factory=dict)
+
+
+# ------------------------------------------------------------------ cameras
+
+
+def orbit_camera(dims, azimuth_deg, elevation_deg, fov_deg, dist_scale=1.0,
+                 stereo=True, spacing=(1.0, 1.0, 1.0)):
+    """Perspective camera looking at the volume centre from (azimuth,
+    elevation); distance chosen so the bounding sphere fills the vertical
+    field of view (times dist_scale).  Separation is distance / 30 and the
+    zero-parallax plane passes through the volume centre."""
+    nx, ny, nz = dims
+    ext = np.array([(nx - 1) * spacing[0], (ny - 1) * spacing[1], (nz - 1) * spacing[2]])
+    centre = ext / 2.0
+    radius = 0.5 * float(np.linalg.norm([nx * spacing[0], ny * spacing[1], nz * spacing[2]]))
+    dist = radius / math.sin(math.radians(fov_deg) / 2.0) * dist_scale
+    az, el = math.radians(azimuth_deg), math.radians(elevation_deg)
+    offset = np.array([math.cos(el) * math.cos(az), math.cos(el) * math.sin(az), math.sin(el)])
+    eye = centre + dist * offset
+    forward = -offset
+    up = np.array([0.0, 0.0, 1.0])
+    if abs(float(np.dot(up, forward))) > 0.99:
+        up = np.array([0.0, 1.0, 0.0])
+    return Cam("perspective", tuple(eye), tuple(forward), tuple(up), math.radians(fov_deg),
+               1.0, dist / 30.0 if stereo else 0.0, dist)
+
+
+def random_view_camera(rng, dims, stereo=True):
+    """View direction uniform on the sphere, fov U[30, 60] degrees, distance
+    R / sin(fov / 2) * U[1, 1.5]."""
+    v = rng.normal(size=3)
+    v /= np.linalg.norm(v)
+    az = math.degrees(math.atan2(v[1], v[0]))
+    el = math.degrees(math.asin(max(-1.0, min(1.0, v[2]))))
+    fov = rng.uniform(30.0, 60.0)
+    return orbit_camera(dims, az, el, fov, rng.uniform(1.0, 1.5), stereo)
+
+
+# ------------------------------------------------------------ shape stamps
+
+
+def _rotation(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def _window(shape_zyx, centre_xyz, half):
+    nz, ny, nx = shape_zyx
+    lo = [max(0, int(math.floor(centre_xyz[a] - half))) for a in range(3)]
+    hi = [min((nx, ny, nz)[a], int(math.ceil(centre_xyz[a] + half)) + 1) for a in range(3)]
+    if any(hi[a] <= lo[a] for a in range(3)):
+        return None
+    z, y, x = np.meshgrid(np.arange(lo[2], hi[2]), np.arange(lo[1], hi[1]),
+                          np.arange(lo[0], hi[0]), indexing="ij")
+    sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+    return sl, x.astype(np.float32), y.astype(np.float32), z.astype(np.float32)
+
+
+def stamp_ellipsoid(buf, centre, radii, rot, peak):
+    """Max-combine an ellipsoid with a one-voxel soft edge into buf [Z][Y][X]."""
+    w = _window(buf.shape, centre, max(radii) + 1.5)
+    if w is None:
+        return
+    sl, x, y, z = w
+    d = np.stack([x - centre[0], y - centre[1], z - centre[2]], axis=-1)
+    q = d @ rot  # local coordinates (rot columns are the axes)
+    rho = np.sqrt(((q / np.asarray(radii)) ** 2).sum(-1))
+    s = (rho - 1.0) * min(radii)
+    val = peak * np.clip(0.5 - s, 0.0, 1.0)
+    np.maximum(buf[sl], val.astype(buf.dtype), out=buf[sl])
+
+
+def catmull_rom(points, per_unit=2.0):
+    """Dense samples of the Catmull-Rom cubic spline through the control
+    points (end points repeated)."""
+    p = np.asarray(points, dtype=np.float64)
+    p = np.vstack([p[:1], p, p[-1:]])
+    out = []
+    for s in range(1, len(p) - 2):
+        p0, p1, p2, p3 = p[s - 1], p[s], p[s + 1], p[s + 2]
+        n = max(2, int(np.linalg.norm(p2 - p1) * per_unit))
+        t = np.linspace(0.0, 1.0, n, endpoint=False)[:, None]
+        out.append(0.5 * ((2 * p1) + (-p0 + p2) * t + (2 * p0 - 5 * p1 + 4 * p2 - p3) * t * t
+                          + (-p0 + 3 * p1 - 3 * p2 + p3) * t * t * t))
+    out.append(p[-2][None])
+    return np.vstack(out)
+
+
+def stamp_tube(buf, points, radius, peak):
+    """Max-combine a tube of the given radius (soft one-voxel edge) around a
+    dense polyline into buf."""
+    for c in points:
+        w = _window(buf.shape, c, radius + 1.5)
+        if w is None:
+            continue
+        sl, x, y, z = w
+        dist = np.sqrt((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2)
+        val = peak * np.clip(radius + 0.5 - dist, 0.0, 1.0)
+        np.maximum(buf[sl], val.astype(buf.dtype), out=buf[sl])
+
+
+# ---------------------------------------------------------------- volumes
+
+
+def blobs_u8(dims, n_blobs, sigma, peak, noise_max, seed):
+    """Gaussian blobs (centres U[8, n - 8]) plus integer-uniform noise, uint8."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    val = np.zeros((nz, ny, nx), np.float64)
+    for _ in range(n_blobs):
+        c = [rng.uniform(8, n - 8) for n in (nx, ny, nz)]
+        r2 = (x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2
+        val += peak * np.exp(-r2 / (2.0 * sigma * sigma))
+    val += rng.integers(0, noise_max + 1, size=val.shape)
+    return np.clip(np.rint(val), 0, 255).astype(np.uint8)[None]
+
+
+def cells_and_vessels(dims, channels, bits, seed, n_cells=40, n_tubes=10,
+                      background=100.0):
+    """Confocal-like multichannel frame, [C][Z][Y][X].  Channel 0: ellipsoidal
+    cells (radii U[4, 8]); channel 1: cubic-spline vessels (radius 3);
+    channels 2 and 3: small round nuclei and puncta.  Counts scale with the
+    volume.  Shot noise: Poisson(background + signal), clipped to full scale."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = dims
+    full = (1 << bits) - 1
+    scale = full / 4095.0
+    out_dtype = np.uint8 if bits <= 8 else np.uint16
+    vol = np.zeros((channels, nz, ny, nx), out_dtype)
+    for c in range(channels):
+        sig = np.zeros((nz, ny, nx), np.float32)
+        if c == 0:
+            for _ in range(n_cells):
+                centre = [rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz)]
+                radii = rng.uniform(4.0, 8.0, size=3)
+                stamp_ellipsoid(sig, centre, radii, _rotation(rng), rng.uniform(1200, 3000) * scale)
+        elif c == 1:
+            for _ in range(n_tubes):
+                k = int(rng.integers(4, 7))
+                ctrl = np.column_stack([rng.uniform(0, nx, k), rng.uniform(0, ny, k),
+                                        rng.uniform(0, nz, k)])
+                stamp_tube(sig, catmull_rom(ctrl), 3.0, rng.uniform(1500, 3500) * scale)
+        else:
+            n = max(1, n_cells * (4 if c == 2 else 20) // 4)
+            rad = 2.0 if c == 2 else 1.0
+            for _ in range(n):
+                centre = [rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz)]
+                stamp_ellipsoid(sig, centre, (rad, rad, rad), np.eye(3),
+                                rng.uniform(1200, 3000) * scale)
+        noisy = rng.poisson(background * scale + sig.astype(np.float64))
+        vol[c] = np.minimum(noisy, full).astype(out_dtype)
+    return vol
+
+
+# --------------------------------------------------------------- workloads
+
+
+def tiny_scene(seed=1):
+    """1-channel 64x64x32 uint8: three Gaussian blobs (sigma 3, peak 200)
+    plus uniform noise 0..20; one 256x256 orthographic mono view along +z,
+    step 0.5, linear-ramp alpha, no early termination."""
+    vol = blobs_u8((64, 64, 32), 3, 3.0, 200.0, 20, seed)
+    cam = Cam("ortho", (31.5, 31.5, -10.0), (0.0, 0.0, 1.0), (0.0, -1.0, 0.0),
+              ortho_height=64.0)
+    return Scene("tiny 1ch u8 64x64x32, 256x256 ortho mono", vol, 8, [TF()], cam,
+                 256, 256, False, 0.5, 1.0)
+
+
+def realistic_scene(seed=2, width=1920, height=1080, dims=(512, 512, 64)):
+    """2-channel 12-bit uint16 512x512x64: 40 ellipsoidal cells (green) and 10
+    spline vessels (red) with Poisson noise; perspective stereo 1920x1080 per
+    eye from azimuth 30, elevation 50 degrees, fov 45; step 1, early
+    termination at alpha 0.99."""
+    vol = cells_and_vessels(dims, 2, 12, seed, n_cells=40, n_tubes=10)
+    cam = orbit_camera(dims, 30.0, 50.0, 45.0)
+    lo, hi = 300.0 / 4095.0, 3000.0 / 4095.0
+    tfs = [TF(lo, hi, 0.0, 1.0, (0.0, 1.0, 0.0)), TF(lo, hi, 0.0, 1.0, (1.0, 0.0, 0.0))]
+    return Scene(f"realistic 2ch u16-12 {dims[0]}x{dims[1]}x{dims[2]}, "
+                 f"{width}x{height} perspective stereo", vol, 12, tfs, cam,
+                 width, height, True, 1.0, 0.99)
+
+
+SCENES = {"tiny": tiny_scene, "realistic": realistic_scene}
