@@ -1,0 +1,159 @@
+"""Benchmark: stereo multichannel ray casting on one MI355X.
+
+Default workload: 2-channel 12-bit uint16 512x512x64 confocal-like volume
+(40 ellipsoidal cells, 10 spline vessels, Poisson noise), perspective stereo
+pair 1920x1080 per eye, step 1 voxel, early termination at alpha 0.99, FP32.
+One step = one stereo pair (one vr_render launch, both eyes).  Prints one
+JSON line: ray-samples/s (composited samples, the method's nominal count),
+stereo frames/s, the HBM roofline of the render kernel on effective sampled
+bytes (8 taps x channels x bytes per voxel per sample), and the FP64 CPU
+oracle timed on a bounded pixel sample of the same frame.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scene, target_s=12.0):
+    """Time the FP64 oracle on seeded random pixels of both eyes."""
+    import numpy as np
+
+    import oracle
+    cores = os.cpu_count() or 1
+    ov = oracle.Volume(scene.volume, scene.bits, scene.spacing, scene.origin)
+    tfs = [oracle.Transfer(t.lo, t.hi, t.curve, t.alpha_mul, t.rgb, t.visible) for t in scene.tfs]
+    c = scene.cam
+    cam = oracle.Camera(c.projection, c.center, c.forward, c.up, c.fov_y, c.ortho_height,
+                        c.eye_separation, c.convergence)
+    rng = np.random.default_rng(12345)
+    npx = scene.width * scene.height
+
+    def run(n):
+        pix = rng.choice(npx, size=min(n, npx), replace=False)
+        t0 = time.perf_counter()
+        s = 0
+        for eye in (-1, 1):
+            r = oracle.render(ov, tfs, cam, scene.width, scene.height, eye, scene.step,
+                              scene.term_alpha, pixels=pix, nthreads=cores)
+            s += int(r["samples"].sum())
+        return s, time.perf_counter() - t0, 2 * len(pix)
+
+    s, dt, rays = run(20000)
+    n = int(20000 * max(1.0, target_s / max(dt, 1e-3)))
+    if n > 20000:
+        s, dt, rays = run(n)
+    return {"value": s / dt, "unit": "ray-samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"{rays} seeded random pixels of the same stereo pair "
+                      f"({rays // 2} per eye), FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", choices=["fp32", "fp16"], default="fp32")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(rays, eyes and requests shard across GPUs with no exchange; see the "
+              "design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1407_2089_amd as vr
+    from paper_1407_2089_amd import synth
+
+    log("generating workload")
+    sc = synth.realistic_scene()
+    ctx = vr.Context(0)
+    c, nz, ny, nx = sc.volume.shape
+    vol = vr.Volume(ctx, (nx, ny, nz), c, 1, vr.VR_U16, sc.bits)
+    stream = torch.cuda.current_stream()
+    vol.upload(0, torch.from_numpy(sc.volume.view(np.int16)).cuda(), stream)
+    for ch, tf in enumerate(sc.tfs):
+        vol.set_transfer(ch, tf)
+    prec = vr.VR_FP16 if args.precision == "fp16" else vr.VR_FP32
+    out = torch.empty((2, sc.height, sc.width, 4), dtype=torch.float32, device="cuda")
+    smp = torch.empty((2, sc.height, sc.width), dtype=torch.int32, device="cuda")
+
+    # Count the composited samples of one step (the frame is the same every step).
+    req_count = vr.make_request(vol.ptr, 0, sc.cam, sc.width, sc.height, True, sc.step,
+                                sc.term_alpha, out, precision=prec, out_samples=smp)
+    vr.vr_render(ctx.ptr, req_count, stream)
+    torch.cuda.synchronize()
+    samples_per_step = int(smp.sum().item())
+    req = vr.make_request(vol.ptr, 0, sc.cam, sc.width, sc.height, True, sc.step,
+                          sc.term_alpha, out, precision=prec)
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        vr.vr_render(ctx.ptr, req, stream)
+    torch.cuda.synchronize()
+
+    log(f"timing {args.steps} steps")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        vr.vr_render(ctx.ptr, req, stream)
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ms_per_step = 1000.0 * wall / args.steps
+    value = samples_per_step * args.steps / wall
+
+    bytes_per_sample = 8 * c * 2
+    alg_bytes = samples_per_step * bytes_per_sample
+    achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    result = {
+        "metric": "ray-samples/s",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16-sample/f32-composite" if prec == vr.VR_FP16 else "f32",
+        "data": "synthetic",
+        "config": {"workload": "realistic frame: 2ch u16-12 512x512x64 cells+vessels, "
+                               "perspective stereo 1920x1080 per eye, step 1, alpha 0.99",
+                   "eyes": 2, "width": sc.width, "height": sc.height,
+                   "samples_per_step": samples_per_step},
+        "stereo_fps": args.steps / wall,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "render_kernel<2ch,u16,fp32>", "kernel_ms": kernel_ms,
+                     "bytes_per_launch": alg_bytes},
+    }
+    vol.destroy()
+    ctx.close()
+    if not args.no_cpu:
+        log("cpu baseline")
+        result["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,220 @@
+/*
+ * vr.h — C ABI of the MI355X stereo multichannel volume ray caster.
+ *
+ * The library renders 5-D (x, y, z, t, channel) microscopy series that stay
+ * resident in GPU memory, as in the paper's viewer: the whole image sequence
+ * is downloaded to video memory once (Methods, acquisition paragraph; User
+ * Interface, work-flow paragraph), each channel gets a colour, a visibility
+ * toggle and a floor / ceiling / curve / alpha-multiplier transfer function
+ * (User Interface, transfer-function paragraph), the volume is drawn for a
+ * view and shown in stereo (User Interface; Results and Discussion), the user
+ * steps through time points (Results and Discussion), and the CPU stays free
+ * while the GPU renders (Abstract).
+ *
+ * Conventions for every entry point:
+ *  - Every function returns a vr_status; no C++ exception crosses the ABI.
+ *    On an error, vr_last_error() returns a message for the calling thread.
+ *  - Argument errors are detected before anything is enqueued: a call that
+ *    returns VR_ERR_INVALID_ARG has launched no GPU work and changed no state.
+ *  - "device" pointers are HIP device addresses on the context's GPU, owned by
+ *    the caller.  The library borrows them: volume storage until
+ *    vr_destroy_volume, render inputs and outputs until the enqueued work has
+ *    finished on the given stream (or the ticket is done / failed).
+ *  - hip_stream arguments are hipStream_t values passed as void*; NULL is the
+ *    default stream.  Rendering calls are asynchronous: they return after the
+ *    kernels are enqueued.
+ *  - Volume storage layout is private to the library (brick-major, channel-
+ *    interleaved, zero halo); callers size it with vr_volume_storage_bytes.
+ *
+ * Threads: calls on distinct volumes may run concurrently; vr_submit and
+ * vr_poll are thread-safe; calls on one volume must not race with
+ * vr_destroy_volume of that volume.
+ */
+#ifndef VR_H
+#define VR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VR_OK = 0,
+    VR_ERR_INVALID_ARG = -1,   /* bad argument; nothing was enqueued            */
+    VR_ERR_OUT_OF_MEMORY = -2, /* memory budget or storage size exceeded       */
+    VR_ERR_NOT_FOUND = -3,     /* unknown ticket                                */
+    VR_ERR_BUSY = -4,          /* queue full, or object referenced by tickets  */
+    VR_ERR_DEVICE = -5,        /* a HIP runtime call failed                     */
+    VR_ERR_UNSUPPORTED = -6    /* no GPU in this context, or not a gfx950 GPU   */
+} vr_status;
+
+typedef struct vr_ctx vr_ctx;       /* one per GPU; owns streams, events, tables */
+typedef struct vr_volume vr_volume; /* one resident multichannel time series     */
+
+typedef enum { VR_U8 = 1, VR_U16 = 2 } vr_dtype;
+typedef enum { VR_FP32 = 0, VR_FP16 = 1 } vr_precision;
+typedef enum { VR_ORTHO = 0, VR_PERSPECTIVE = 1 } vr_projection;
+
+/* A 5-D series: frames x channels x nz x ny x nx voxels.  Voxel (i, j, k) of
+ * a frame sits at world position origin + (i sx, j sy, k sz), with the
+ * anisotropic spacing taken from the acquisition metadata (Methods, import
+ * paragraph).  Normalised intensity is raw / (2^bits - 1): 255 for 8-bit data
+ * as the transfer-function description states, 4095 for 12-bit, 65535 for
+ * 16-bit. */
+typedef struct {
+    int32_t nx, ny, nz; /* >= 1 each, <= 8192                                */
+    int32_t channels;   /* 1..4                                              */
+    int32_t frames;     /* >= 1 time points                                  */
+    int32_t dtype;      /* vr_dtype                                          */
+    int32_t bits;       /* VR_U8: 8.  VR_U16: 9..16                          */
+    float spacing[3];   /* > 0, world units per voxel along x, y, z          */
+    float origin[3];    /* world position of voxel (0, 0, 0)                 */
+    int32_t brick[3];   /* brick edge per axis, each 4, 8, 16 or 32; all 0
+                           selects the library default.  Fixed at creation.  */
+} vr_volume_desc;
+
+/* One channel's transfer function (User Interface, transfer-function
+ * paragraph): u = clamp((x - lo) / (hi - lo), 0, 1) on normalised intensity
+ * x; curve g = (1 - curve) u + curve u^2; channel alpha = alpha_mul * g;
+ * channel colour = g * rgb.  A sample's alpha is the largest visible channel
+ * alpha capped at 1, its colour the per-component sum of the visible
+ * channels' colours capped at 1. */
+typedef struct {
+    float lo, hi;     /* 0 <= lo < hi <= 1                                   */
+    float curve;      /* [-1, 1]; 0 = linear ramp                            */
+    float alpha_mul;  /* [0, 2]; 1 = slider centre                           */
+    float rgb[3];     /* [0, 1] each                                         */
+    int32_t visible;  /* 0 hides the channel                                 */
+} vr_transfer;
+
+/* View.  Basis: f = normalise(forward), r = normalise(f x up), u = r x f.
+ * Pixel (i, j) has its centre at (i + 1/2, j + 1/2), row 0 at the top;
+ * screen coordinates sx = 2 (i + 1/2) / W - 1, sy = 1 - 2 (j + 1/2) / H.
+ * Perspective: eye e = center + s (eye_separation / 2) r with s = -1 for the
+ * left eye, +1 for the right and 0 for mono; both eyes look through one
+ * screen at distance `convergence` (half-height convergence * tan(fov_y / 2),
+ * aspect W / H); ray from e through the screen point, t >= 0.
+ * Orthographic (mono only): rays along f from the screen rectangle of height
+ * ortho_height centred on `center`, unbounded in t. */
+typedef struct {
+    int32_t projection;   /* vr_projection                                   */
+    float center[3];
+    float forward[3];     /* non-zero                                        */
+    float up[3];          /* not parallel to forward                         */
+    float fov_y;          /* radians in (0, pi), perspective                 */
+    float ortho_height;   /* > 0, orthographic                               */
+    float eye_separation; /* >= 0; 0 renders identical eyes                  */
+    float convergence;    /* > 0, perspective                                */
+} vr_camera;
+
+/* One render request: a frame of a volume seen from a camera, one eye
+ * (stereo = 0) or a left / right pair (stereo = 1, perspective only).
+ * Samples sit at world distances t_enter + (k + 1/2) step along each ray
+ * inside the box [-1, n] (index space) while t < t_exit; compositing is
+ * front to back and stops after the first sample at which the accumulated
+ * alpha reaches term_alpha (1 = no early stop).  The result is
+ * rgb = C + (1 - A) bg_a bg_rgb, alpha = A + (1 - A) bg_a. */
+typedef struct {
+    vr_volume* vol;
+    int32_t frame;          /* 0 .. frames - 1                                */
+    vr_camera cam;
+    int32_t width, height;  /* >= 0, <= 16384; a zero size renders nothing   */
+    int32_t stereo;         /* 0 mono, 1 left + right                        */
+    float step;             /* world units, > 0                               */
+    float term_alpha;       /* (0, 1]                                         */
+    float background[4];    /* rgb, a in [0, 1]                               */
+    int32_t precision;      /* vr_precision: FP16 samples, FP32 compositing  */
+    float* out_rgba;        /* device, [eyes][height][width][4] float32       */
+    int32_t* out_samples;   /* device, [eyes][height][width] or NULL: samples
+                               composited per pixel                          */
+} vr_render_req;
+
+/* Ticket state reported by vr_poll. */
+typedef struct {
+    int32_t state;        /* 0 pending, 1 running, 2 done, 3 failed          */
+    int32_t err;          /* vr_status of a failed ticket                    */
+    uint64_t t_arrive_ns; /* steady-clock stamps; 0 until reached            */
+    uint64_t t_admit_ns;
+    uint64_t t_start_ns;
+    uint64_t t_done_ns;
+    uint64_t rays;        /* pixels x eyes of the request                    */
+} vr_ticket_info;
+
+/* Open a context on HIP device `device` with a memory budget for volumes and
+ * in-flight served requests (0 = the device's free memory at open time minus
+ * a 4 GiB reserve).  device = -1 opens a validation-only context with no GPU:
+ * every call validates its arguments, then calls that need a GPU return
+ * VR_ERR_UNSUPPORTED.  *out receives the context. */
+vr_status vr_init(int32_t device, uint64_t mem_budget_bytes, vr_ctx** out);
+
+/* Stop the serving thread and free the context.  VR_ERR_BUSY while served
+ * tickets are pending or running, or volumes are still alive. */
+vr_status vr_shutdown(vr_ctx* ctx);
+
+/* Bytes of device storage a volume with this description needs (all
+ * frames).  Pure host computation. */
+vr_status vr_volume_storage_bytes(const vr_volume_desc* desc, uint64_t* bytes);
+
+/* Register a resident series in caller-owned device storage of at least
+ * vr_volume_storage_bytes(desc) bytes, 256-byte aligned.  Its bytes count
+ * against the context's budget (VR_ERR_OUT_OF_MEMORY when they do not fit).
+ * All channels start with the default transfer function (lo 0, hi 1, curve 0,
+ * alpha_mul 1, white, visible).  Contents are undefined until uploaded. */
+vr_status vr_create_volume(vr_ctx* ctx, const vr_volume_desc* desc, void* dev_storage,
+                           uint64_t storage_bytes, vr_volume** out);
+
+/* Copy one frame into the volume's storage on `hip_stream`.  dev_src is a
+ * device array [channels][nz][ny][nx] of uint8 or uint16 (the volume's
+ * dtype), contiguous; values above 2^bits - 1 are clamped to it. */
+vr_status vr_upload_frame(vr_volume* vol, int32_t frame, const void* dev_src,
+                          void* hip_stream);
+
+/* Unregister a volume and return its bytes to the budget.  VR_ERR_BUSY while
+ * a served ticket that reads it is pending or running. */
+vr_status vr_destroy_volume(vr_volume* vol);
+
+/* Set channel `channel`'s transfer function; copied.  Requests enqueued or
+ * submitted earlier keep the function they were given. */
+vr_status vr_set_transfer(vr_volume* vol, int32_t channel, const vr_transfer* tf);
+
+/* Enqueue one request on `hip_stream` (one kernel launch per call). */
+vr_status vr_render(vr_ctx* ctx, const vr_render_req* req, void* hip_stream);
+
+/* Enqueue n requests as one persistent, load-balanced launch (replayed from
+ * a captured HIP graph) on `hip_stream`.  Every request's output is bitwise
+ * identical to what vr_render gives for it alone.  n = 0 is a no-op. */
+vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
+                          void* hip_stream);
+
+/* Queue a request for the context's serving loop and return at once with a
+ * ticket.  The loop admits queued requests when a slot is free and their
+ * output bytes fit in the budget, batches the admitted ones, and overlaps
+ * batches on several streams.  The request (and the volume's transfer
+ * functions) are copied now.  VR_ERR_BUSY when 4096 tickets are pending. */
+vr_status vr_submit(vr_ctx* ctx, const vr_render_req* req, uint64_t* ticket);
+
+/* State and timestamps of a ticket.  Tickets stay queryable until released.
+ * VR_ERR_NOT_FOUND for an unknown or released ticket. */
+vr_status vr_poll(vr_ctx* ctx, uint64_t ticket, vr_ticket_info* info);
+
+/* Forget a finished (done or failed) ticket.  VR_ERR_BUSY if it is still
+ * pending or running; VR_ERR_NOT_FOUND if unknown. */
+vr_status vr_release(vr_ctx* ctx, uint64_t ticket);
+
+/* Message of the calling thread's last error ("" after success).  Valid
+ * until the thread's next vr_* call. */
+const char* vr_last_error(void);
+
+/* Test hook: trilinear field of every channel of `frame` at n index-space
+ * points pts [n][3] (x, y, z), written to out [n][channels] float32 in raw
+ * intensity units, through the renderer's own sampling code.  pts and out
+ * are device pointers. */
+vr_status vr_debug_sample(vr_volume* vol, int32_t frame, const float* pts, int32_t n,
+                          float* out, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VR_H */

@@ -1,0 +1,277 @@
+"""Python binding of libvr, the MI355X stereo multichannel volume ray caster.
+
+The functions named ``vr_*`` mirror the C ABI in ``include/vr.h`` one to one
+and only marshal arguments through ctypes: every step of rendering runs in
+the library's HIP kernels.  A non-OK status raises :class:`VrError`.  The
+small classes at the bottom (``Context``, ``Volume``) use PyTorch for device
+memory and streams and call the same functions.
+
+The library must be built (``__graft_entry__.build()``); importing this
+module never falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+__all__ = [
+    "VrError", "lib", "vr_init", "vr_shutdown", "vr_volume_storage_bytes",
+    "vr_create_volume", "vr_upload_frame", "vr_destroy_volume", "vr_set_transfer",
+    "vr_render", "vr_render_batch", "vr_submit", "vr_poll", "vr_release",
+    "vr_last_error", "vr_debug_sample", "Context", "Volume", "VR_U8", "VR_U16",
+    "VR_FP32", "VR_FP16", "VR_ORTHO", "VR_PERSPECTIVE",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvr.so")
+
+VR_OK, VR_ERR_INVALID_ARG, VR_ERR_OUT_OF_MEMORY, VR_ERR_NOT_FOUND = 0, -1, -2, -3
+VR_ERR_BUSY, VR_ERR_DEVICE, VR_ERR_UNSUPPORTED = -4, -5, -6
+VR_U8, VR_U16 = 1, 2
+VR_FP32, VR_FP16 = 0, 1
+VR_ORTHO, VR_PERSPECTIVE = 0, 1
+STATUS_NAMES = {0: "VR_OK", -1: "VR_ERR_INVALID_ARG", -2: "VR_ERR_OUT_OF_MEMORY",
+                -3: "VR_ERR_NOT_FOUND", -4: "VR_ERR_BUSY", -5: "VR_ERR_DEVICE",
+                -6: "VR_ERR_UNSUPPORTED"}
+
+
+class VrError(RuntimeError):
+    def __init__(self, status, message):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+
+
+class vr_volume_desc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("channels", C.c_int32), ("frames", C.c_int32), ("dtype", C.c_int32),
+                ("bits", C.c_int32), ("spacing", C.c_float * 3), ("origin", C.c_float * 3),
+                ("brick", C.c_int32 * 3)]
+
+
+class vr_transfer(C.Structure):
+    _fields_ = [("lo", C.c_float), ("hi", C.c_float), ("curve", C.c_float),
+                ("alpha_mul", C.c_float), ("rgb", C.c_float * 3), ("visible", C.c_int32)]
+
+
+class vr_camera(C.Structure):
+    _fields_ = [("projection", C.c_int32), ("center", C.c_float * 3),
+                ("forward", C.c_float * 3), ("up", C.c_float * 3), ("fov_y", C.c_float),
+                ("ortho_height", C.c_float), ("eye_separation", C.c_float),
+                ("convergence", C.c_float)]
+
+
+class vr_render_req(C.Structure):
+    _fields_ = [("vol", C.c_void_p), ("frame", C.c_int32), ("cam", vr_camera),
+                ("width", C.c_int32), ("height", C.c_int32), ("stereo", C.c_int32),
+                ("step", C.c_float), ("term_alpha", C.c_float),
+                ("background", C.c_float * 4), ("precision", C.c_int32),
+                ("out_rgba", C.c_void_p), ("out_samples", C.c_void_p)]
+
+
+class vr_ticket_info(C.Structure):
+    _fields_ = [("state", C.c_int32), ("err", C.c_int32), ("t_arrive_ns", C.c_uint64),
+                ("t_admit_ns", C.c_uint64), ("t_start_ns", C.c_uint64),
+                ("t_done_ns", C.c_uint64), ("rays", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libvr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        P, S = C.c_void_p, C.c_int
+        sig = {
+            "vr_init": [C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)],
+            "vr_shutdown": [P],
+            "vr_volume_storage_bytes": [C.POINTER(vr_volume_desc), C.POINTER(C.c_uint64)],
+            "vr_create_volume": [P, C.POINTER(vr_volume_desc), P, C.c_uint64,
+                                 C.POINTER(C.c_void_p)],
+            "vr_upload_frame": [P, C.c_int32, P, P],
+            "vr_destroy_volume": [P],
+            "vr_set_transfer": [P, C.c_int32, C.POINTER(vr_transfer)],
+            "vr_render": [P, C.POINTER(vr_render_req), P],
+            "vr_render_batch": [P, C.POINTER(vr_render_req), C.c_int32, P],
+            "vr_submit": [P, C.POINTER(vr_render_req), C.POINTER(C.c_uint64)],
+            "vr_poll": [P, C.c_uint64, C.POINTER(vr_ticket_info)],
+            "vr_release": [P, C.c_uint64],
+            "vr_debug_sample": [P, C.c_int32, P, C.c_int32, P, P],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = S
+        L.vr_last_error.argtypes = []
+        L.vr_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def vr_last_error() -> str:
+    return lib().vr_last_error().decode()
+
+
+def _check(status):
+    if status != VR_OK:
+        raise VrError(status, vr_last_error())
+    return status
+
+
+def _ptr(x):
+    """Device address of a torch tensor, an int, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(s):
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+# ------------------------------------------------------------- C ABI mirror
+
+def vr_init(device: int = 0, mem_budget_bytes: int = 0):
+    out = C.c_void_p()
+    _check(lib().vr_init(device, mem_budget_bytes, C.byref(out)))
+    return out.value
+
+
+def vr_shutdown(ctx):
+    _check(lib().vr_shutdown(ctx))
+
+
+def vr_volume_storage_bytes(desc: vr_volume_desc) -> int:
+    out = C.c_uint64()
+    _check(lib().vr_volume_storage_bytes(C.byref(desc), C.byref(out)))
+    return out.value
+
+
+def vr_create_volume(ctx, desc: vr_volume_desc, dev_storage, storage_bytes: int):
+    out = C.c_void_p()
+    _check(lib().vr_create_volume(ctx, C.byref(desc), _ptr(dev_storage), storage_bytes,
+                                  C.byref(out)))
+    return out.value
+
+
+def vr_upload_frame(vol, frame: int, dev_src, stream=None):
+    _check(lib().vr_upload_frame(vol, frame, _ptr(dev_src), _stream(stream)))
+
+
+def vr_destroy_volume(vol):
+    _check(lib().vr_destroy_volume(vol))
+
+
+def vr_set_transfer(vol, channel: int, tf: vr_transfer):
+    _check(lib().vr_set_transfer(vol, channel, C.byref(tf)))
+
+
+def vr_render(ctx, req: vr_render_req, stream=None):
+    _check(lib().vr_render(ctx, C.byref(req), _stream(stream)))
+
+
+def vr_render_batch(ctx, reqs, stream=None):
+    n = len(reqs)
+    arr = (vr_render_req * max(n, 1))(*reqs)
+    _check(lib().vr_render_batch(ctx, arr, n, _stream(stream)))
+
+
+def vr_submit(ctx, req: vr_render_req) -> int:
+    t = C.c_uint64()
+    _check(lib().vr_submit(ctx, C.byref(req), C.byref(t)))
+    return t.value
+
+
+def vr_poll(ctx, ticket: int) -> vr_ticket_info:
+    info = vr_ticket_info()
+    _check(lib().vr_poll(ctx, ticket, C.byref(info)))
+    return info
+
+
+def vr_release(ctx, ticket: int):
+    _check(lib().vr_release(ctx, ticket))
+
+
+def vr_debug_sample(vol, frame: int, pts, n: int, out, stream=None):
+    _check(lib().vr_debug_sample(vol, frame, _ptr(pts), n, _ptr(out), _stream(stream)))
+
+
+# ---------------------------------------------------------- record helpers
+
+def make_transfer(lo=0.0, hi=1.0, curve=0.0, alpha_mul=1.0, rgb=(1.0, 1.0, 1.0), visible=True):
+    return vr_transfer(lo, hi, curve, alpha_mul, (C.c_float * 3)(*rgb), int(bool(visible)))
+
+
+def make_camera(cam) -> vr_camera:
+    """vr_camera from any object with the synth.Cam fields."""
+    f3 = C.c_float * 3
+    proj = VR_PERSPECTIVE if cam.projection in ("perspective", VR_PERSPECTIVE) else VR_ORTHO
+    return vr_camera(proj, f3(*cam.center), f3(*cam.forward), f3(*cam.up), cam.fov_y,
+                     cam.ortho_height, cam.eye_separation, cam.convergence)
+
+
+def make_request(vol, frame, cam, width, height, stereo, step, term_alpha, out_rgba,
+                 background=(0.0, 0.0, 0.0, 0.0), precision=VR_FP32, out_samples=None):
+    return vr_render_req(vol, frame, make_camera(cam), width, height, int(bool(stereo)),
+                         step, term_alpha, (C.c_float * 4)(*background), precision,
+                         _ptr(out_rgba), _ptr(out_samples))
+
+
+# --------------------------------------------------------- torch helpers
+
+class Context:
+    """A libvr context on one GPU (torch provides memory and streams)."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 0):
+        self.device = device
+        self.ptr = vr_init(device, mem_budget_bytes)
+
+    def close(self):
+        if self.ptr:
+            vr_shutdown(self.ptr)
+            self.ptr = None
+
+
+class Volume:
+    """A resident series in torch-allocated device storage."""
+
+    def __init__(self, ctx: Context, dims, channels, frames=1, dtype=VR_U8, bits=None,
+                 spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), brick=(0, 0, 0)):
+        import torch
+        nx, ny, nz = dims
+        bits = bits if bits is not None else (8 if dtype == VR_U8 else 16)
+        self.desc = vr_volume_desc(nx, ny, nz, channels, frames, dtype, bits,
+                                   (C.c_float * 3)(*spacing), (C.c_float * 3)(*origin),
+                                   (C.c_int32 * 3)(*brick))
+        self.bytes = vr_volume_storage_bytes(self.desc)
+        self.storage = torch.empty(self.bytes + 256, dtype=torch.uint8,
+                                   device=f"cuda:{ctx.device}")
+        base = self.storage.data_ptr()
+        self.base = (base + 255) & ~255
+        self.ctx = ctx
+        self.ptr = vr_create_volume(ctx.ptr, self.desc, self.base, self.bytes)
+        self.channels = channels
+
+    def upload(self, frame, src, stream=None):
+        """src: torch device tensor [C][Z][Y][X] of uint8 / int16-viewed uint16."""
+        if not src.is_contiguous():
+            raise ValueError("source frame must be contiguous")
+        vr_upload_frame(self.ptr, frame, src, stream)
+
+    def set_transfer(self, channel, tf):
+        if not isinstance(tf, vr_transfer):
+            tf = make_transfer(tf.lo, tf.hi, tf.curve, tf.alpha_mul, tf.rgb, tf.visible)
+        vr_set_transfer(self.ptr, channel, tf)
+
+    def destroy(self):
+        if self.ptr:
+            vr_destroy_volume(self.ptr)
+            self.ptr = None

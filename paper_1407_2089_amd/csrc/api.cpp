@@ -1,0 +1,464 @@
+// C ABI of libvr: contexts, resident volumes, transfer functions, the plain
+// render call, validation and error reporting.  Batched launches live in
+// batch.cpp, the serving loop in server.cpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+
+#include "lib.h"
+
+namespace vr {
+
+static thread_local std::string t_err;
+
+vr_status fail(vr_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return st;
+}
+
+vr_status ok() {
+    t_err.clear();
+    return VR_OK;
+}
+
+vr_status hip_fail(hipError_t e, const char* what) {
+    return fail(VR_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool finite3(const float* v) {
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+static int log2_exact(int v) {
+    int s = 0;
+    while ((1 << s) < v) ++s;
+    return (1 << s) == v ? s : -1;
+}
+
+constexpr int kDefaultBrick = 16;
+
+static void brick_edges(const vr_volume_desc& d, int b[3]) {
+    const bool dflt = d.brick[0] == 0 && d.brick[1] == 0 && d.brick[2] == 0;
+    for (int a = 0; a < 3; ++a) b[a] = dflt ? kDefaultBrick : d.brick[a];
+}
+
+BrickGeom make_geom(const vr_volume_desc& d) {
+    BrickGeom g{};
+    int b[3];
+    brick_edges(d, b);
+    const int n[3] = {d.nx, d.ny, d.nz};
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = n[a];
+        g.shift[a] = log2_exact(b[a]);
+        g.nb[a] = (n[a] + 1 + b[a] - 1) / b[a];
+    }
+    g.row = b[0] + 1;
+    g.plane = (b[0] + 1) * (b[1] + 1);
+    g.brick = g.plane * (b[2] + 1);
+    g.word = word_bytes(d.channels, d.dtype == VR_U16);
+    const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
+    g.frame_bytes = (words * (uint64_t)g.word + 255u) & ~(uint64_t)255u;
+    return g;
+}
+
+vr_status check_desc(const vr_volume_desc* d) {
+    if (!d) return fail(VR_ERR_INVALID_ARG, "volume description is NULL");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 8192 || d->ny > 8192 || d->nz > 8192)
+        return fail(VR_ERR_INVALID_ARG, "dimensions %d x %d x %d outside 1..8192", d->nx, d->ny,
+                    d->nz);
+    if (d->channels < 1 || d->channels > kMaxChannels)
+        return fail(VR_ERR_INVALID_ARG, "channels = %d outside 1..4", d->channels);
+    if (d->frames < 1) return fail(VR_ERR_INVALID_ARG, "frames = %d < 1", d->frames);
+    if (d->dtype == VR_U8) {
+        if (d->bits != 8) return fail(VR_ERR_INVALID_ARG, "uint8 volumes need bits = 8");
+    } else if (d->dtype == VR_U16) {
+        if (d->bits < 9 || d->bits > 16)
+            return fail(VR_ERR_INVALID_ARG, "uint16 volumes need bits in 9..16");
+    } else {
+        return fail(VR_ERR_INVALID_ARG, "dtype %d is neither VR_U8 nor VR_U16", d->dtype);
+    }
+    for (int a = 0; a < 3; ++a)
+        if (!(d->spacing[a] > 0.0f) || !std::isfinite(d->spacing[a]))
+            return fail(VR_ERR_INVALID_ARG, "spacing[%d] must be finite and > 0", a);
+    if (!finite3(d->origin)) return fail(VR_ERR_INVALID_ARG, "origin must be finite");
+    const bool dflt = d->brick[0] == 0 && d->brick[1] == 0 && d->brick[2] == 0;
+    if (!dflt)
+        for (int a = 0; a < 3; ++a)
+            if (d->brick[a] != 4 && d->brick[a] != 8 && d->brick[a] != 16 && d->brick[a] != 32)
+                return fail(VR_ERR_INVALID_ARG, "brick[%d] = %d is not 4, 8, 16 or 32", a,
+                            d->brick[a]);
+    const BrickGeom g = make_geom(*d);
+    const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
+    if (words >= (1ull << 31))
+        return fail(VR_ERR_INVALID_ARG, "one frame needs %llu stored voxels (limit 2^31)",
+                    (unsigned long long)words);
+    return VR_OK;
+}
+
+static vr_status check_camera(const vr_camera& c, bool stereo) {
+    if (c.projection != VR_ORTHO && c.projection != VR_PERSPECTIVE)
+        return fail(VR_ERR_INVALID_ARG, "camera projection %d is unknown", c.projection);
+    if (!finite3(c.center) || !finite3(c.forward) || !finite3(c.up))
+        return fail(VR_ERR_INVALID_ARG, "camera vectors must be finite");
+    const double f[3] = {c.forward[0], c.forward[1], c.forward[2]};
+    const double u[3] = {c.up[0], c.up[1], c.up[2]};
+    const double fn = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    const double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(fn > 0.0)) return fail(VR_ERR_INVALID_ARG, "camera forward is zero");
+    const double x[3] = {f[1] * u[2] - f[2] * u[1], f[2] * u[0] - f[0] * u[2],
+                         f[0] * u[1] - f[1] * u[0]};
+    const double xn = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    if (!(un > 0.0) || !(xn > 1e-6 * fn * un))
+        return fail(VR_ERR_INVALID_ARG, "camera up is zero or parallel to forward");
+    if (c.projection == VR_PERSPECTIVE) {
+        if (!(c.fov_y > 0.0f) || !(c.fov_y < 3.14159f))
+            return fail(VR_ERR_INVALID_ARG, "fov_y must lie in (0, pi)");
+        if (!(c.convergence > 0.0f) || !std::isfinite(c.convergence))
+            return fail(VR_ERR_INVALID_ARG, "convergence must be finite and > 0");
+        if (!(c.eye_separation >= 0.0f) || !std::isfinite(c.eye_separation))
+            return fail(VR_ERR_INVALID_ARG, "eye_separation must be finite and >= 0");
+    } else {
+        if (stereo) return fail(VR_ERR_INVALID_ARG, "stereo needs a perspective camera");
+        if (!(c.ortho_height > 0.0f) || !std::isfinite(c.ortho_height))
+            return fail(VR_ERR_INVALID_ARG, "ortho_height must be finite and > 0");
+    }
+    return VR_OK;
+}
+
+vr_status check_request(const vr_ctx* ctx, const vr_render_req* r) {
+    if (!r) return fail(VR_ERR_INVALID_ARG, "request is NULL");
+    if (!r->vol) return fail(VR_ERR_INVALID_ARG, "request has no volume");
+    if (r->vol->ctx != ctx) return fail(VR_ERR_INVALID_ARG, "volume belongs to another context");
+    if (r->frame < 0 || r->frame >= r->vol->desc.frames)
+        return fail(VR_ERR_INVALID_ARG, "frame %d outside 0..%d", r->frame,
+                    r->vol->desc.frames - 1);
+    if (r->width < 0 || r->height < 0 || r->width > 16384 || r->height > 16384)
+        return fail(VR_ERR_INVALID_ARG, "image size %d x %d outside 0..16384", r->width,
+                    r->height);
+    if (r->stereo != 0 && r->stereo != 1) return fail(VR_ERR_INVALID_ARG, "stereo must be 0 or 1");
+    if (!(r->step > 0.0f) || !std::isfinite(r->step))
+        return fail(VR_ERR_INVALID_ARG, "step must be finite and > 0");
+    if (!(r->term_alpha > 0.0f) || !(r->term_alpha <= 1.0f))
+        return fail(VR_ERR_INVALID_ARG, "term_alpha must lie in (0, 1]");
+    for (int q = 0; q < 4; ++q)
+        if (!(r->background[q] >= 0.0f) || !(r->background[q] <= 1.0f))
+            return fail(VR_ERR_INVALID_ARG, "background[%d] outside [0, 1]", q);
+    if (r->precision != VR_FP32 && r->precision != VR_FP16)
+        return fail(VR_ERR_INVALID_ARG, "precision %d is unknown", r->precision);
+    vr_status st = check_camera(r->cam, r->stereo == 1);
+    if (st != VR_OK) return st;
+    if ((int64_t)r->width * r->height > 0 && !r->out_rgba)
+        return fail(VR_ERR_INVALID_ARG, "out_rgba is NULL");
+    return VR_OK;
+}
+
+static vr_status check_transfer(const vr_transfer* t) {
+    if (!t) return fail(VR_ERR_INVALID_ARG, "transfer function is NULL");
+    if (!(t->lo >= 0.0f) || !(t->hi <= 1.0f) || !(t->lo < t->hi))
+        return fail(VR_ERR_INVALID_ARG, "need 0 <= lo < hi <= 1 (lo %g, hi %g)", t->lo, t->hi);
+    if (!(t->curve >= -1.0f) || !(t->curve <= 1.0f))
+        return fail(VR_ERR_INVALID_ARG, "curve %g outside [-1, 1]", t->curve);
+    if (!(t->alpha_mul >= 0.0f) || !(t->alpha_mul <= 2.0f))
+        return fail(VR_ERR_INVALID_ARG, "alpha_mul %g outside [0, 2]", t->alpha_mul);
+    for (int q = 0; q < 3; ++q)
+        if (!(t->rgb[q] >= 0.0f) || !(t->rgb[q] <= 1.0f))
+            return fail(VR_ERR_INVALID_ARG, "rgb[%d] outside [0, 1]", q);
+    return VR_OK;
+}
+
+TileShape default_tile() { return TileShape{8, 8, 2, 2}; }
+
+static void cross(const double a[3], const double b[3], double o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static void normalise(double a[3]) {
+    const double n = std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    for (int q = 0; q < 3; ++q) a[q] /= n;
+}
+
+// Per-eye ray basis in double, rounded once to float.  Perspective: origin is
+// the eye e_s = center + s (sep / 2) r; the unnormalised direction to pixel
+// (sx, sy) is conv f - s (sep / 2) r + sx w r + sy h u.  Orthographic: the
+// origin moves over the screen rectangle, the direction is f.
+void make_params(const vr_render_req& r, const vr_transfer* tf_in, ReqParams* P) {
+    std::memset(P, 0, sizeof *P);
+    const vr_volume& v = *r.vol;
+    const vr_volume_desc& d = v.desc;
+    P->g = v.geom;
+    P->vox = v.storage + (uint64_t)r.frame * v.geom.frame_bytes;
+    P->channels = d.channels;
+    P->variant = variant_index(d.channels, d.dtype == VR_U16, r.precision == VR_FP16);
+
+    const double full = std::ldexp(1.0, d.bits) - 1.0;
+    for (int c = 0; c < d.channels; ++c) {
+        const vr_transfer& t = tf_in[c];
+        ChanTF& o = P->tf[c];
+        const double range = (double)t.hi - (double)t.lo;
+        o.scale = (float)(1.0 / (full * range));
+        o.bias = (float)(-(double)t.lo / range);
+        o.one_m_curve = (float)(1.0 - (double)t.curve);
+        o.curve = t.curve;
+        o.alpha_mul = t.visible ? t.alpha_mul : 0.0f;
+        for (int q = 0; q < 3; ++q) o.rgb[q] = t.visible ? t.rgb[q] : 0.0f;
+    }
+
+    double f[3] = {r.cam.forward[0], r.cam.forward[1], r.cam.forward[2]};
+    const double up[3] = {r.cam.up[0], r.cam.up[1], r.cam.up[2]};
+    normalise(f);
+    double rt[3], u[3];
+    cross(f, up, rt);
+    normalise(rt);
+    cross(rt, f, u);
+    const double sp[3] = {d.spacing[0], d.spacing[1], d.spacing[2]};
+    const double org[3] = {d.origin[0], d.origin[1], d.origin[2]};
+    const double c[3] = {r.cam.center[0], r.cam.center[1], r.cam.center[2]};
+    const double W = r.width > 0 ? r.width : 1, H = r.height > 0 ? r.height : 1;
+    P->eyes = r.stereo ? 2 : 1;
+    if (r.cam.projection == VR_PERSPECTIVE) {
+        const double conv = r.cam.convergence;
+        const double h = conv * std::tan(0.5 * (double)r.cam.fov_y);
+        const double w = h * W / H;
+        const double half_sep = 0.5 * (double)r.cam.eye_separation;
+        for (int e = 0; e < P->eyes; ++e) {
+            const double s = r.stereo ? (e == 0 ? -1.0 : 1.0) : 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double eye = c[a] + s * half_sep * rt[a];
+                P->o0[e][a] = (float)((eye - org[a]) / sp[a]);
+                P->base[e][a] = (float)(conv * f[a] - s * half_sep * rt[a]);
+            }
+        }
+        for (int a = 0; a < 3; ++a) {
+            P->ou[a] = P->ov[a] = 0.0f;
+            P->du[a] = (float)(w * rt[a]);
+            P->dv[a] = (float)(h * u[a]);
+        }
+        P->tmin = 0.0f;
+    } else {
+        const double h = 0.5 * (double)r.cam.ortho_height;
+        const double w = h * W / H;
+        for (int a = 0; a < 3; ++a) {
+            P->o0[0][a] = P->o0[1][a] = (float)((c[a] - org[a]) / sp[a]);
+            P->ou[a] = (float)(w * rt[a] / sp[a]);
+            P->ov[a] = (float)(h * u[a] / sp[a]);
+            P->base[0][a] = P->base[1][a] = (float)f[a];
+            P->du[a] = P->dv[a] = 0.0f;
+        }
+        P->tmin = -std::numeric_limits<float>::infinity();
+    }
+    for (int a = 0; a < 3; ++a) P->inv_sp[a] = (float)(1.0 / sp[a]);
+    P->step = r.step;
+    P->tau = r.term_alpha;
+    const double bga = r.background[3];
+    for (int q = 0; q < 3; ++q) P->bg[q] = (float)(bga * (double)r.background[q]);
+    P->bg[3] = r.background[3];
+    P->sx_scale = (float)(2.0 / W);
+    P->sy_scale = (float)(2.0 / H);
+    P->width = r.width;
+    P->height = r.height;
+    P->out = r.out_rgba;
+    P->samples = r.out_samples;
+}
+
+static void default_transfer(vr_transfer* t) {
+    t->lo = 0.0f;
+    t->hi = 1.0f;
+    t->curve = 0.0f;
+    t->alpha_mul = 1.0f;
+    t->rgb[0] = t->rgb[1] = t->rgb[2] = 1.0f;
+    t->visible = 1;
+}
+
+}  // namespace vr
+
+using namespace vr;
+
+extern "C" {
+
+vr_status vr_init(int32_t device, uint64_t mem_budget_bytes, vr_ctx** out) {
+    if (!out) return fail(VR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (device < -1) return fail(VR_ERR_INVALID_ARG, "device %d is invalid", device);
+    vr_ctx* ctx = new vr_ctx();
+    ctx->device = device;
+    if (device == -1) {
+        ctx->budget = mem_budget_bytes ? mem_budget_bytes : ~0ull;
+        *out = ctx;
+        return ok();
+    }
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || device >= count) {
+        delete ctx;
+        return fail(VR_ERR_UNSUPPORTED, "HIP device %d is not available", device);
+    }
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) {
+        delete ctx;
+        return hip_fail(e, "hipGetDeviceProperties");
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        delete ctx;
+        return fail(VR_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950",
+                    device, prop.gcnArchName);
+    }
+    if ((e = hipSetDevice(device)) != hipSuccess) {
+        delete ctx;
+        return hip_fail(e, "hipSetDevice");
+    }
+    if (mem_budget_bytes == 0) {
+        size_t free_b = 0, total_b = 0;
+        if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) {
+            delete ctx;
+            return hip_fail(e, "hipMemGetInfo");
+        }
+        const uint64_t reserve = 4ull << 30;
+        mem_budget_bytes = free_b > reserve ? free_b - reserve : free_b / 2;
+    }
+    ctx->budget = mem_budget_bytes;
+    ctx->batch_grid = batch_grid_blocks(device);
+    *out = ctx;
+    return ok();
+}
+
+vr_status vr_shutdown(vr_ctx* ctx) {
+    if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    vr_status st = server_stop(ctx);
+    if (st != VR_OK) return st;
+    if (ctx->volumes.load() != 0)
+        return fail(VR_ERR_BUSY, "%d volumes are still alive", ctx->volumes.load());
+    if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+    for (auto& kv : ctx->batch_slots) batch_slot_destroy(kv.second);
+    ctx->batch_slots.clear();
+    delete ctx;
+    return ok();
+}
+
+vr_status vr_volume_storage_bytes(const vr_volume_desc* desc, uint64_t* bytes) {
+    if (!bytes) return fail(VR_ERR_INVALID_ARG, "bytes is NULL");
+    vr_status st = check_desc(desc);
+    if (st != VR_OK) return st;
+    const BrickGeom g = make_geom(*desc);
+    *bytes = g.frame_bytes * (uint64_t)desc->frames;
+    return ok();
+}
+
+vr_status vr_create_volume(vr_ctx* ctx, const vr_volume_desc* desc, void* dev_storage,
+                           uint64_t storage_bytes, vr_volume** out) {
+    if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    if (!out) return fail(VR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    vr_status st = check_desc(desc);
+    if (st != VR_OK) return st;
+    if (!dev_storage) return fail(VR_ERR_INVALID_ARG, "device storage is NULL");
+    if (((uintptr_t)dev_storage & 255u) != 0)
+        return fail(VR_ERR_INVALID_ARG, "device storage must be 256-byte aligned");
+    const BrickGeom g = make_geom(*desc);
+    const uint64_t need = g.frame_bytes * (uint64_t)desc->frames;
+    if (storage_bytes < need)
+        return fail(VR_ERR_OUT_OF_MEMORY, "storage holds %llu bytes, the volume needs %llu",
+                    (unsigned long long)storage_bytes, (unsigned long long)need);
+    uint64_t used = ctx->used.load();
+    do {
+        if (used + need > ctx->budget)
+            return fail(VR_ERR_OUT_OF_MEMORY, "volume needs %llu bytes, %llu of %llu budgeted in use",
+                        (unsigned long long)need, (unsigned long long)used,
+                        (unsigned long long)ctx->budget);
+    } while (!ctx->used.compare_exchange_weak(used, used + need));
+    vr_volume* v = new vr_volume();
+    v->ctx = ctx;
+    v->desc = *desc;
+    v->geom = g;
+    v->storage = (uint8_t*)dev_storage;
+    v->bytes = need;
+    for (int c = 0; c < kMaxChannels; ++c) default_transfer(&v->tf[c]);
+    ctx->volumes.fetch_add(1);
+    *out = v;
+    return ok();
+}
+
+vr_status vr_upload_frame(vr_volume* vol, int32_t frame, const void* dev_src, void* hip_stream) {
+    if (!vol) return fail(VR_ERR_INVALID_ARG, "volume is NULL");
+    if (frame < 0 || frame >= vol->desc.frames)
+        return fail(VR_ERR_INVALID_ARG, "frame %d outside 0..%d", frame, vol->desc.frames - 1);
+    if (!dev_src) return fail(VR_ERR_INVALID_ARG, "source is NULL");
+    if (vol->ctx->device < 0) return fail(VR_ERR_UNSUPPORTED, "validation-only context");
+    hipError_t e = launch_relayout(vol->geom, vol->desc.channels, vol->desc.dtype == VR_U16,
+                                   vol->desc.bits, dev_src,
+                                   vol->storage + (uint64_t)frame * vol->geom.frame_bytes,
+                                   (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "relayout launch");
+    return ok();
+}
+
+vr_status vr_destroy_volume(vr_volume* vol) {
+    if (!vol) return fail(VR_ERR_INVALID_ARG, "volume is NULL");
+    if (vol->in_flight.load() != 0)
+        return fail(VR_ERR_BUSY, "%d served tickets still read this volume", vol->in_flight.load());
+    vr_ctx* ctx = vol->ctx;
+    ctx->used.fetch_sub(vol->bytes);
+    ctx->volumes.fetch_sub(1);
+    delete vol;
+    return ok();
+}
+
+vr_status vr_set_transfer(vr_volume* vol, int32_t channel, const vr_transfer* tf) {
+    if (!vol) return fail(VR_ERR_INVALID_ARG, "volume is NULL");
+    if (channel < 0 || channel >= vol->desc.channels)
+        return fail(VR_ERR_INVALID_ARG, "channel %d outside 0..%d", channel, vol->desc.channels - 1);
+    vr_status st = check_transfer(tf);
+    if (st != VR_OK) return st;
+    std::lock_guard<std::mutex> lk(vol->tf_mu);
+    vol->tf[channel] = *tf;
+    return ok();
+}
+
+vr_status vr_render(vr_ctx* ctx, const vr_render_req* req, void* hip_stream) {
+    if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    vr_status st = check_request(ctx, req);
+    if (st != VR_OK) return st;
+    if (ctx->device < 0) return fail(VR_ERR_UNSUPPORTED, "validation-only context");
+    if ((int64_t)req->width * req->height == 0) return ok();
+    ReqParams P;
+    {
+        std::lock_guard<std::mutex> lk(req->vol->tf_mu);
+        make_params(*req, req->vol->tf, &P);
+    }
+    hipError_t e = launch_render(P, default_tile(), (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    return ok();
+}
+
+vr_status vr_debug_sample(vr_volume* vol, int32_t frame, const float* pts, int32_t n, float* out,
+                          void* hip_stream) {
+    if (!vol) return fail(VR_ERR_INVALID_ARG, "volume is NULL");
+    if (frame < 0 || frame >= vol->desc.frames)
+        return fail(VR_ERR_INVALID_ARG, "frame %d outside 0..%d", frame, vol->desc.frames - 1);
+    if (n < 0) return fail(VR_ERR_INVALID_ARG, "n < 0");
+    if (n > 0 && (!pts || !out)) return fail(VR_ERR_INVALID_ARG, "points or output is NULL");
+    if (vol->ctx->device < 0) return fail(VR_ERR_UNSUPPORTED, "validation-only context");
+    ReqParams P;
+    std::memset(&P, 0, sizeof P);
+    P.g = vol->geom;
+    P.vox = vol->storage + (uint64_t)frame * vol->geom.frame_bytes;
+    P.channels = vol->desc.channels;
+    P.variant = variant_index(vol->desc.channels, vol->desc.dtype == VR_U16, false);
+    hipError_t e = launch_debug_sample(P, pts, n, out, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "debug sample launch");
+    return ok();
+}
+
+const char* vr_last_error(void) { return t_err.c_str(); }
+
+}  // extern "C"

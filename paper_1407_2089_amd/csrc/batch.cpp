@@ -1,0 +1,228 @@
+// Batched rendering: many requests (of different sizes, volumes, channel
+// counts and precisions) in one persistent launch.  Each (request, eye,
+// tile) is one work item; blocks claim items from a device counter, most
+// expensive request first, so one large view does not become the tail.  The
+// launch (counter reset + persistent kernel) is captured once per stream
+// into a HIP graph whose arguments point at fixed device tables; each batch
+// only rewrites the tables.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "lib.h"
+
+namespace vr {
+
+double request_cost(const ReqParams& P) {
+    // Rays times an upper estimate of samples per ray (box diagonal / step).
+    double diag2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double len = (P.g.n[a] + 1.0) / (double)P.inv_sp[a];
+        diag2 += len * len;
+    }
+    const double samples = std::sqrt(diag2) / (double)P.step;
+    return (double)P.eyes * P.width * P.height * samples * (1.0 + 0.25 * P.channels);
+}
+
+static void free_tables(BatchSlot* s) {
+    if (s->d_reqs) (void)hipFree(s->d_reqs);
+    if (s->d_prefix) (void)hipFree(s->d_prefix);
+    if (s->h_reqs) (void)hipHostFree(s->h_reqs);
+    if (s->h_prefix) (void)hipHostFree(s->h_prefix);
+    s->d_reqs = nullptr;
+    s->d_prefix = nullptr;
+    s->h_reqs = nullptr;
+    s->h_prefix = nullptr;
+    s->capacity = 0;
+}
+
+static void drop_graph(BatchSlot* s) {
+    if (s->exec) (void)hipGraphExecDestroy(s->exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->exec = nullptr;
+    s->graph = nullptr;
+}
+
+void batch_slot_destroy(BatchSlot* s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    drop_graph(s);
+    free_tables(s);
+    if (s->d_work) (void)hipFree(s->d_work);
+    if (s->d_counter) (void)hipFree(s->d_counter);
+    if (s->h_work) (void)hipHostFree(s->h_work);
+    if (s->staged) (void)hipEventDestroy(s->staged);
+    if (s->capture) (void)hipStreamDestroy(s->capture);
+    delete s;
+}
+
+static vr_status grow(BatchSlot* s, int cap) {
+    // Earlier launches on this stream may still read the old tables.
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    drop_graph(s);
+    free_tables(s);
+    if ((e = hipMalloc(&s->d_reqs, sizeof(ReqParams) * (size_t)cap)) != hipSuccess ||
+        (e = hipMalloc(&s->d_prefix, sizeof(int32_t) * (size_t)cap)) != hipSuccess ||
+        (e = hipHostMalloc(&s->h_reqs, sizeof(ReqParams) * (size_t)cap, hipHostMallocDefault)) !=
+            hipSuccess ||
+        (e = hipHostMalloc(&s->h_prefix, sizeof(int32_t) * (size_t)cap, hipHostMallocDefault)) !=
+            hipSuccess) {
+        free_tables(s);
+        return fail(VR_ERR_OUT_OF_MEMORY, "batch tables for %d requests: %s", cap,
+                    hipGetErrorString(e));
+    }
+    s->capacity = cap;
+    return VR_OK;
+}
+
+BatchSlot* batch_slot_create(vr_ctx* ctx, hipStream_t stream, vr_status* st) {
+    BatchSlot* s = new BatchSlot();
+    s->stream = stream;
+    s->grid = ctx->batch_grid;
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&s->staged, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipMalloc(&s->d_work, sizeof(BatchWork))) != hipSuccess ||
+        (e = hipMalloc(&s->d_counter, 256)) != hipSuccess ||
+        (e = hipHostMalloc(&s->h_work, sizeof(BatchWork), hipHostMallocDefault)) != hipSuccess) {
+        *st = hip_fail(e, "batch workspace");
+        batch_slot_destroy(s);
+        return nullptr;
+    }
+    *st = grow(s, 64);
+    if (*st != VR_OK) {
+        batch_slot_destroy(s);
+        return nullptr;
+    }
+    return s;
+}
+
+BatchSlot* batch_slot_for(vr_ctx* ctx, hipStream_t stream, vr_status* st) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->batch_slots.find(stream);
+    if (it != ctx->batch_slots.end()) {
+        *st = VR_OK;
+        return it->second;
+    }
+    BatchSlot* s = batch_slot_create(ctx, stream, st);
+    if (s) ctx->batch_slots[stream] = s;
+    return s;
+}
+
+static vr_status capture(BatchSlot* s) {
+    drop_graph(s);
+    hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = launch_batch(s->d_work, s->d_counter, s->grid, s->capture);
+    e = hipStreamEndCapture(s->capture, &s->graph);
+    if (le != hipSuccess) return hip_fail(le, "batch launch capture");
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        drop_graph(s);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return VR_OK;
+}
+
+vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n) {
+    if (n <= 0) return VR_OK;
+    hipError_t e;
+    // Most expensive first.
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost(n);
+    for (int q = 0; q < n; ++q) cost[q] = request_cost(params[q]);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+
+    if (n > s->capacity) {
+        int cap = s->capacity;
+        while (cap < n) cap *= 2;
+        vr_status st = grow(s, cap);
+        if (st != VR_OK) return st;
+    }
+    // The pinned staging buffers are reused: wait until the previous batch's
+    // copies out of them have run.
+    if (s->staged_pending) {
+        if ((e = hipEventSynchronize(s->staged)) != hipSuccess) return hip_fail(e, "staging wait");
+        s->staged_pending = false;
+    }
+    const TileShape ts = ctx->batch_tile;
+    const int bw = ts.wave_w * ts.waves_x, bh = ts.wave_h * ts.waves_y;
+    int64_t items = 0;
+    for (int q = 0; q < n; ++q) {
+        const ReqParams& P = params[order[q]];
+        s->h_reqs[q] = P;
+        s->h_prefix[q] = (int32_t)items;
+        const int64_t tx = (P.width + bw - 1) / bw, ty = (P.height + bh - 1) / bh;
+        items += tx * ty * P.eyes;
+    }
+    if (items == 0) return VR_OK;
+    if (items > 0x7fffffff) return fail(VR_ERR_INVALID_ARG, "batch has too many tiles");
+    BatchWork* w = s->h_work;
+    w->reqs = s->d_reqs;
+    w->prefix = s->d_prefix;
+    w->counter = s->d_counter;
+    w->n_req = n;
+    w->n_items = (int32_t)items;
+    w->tile = ts;
+    if ((e = hipMemcpyAsync(s->d_reqs, s->h_reqs, sizeof(ReqParams) * (size_t)n,
+                            hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(s->d_prefix, s->h_prefix, sizeof(int32_t) * (size_t)n,
+                            hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(s->d_work, s->h_work, sizeof(BatchWork), hipMemcpyHostToDevice,
+                            s->stream)) != hipSuccess)
+        return hip_fail(e, "batch table upload");
+    if ((e = hipEventRecord(s->staged, s->stream)) != hipSuccess) return hip_fail(e, "event");
+    s->staged_pending = true;
+
+    if (ctx->use_graphs) {
+        if (!s->exec || s->grid != ctx->batch_grid) {
+            s->grid = ctx->batch_grid;
+            vr_status st = capture(s);
+            if (st != VR_OK) return st;
+        }
+        if ((e = hipGraphLaunch(s->exec, s->stream)) != hipSuccess)
+            return hip_fail(e, "hipGraphLaunch");
+    } else {
+        if ((e = launch_batch(s->d_work, s->d_counter, ctx->batch_grid, s->stream)) != hipSuccess)
+            return hip_fail(e, "batch launch");
+    }
+    return VR_OK;
+}
+
+}  // namespace vr
+
+using namespace vr;
+
+extern "C" vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
+                                     void* hip_stream) {
+    if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    if (n < 0) return fail(VR_ERR_INVALID_ARG, "n < 0");
+    if (n > 0 && !reqs) return fail(VR_ERR_INVALID_ARG, "requests are NULL");
+    for (int q = 0; q < n; ++q) {
+        vr_status st = check_request(ctx, &reqs[q]);
+        if (st != VR_OK) {
+            std::string m = vr_last_error();
+            return fail(st, "request %d: %s", q, m.c_str());
+        }
+    }
+    if (ctx->device < 0) return fail(VR_ERR_UNSUPPORTED, "validation-only context");
+    if (n == 0) return ok();
+    std::vector<ReqParams> P((size_t)n);
+    for (int q = 0; q < n; ++q) {
+        std::lock_guard<std::mutex> lk(reqs[q].vol->tf_mu);
+        make_params(reqs[q], reqs[q].vol->tf, &P[q]);
+    }
+    vr_status st;
+    BatchSlot* s = batch_slot_for(ctx, (hipStream_t)hip_stream, &st);
+    if (!s) return st;
+    st = batch_enqueue(ctx, s, P.data(), n);
+    if (st != VR_OK) return st;
+    return ok();
+}

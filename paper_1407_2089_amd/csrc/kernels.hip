@@ -1,0 +1,242 @@
+// HIP kernels for gfx950: frame relayout into bricks, the plain per-request
+// render launch, the persistent batched render launch, and the sampling test
+// hook.  Host-side launchers at the bottom are the only entry points the
+// library's C++ code calls.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+#include "march.h"
+
+namespace vr {
+
+// ------------------------------------------------------------- relayout
+// One thread per stored word of the frame: gathers the word's channels from
+// the linear [C][Z][Y][X] source (zero outside the grid), clamps them to the
+// declared bit depth and packs them side by side.
+template <int C, bool U16>
+__global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* __restrict__ src,
+                                                        uint8_t* __restrict__ dst, uint32_t maxval,
+                                                        uint64_t total_words) {
+    using T = typename WordT<C, U16>::T;
+    using S = typename std::conditional<U16, uint16_t, uint8_t>::type;
+    const S* in = reinterpret_cast<const S*>(src);
+    T* out = reinterpret_cast<T*>(dst);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t bx_mask = (1u << g.shift[0]) - 1u;
+    (void)bx_mask;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total_words; w += stride) {
+        const uint32_t brick = (uint32_t)(w / (uint32_t)g.brick);
+        const uint32_t rem = (uint32_t)(w - (uint64_t)brick * (uint32_t)g.brick);
+        const uint32_t lz = rem / (uint32_t)g.plane;
+        const uint32_t r2 = rem - lz * (uint32_t)g.plane;
+        const uint32_t ly = r2 / (uint32_t)g.row;
+        const uint32_t lx = r2 - ly * (uint32_t)g.row;
+        const uint32_t bx = brick % (uint32_t)g.nb[0];
+        const uint32_t byz = brick / (uint32_t)g.nb[0];
+        const uint32_t by = byz % (uint32_t)g.nb[1];
+        const uint32_t bz = byz / (uint32_t)g.nb[1];
+        // voxel index = stored coordinate - 1
+        const int i = (int)((bx << g.shift[0]) + lx) - 1;
+        const int j = (int)((by << g.shift[1]) + ly) - 1;
+        const int k = (int)((bz << g.shift[2]) + lz) - 1;
+        uint32_t ch[4] = {0u, 0u, 0u, 0u};
+        if (i >= 0 && j >= 0 && k >= 0 && i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+            const size_t plane = (size_t)g.n[0] * g.n[1];
+            const size_t vol = plane * g.n[2];
+            const size_t base = (size_t)k * plane + (size_t)j * g.n[0] + i;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                uint32_t v = in[(size_t)c * vol + base];
+                ch[c] = v > maxval ? maxval : v;
+            }
+        }
+        T word;
+        if constexpr (!U16) {
+            if constexpr (C == 1) word = (T)ch[0];
+            else if constexpr (C == 2) word = (T)(ch[0] | (ch[1] << 8));
+            else word = (T)(ch[0] | (ch[1] << 8) | (ch[2] << 16) | (ch[3] << 24));
+        } else {
+            if constexpr (C == 1) word = (T)ch[0];
+            else if constexpr (C == 2) word = (T)(ch[0] | (ch[1] << 16));
+            else word = make_uint2(ch[0] | (ch[1] << 16), ch[2] | (ch[3] << 16));
+        }
+        out[w] = word;
+    }
+}
+
+// ------------------------------------------------------------ plain render
+// Grid: one block per (eye, tile); block = 4 waves, each wave a wave_w x
+// wave_h pixel tile.
+template <int V>
+__global__ __launch_bounds__(kBlockThreads) void render_kernel(ReqParams P, TileShape ts,
+                                                               int tiles_x, int tiles_y) {
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int per_eye = tiles_x * tiles_y;
+    const int eye = b / per_eye;
+    const int t = b - eye * per_eye;
+    const int ty = t / tiles_x;
+    const int tx = t - ty * tiles_x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wxi = wave % ts.waves_x, wyi = wave / ts.waves_x;
+    const int px = tx * ts.wave_w * ts.waves_x + wxi * ts.wave_w + lane % ts.wave_w;
+    const int py = ty * ts.wave_h * ts.waves_y + wyi * ts.wave_h + lane / ts.wave_w;
+    const bool valid = px < P.width && py < P.height;
+    render_pixel<V>(P, eye, valid ? px : 0, valid ? py : 0, valid);
+}
+
+// ------------------------------------------------------- persistent batch
+// Work items are (request, eye, tile) triples numbered request by request in
+// the order the host laid the requests out (most expensive first); prefix[q]
+// is the first item of request q.  Blocks pull items from a global counter until none are left:
+// every block reaches the exit once the counter passes n_items.
+__device__ __forceinline__ int find_req(const int32_t* __restrict__ prefix, int n, int item) {
+    int lo = 0, hi = n - 1;  // largest q with prefix[q] <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int V>
+__device__ __forceinline__ void batch_tile(const ReqParams& P, const TileShape& ts, int local) {
+    const int tiles_x = (P.width + ts.wave_w * ts.waves_x - 1) / (ts.wave_w * ts.waves_x);
+    const int tiles_y = (P.height + ts.wave_h * ts.waves_y - 1) / (ts.wave_h * ts.waves_y);
+    const int per_eye = tiles_x * tiles_y;
+    const int eye = local / per_eye;
+    const int t = local - eye * per_eye;
+    const int ty = t / tiles_x;
+    const int tx = t - ty * tiles_x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wxi = wave % ts.waves_x, wyi = wave / ts.waves_x;
+    const int px = tx * ts.wave_w * ts.waves_x + wxi * ts.wave_w + lane % ts.wave_w;
+    const int py = ty * ts.wave_h * ts.waves_y + wyi * ts.wave_h + lane / ts.wave_w;
+    const bool valid = px < P.width && py < P.height;
+    render_pixel<V>(P, eye, valid ? px : 0, valid ? py : 0, valid);
+}
+
+__global__ __launch_bounds__(kBlockThreads) void batch_kernel(const BatchWork* __restrict__ work) {
+    __shared__ int s_item;
+    const int n_req = work->n_req;
+    const int n_items = work->n_items;
+    const TileShape ts = work->tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(work->counter, 1);
+        __syncthreads();
+        const int item = s_item;
+        __syncthreads();
+        if (item >= n_items) break;
+        const int q = find_req(work->prefix, n_req, item);
+        const int local = item - work->prefix[q];
+        const ReqParams& P = work->reqs[q];
+        switch (P.variant) {
+#define VR_CASE(v) case v: batch_tile<v>(P, ts, local); break;
+            VR_CASE(0) VR_CASE(1) VR_CASE(2) VR_CASE(3) VR_CASE(4) VR_CASE(5) VR_CASE(6)
+            VR_CASE(7) VR_CASE(8) VR_CASE(9) VR_CASE(10) VR_CASE(11) VR_CASE(12)
+            VR_CASE(13) VR_CASE(14) VR_CASE(15)
+#undef VR_CASE
+            default: break;
+        }
+    }
+}
+
+__global__ void reset_counter_kernel(int* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+// ------------------------------------------------------------ test hook
+template <int V>
+__global__ __launch_bounds__(256) void debug_sample_kernel(ReqParams P, const float* __restrict__ pts,
+                                                           int n, float* __restrict__ out) {
+    constexpr int C = Variant<V>::C;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x[C];
+    sample<C, Variant<V>::U16, Variant<V>::F16>(P.vox, P.g, pts[3 * i], pts[3 * i + 1],
+                                                pts[3 * i + 2], x);
+#pragma unroll
+    for (int c = 0; c < C; ++c) out[(size_t)i * C + c] = x[c];
+}
+
+// ------------------------------------------------------------- launchers
+
+hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
+                           const void* src, uint8_t* dst, hipStream_t s) {
+    const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
+    const uint32_t maxval = (1u << bits) - 1u;
+    uint64_t blocks64 = (words + 255) / 256;
+    const unsigned blocks = (unsigned)(blocks64 > 65536 ? 65536 : blocks64);
+    if (words == 0) return hipSuccess;
+#define VR_RL(C, U)                                                                      \
+    if (channels == C && u16 == U) {                                                     \
+        hipLaunchKernelGGL((relayout_kernel<C, U>), dim3(blocks), dim3(256), 0, s, g, src, \
+                           dst, maxval, words);                                          \
+        return hipGetLastError();                                                        \
+    }
+    VR_RL(1, false) VR_RL(2, false) VR_RL(3, false) VR_RL(4, false)
+    VR_RL(1, true) VR_RL(2, true) VR_RL(3, true) VR_RL(4, true)
+#undef VR_RL
+    return hipErrorInvalidValue;
+}
+
+typedef void (*render_fn)(ReqParams, TileShape, int, int);
+static const render_fn kRender[kVariants] = {
+    render_kernel<0>, render_kernel<1>, render_kernel<2>, render_kernel<3>,
+    render_kernel<4>, render_kernel<5>, render_kernel<6>, render_kernel<7>,
+    render_kernel<8>, render_kernel<9>, render_kernel<10>, render_kernel<11>,
+    render_kernel<12>, render_kernel<13>, render_kernel<14>, render_kernel<15>};
+
+hipError_t launch_render(const ReqParams& P, const TileShape& ts, hipStream_t s) {
+    if (P.variant < 0 || P.variant >= kVariants) return hipErrorInvalidValue;
+    if (ts.wave_w * ts.wave_h != kWave || ts.waves_x * ts.waves_y * kWave != kBlockThreads)
+        return hipErrorInvalidValue;
+    const int bw = ts.wave_w * ts.waves_x, bh = ts.wave_h * ts.waves_y;
+    const int tiles_x = (P.width + bw - 1) / bw, tiles_y = (P.height + bh - 1) / bh;
+    const long long blocks = (long long)tiles_x * tiles_y * P.eyes;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(kRender[P.variant], dim3((unsigned)blocks), dim3(kBlockThreads), 0, s, P,
+                       ts, tiles_x, tiles_y);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch(const BatchWork* dev_work, int* dev_counter, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, dev_counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kBlockThreads), 0, s, dev_work);
+    return hipGetLastError();
+}
+
+typedef void (*debug_fn)(ReqParams, const float*, int, float*);
+static const debug_fn kDebug[kVariants] = {
+    debug_sample_kernel<0>, debug_sample_kernel<1>, debug_sample_kernel<2>,
+    debug_sample_kernel<3>, debug_sample_kernel<4>, debug_sample_kernel<5>,
+    debug_sample_kernel<6>, debug_sample_kernel<7>, debug_sample_kernel<8>,
+    debug_sample_kernel<9>, debug_sample_kernel<10>, debug_sample_kernel<11>,
+    debug_sample_kernel<12>, debug_sample_kernel<13>, debug_sample_kernel<14>,
+    debug_sample_kernel<15>};
+
+hipError_t launch_debug_sample(const ReqParams& P, const float* pts, int n, float* out,
+                               hipStream_t s) {
+    if (P.variant < 0 || P.variant >= kVariants) return hipErrorInvalidValue;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kDebug[P.variant], dim3((n + 255) / 256), dim3(256), 0, s, P, pts, n,
+                       out);
+    return hipGetLastError();
+}
+
+int batch_grid_blocks(int device) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel, kBlockThreads, 0) !=
+            hipSuccess ||
+        per_cu <= 0)
+        per_cu = 1;
+    return cus * per_cu;
+}
+
+}  // namespace vr

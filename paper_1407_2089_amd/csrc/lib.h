@@ -1,0 +1,100 @@
+// Internal host-side state of libvr (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdarg>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/vr.h"
+#include "kernels.h"
+#include "params.h"
+
+namespace vr {
+
+class Server;
+
+// Workspace of batched launches on one stream: device tables that a captured
+// graph reads, their pinned host staging copies, and the instantiated graph.
+struct BatchSlot {
+    hipStream_t stream = nullptr;   // the caller's stream this slot serves
+    hipStream_t capture = nullptr;  // private stream used only for capture
+    int capacity = 0;               // requests the tables can hold
+    ReqParams* d_reqs = nullptr;
+    int32_t* d_prefix = nullptr;
+    int32_t* d_counter = nullptr;
+    BatchWork* d_work = nullptr;
+    ReqParams* h_reqs = nullptr;    // pinned
+    int32_t* h_prefix = nullptr;    // pinned
+    BatchWork* h_work = nullptr;    // pinned
+    hipEvent_t staged = nullptr;    // staging copies of the last batch done
+    bool staged_pending = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int grid = 0;
+    TileShape tile{};
+};
+
+// Sets the calling thread's error message and returns `st`.
+vr_status fail(vr_status st, const char* fmt, ...);
+vr_status ok();
+vr_status hip_fail(hipError_t e, const char* what);
+
+}  // namespace vr
+
+struct vr_volume {
+    vr_ctx* ctx = nullptr;
+    vr_volume_desc desc{};
+    vr::BrickGeom geom{};
+    uint8_t* storage = nullptr;
+    uint64_t bytes = 0;
+    std::mutex tf_mu;
+    vr_transfer tf[vr::kMaxChannels]{};
+    std::atomic<int> in_flight{0};  // served tickets that read this volume
+};
+
+struct vr_ctx {
+    int device = -1;           // -1: validation-only context
+    uint64_t budget = 0;
+    std::atomic<uint64_t> used{0};
+    std::atomic<int> volumes{0};
+    int batch_grid = 0;        // persistent blocks for a batched launch
+    std::mutex mu;
+    // Batched-launch workspaces keyed by stream (batch.cpp).
+    std::map<hipStream_t, vr::BatchSlot*> batch_slots;
+    vr::TileShape batch_tile{8, 8, 2, 2};
+    bool use_graphs = true;
+    vr::Server* server = nullptr;   // created by the first vr_submit (server.cpp)
+    std::mutex server_mu;
+};
+
+namespace vr {
+
+// Validation helpers (api.cpp).
+vr_status check_desc(const vr_volume_desc* d);
+vr_status check_request(const vr_ctx* ctx, const vr_render_req* r);
+BrickGeom make_geom(const vr_volume_desc& d);
+// Fills the device parameters of a request from the volume's current transfer
+// functions (or from `tf` when given).
+void make_params(const vr_render_req& r, const vr_transfer* tf, ReqParams* P);
+TileShape default_tile();
+
+// Batched path (batch.cpp).
+vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* slot, const ReqParams* params, int n);
+BatchSlot* batch_slot_for(vr_ctx* ctx, hipStream_t stream, vr_status* st);
+BatchSlot* batch_slot_create(vr_ctx* ctx, hipStream_t stream, vr_status* st);
+void batch_slot_destroy(BatchSlot* slot);
+// Estimated relative cost of a request (for ordering work).
+double request_cost(const ReqParams& P);
+
+// Serving (server.cpp).
+vr_status server_submit(vr_ctx* ctx, const vr_render_req* req, uint64_t* ticket);
+vr_status server_poll(vr_ctx* ctx, uint64_t ticket, vr_ticket_info* info);
+vr_status server_release(vr_ctx* ctx, uint64_t ticket);
+vr_status server_stop(vr_ctx* ctx);
+
+}  // namespace vr

@@ -1,0 +1,283 @@
+// Device-side ray marcher: ray set-up, box clip, trilinear sampling from the
+// brick-major layout, per-channel transfer functions, front-to-back
+// compositing with early termination.  One lane owns one pixel of one eye.
+//
+// Every kernel that renders (the plain per-request launch and the persistent
+// batched launch) calls render_pixel<V>() below, so a pixel's arithmetic is
+// the same instruction sequence whichever way it was scheduled.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "params.h"
+
+namespace vr {
+
+constexpr int kMaxSamples = 1 << 22;  // hard cap on samples per ray
+
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+template <int C, bool U16> struct WordT;
+template <> struct WordT<1, false> { using T = uint8_t; };
+template <> struct WordT<2, false> { using T = uint16_t; };
+template <> struct WordT<3, false> { using T = uint32_t; };
+template <> struct WordT<4, false> { using T = uint32_t; };
+template <> struct WordT<1, true> { using T = uint16_t; };
+template <> struct WordT<2, true> { using T = uint32_t; };
+template <> struct WordT<3, true> { using T = uint2; };
+template <> struct WordT<4, true> { using T = uint2; };
+
+// Raw channel values of one stored word, as float.
+template <int C, bool U16, typename T>
+__device__ __forceinline__ void unpack_f32(T w, float (&x)[C]) {
+    if constexpr (!U16) {
+        if constexpr (C == 1) {
+            x[0] = (float)(uint32_t)w;
+        } else {
+            uint32_t u = (uint32_t)w;
+#pragma unroll
+            for (int c = 0; c < C; ++c) x[c] = (float)((u >> (8 * c)) & 0xffu);
+        }
+    } else {
+        if constexpr (C == 1) {
+            x[0] = (float)(uint32_t)w;
+        } else if constexpr (C == 2) {
+            uint32_t u = (uint32_t)w;
+            x[0] = (float)(u & 0xffffu);
+            x[1] = (float)(u >> 16);
+        } else {
+            x[0] = (float)(w.x & 0xffffu);
+            x[1] = (float)(w.x >> 16);
+            x[2] = (float)(w.y & 0xffffu);
+            if constexpr (C == 4) x[3] = (float)(w.y >> 16);
+        }
+    }
+}
+
+// Raw channel values of one stored word as FP16 pairs (channel 2q, 2q + 1).
+template <int C, bool U16, typename T>
+__device__ __forceinline__ void unpack_f16(T w, half2_t (&h)[(C + 1) / 2]) {
+    float x[C];
+    unpack_f32<C, U16>(w, x);
+#pragma unroll
+    for (int q = 0; q < (C + 1) / 2; ++q) {
+        h[q].x = (_Float16)x[2 * q];
+        h[q].y = (2 * q + 1 < C) ? (_Float16)x[2 * q + 1] : (_Float16)0.0f;
+    }
+}
+
+// Locate the 2x2x2 words around index-space point p.  Returns the word index
+// of the lowest corner within the frame and the fractional offsets.  Clamping
+// keeps every tap inside the stored grid for any input (points outside the
+// box [-1, n] read the zero padding, where the field is zero anyway).
+__device__ __forceinline__ uint32_t corner_index(const BrickGeom& g, float px, float py,
+                                                 float pz, float& fx, float& fy, float& fz) {
+    float p[3] = {px, py, pz};
+    float f[3];
+    int s[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float fl = floorf(p[a]);
+        float fr = p[a] - fl;
+        int si = (int)fl + 1;  // stored coordinate of the low tap
+        fr = si < 0 ? 0.0f : fr;
+        si = si < 0 ? 0 : si;
+        fr = si > g.n[a] ? 1.0f : fr;
+        si = si > g.n[a] ? g.n[a] : si;
+        f[a] = fr;
+        s[a] = si;
+    }
+    fx = f[0];
+    fy = f[1];
+    fz = f[2];
+    uint32_t bx = (uint32_t)s[0] >> g.shift[0], lx = (uint32_t)s[0] & ((1u << g.shift[0]) - 1u);
+    uint32_t by = (uint32_t)s[1] >> g.shift[1], ly = (uint32_t)s[1] & ((1u << g.shift[1]) - 1u);
+    uint32_t bz = (uint32_t)s[2] >> g.shift[2], lz = (uint32_t)s[2] & ((1u << g.shift[2]) - 1u);
+    uint32_t brick = (bz * (uint32_t)g.nb[1] + by) * (uint32_t)g.nb[0] + bx;
+    return brick * (uint32_t)g.brick + lz * (uint32_t)g.plane + ly * (uint32_t)g.row + lx;
+}
+
+__device__ __forceinline__ float lerp(float a, float b, float f) { return fmaf(f, b - a, a); }
+__device__ __forceinline__ half2_t lerp(half2_t a, half2_t b, half2_t f) {
+    return f * (b - a) + a;
+}
+
+// Trilinear field (raw units) of every channel at index-space point p.
+template <int C, bool U16, bool F16>
+__device__ __forceinline__ void sample(const uint8_t* __restrict__ vox, const BrickGeom& g,
+                                       float px, float py, float pz, float (&x)[C]) {
+    using T = typename WordT<C, U16>::T;
+    float fx, fy, fz;
+    uint32_t idx = corner_index(g, px, py, pz, fx, fy, fz);
+    const T* b = reinterpret_cast<const T*>(vox) + idx;
+    const uint32_t r = (uint32_t)g.row, pl = (uint32_t)g.plane;
+    T w000 = b[0], w100 = b[1], w010 = b[r], w110 = b[r + 1];
+    T w001 = b[pl], w101 = b[pl + 1], w011 = b[pl + r], w111 = b[pl + r + 1];
+    if constexpr (!F16) {
+        float a000[C], a100[C], a010[C], a110[C], a001[C], a101[C], a011[C], a111[C];
+        unpack_f32<C, U16>(w000, a000);
+        unpack_f32<C, U16>(w100, a100);
+        unpack_f32<C, U16>(w010, a010);
+        unpack_f32<C, U16>(w110, a110);
+        unpack_f32<C, U16>(w001, a001);
+        unpack_f32<C, U16>(w101, a101);
+        unpack_f32<C, U16>(w011, a011);
+        unpack_f32<C, U16>(w111, a111);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            float c00 = lerp(a000[c], a100[c], fx);
+            float c10 = lerp(a010[c], a110[c], fx);
+            float c01 = lerp(a001[c], a101[c], fx);
+            float c11 = lerp(a011[c], a111[c], fx);
+            float c0 = lerp(c00, c10, fy);
+            float c1 = lerp(c01, c11, fy);
+            x[c] = lerp(c0, c1, fz);
+        }
+    } else {
+        constexpr int NP = (C + 1) / 2;
+        half2_t a000[NP], a100[NP], a010[NP], a110[NP], a001[NP], a101[NP], a011[NP], a111[NP];
+        unpack_f16<C, U16>(w000, a000);
+        unpack_f16<C, U16>(w100, a100);
+        unpack_f16<C, U16>(w010, a010);
+        unpack_f16<C, U16>(w110, a110);
+        unpack_f16<C, U16>(w001, a001);
+        unpack_f16<C, U16>(w101, a101);
+        unpack_f16<C, U16>(w011, a011);
+        unpack_f16<C, U16>(w111, a111);
+        half2_t hx = {(_Float16)fx, (_Float16)fx};
+        half2_t hy = {(_Float16)fy, (_Float16)fy};
+        half2_t hz = {(_Float16)fz, (_Float16)fz};
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+            half2_t c00 = lerp(a000[q], a100[q], hx);
+            half2_t c10 = lerp(a010[q], a110[q], hx);
+            half2_t c01 = lerp(a001[q], a101[q], hx);
+            half2_t c11 = lerp(a011[q], a111[q], hx);
+            half2_t c0 = lerp(c00, c10, hy);
+            half2_t c1 = lerp(c01, c11, hy);
+            half2_t v = lerp(c0, c1, hz);
+            x[2 * q] = (float)v.x;
+            if (2 * q + 1 < C) x[2 * q + 1] = (float)v.y;
+        }
+    }
+}
+
+template <int V> struct Variant {
+    static constexpr int C = (V & 3) + 1;
+    static constexpr bool U16 = (V & 4) != 0;
+    static constexpr bool F16 = (V & 8) != 0;
+};
+
+// One pixel of one eye: returns nothing, writes RGBA (and the sample count).
+// `valid` false lanes take part in the wave's loop structure but do no work.
+template <int V>
+__device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px, int py,
+                                             bool valid) {
+    constexpr int C = Variant<V>::C;
+    constexpr bool U16 = Variant<V>::U16;
+    constexpr bool F16 = Variant<V>::F16;
+
+    const float sx = fmaf((float)px + 0.5f, P.sx_scale, -1.0f);
+    const float sy = fmaf(-((float)py + 0.5f), P.sy_scale, 1.0f);
+
+    float p0[3], d[3];
+    float w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float o = eye ? P.o0[1][a] : P.o0[0][a];
+        const float bse = eye ? P.base[1][a] : P.base[0][a];
+        p0[a] = fmaf(sy, P.ov[a], fmaf(sx, P.ou[a], o));
+        w[a] = fmaf(sy, P.dv[a], fmaf(sx, P.du[a], bse));
+    }
+    const float inv_len = rsqrtf(fmaf(w[0], w[0], fmaf(w[1], w[1], w[2] * w[2])));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = w[a] * inv_len * P.inv_sp[a];
+
+    // Slab clip against the extended box [-1, n] per axis.
+    float t_in = P.tmin, t_out = INFINITY;
+    bool hit = valid;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float hi = (float)P.g.n[a];
+        if (d[a] != 0.0f) {
+            const float inv = 1.0f / d[a];
+            const float t1 = (-1.0f - p0[a]) * inv;
+            const float t2 = (hi - p0[a]) * inv;
+            t_in = fmaxf(t_in, fminf(t1, t2));
+            t_out = fminf(t_out, fmaxf(t1, t2));
+        } else {
+            hit = hit && (p0[a] >= -1.0f) && (p0[a] <= hi);
+        }
+    }
+    int n = 0;
+    if (hit && t_in < t_out) {
+        const float span = (t_out - t_in) / P.step - 0.5f;
+        const float c = ceilf(span);
+        n = c <= 0.0f ? 0 : (c >= (float)kMaxSamples ? kMaxSamples : (int)c);
+    }
+
+    float pe[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pe[a] = fmaf(n > 0 ? t_in : 0.0f, d[a], p0[a]);
+
+    // Transfer-function coefficients (wave-uniform).
+    ChanTF tf[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) tf[c] = P.tf[c];
+
+    const float half_step = 0.5f * P.step;
+    const float tau = P.tau;
+    float Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, A = 0.0f;
+    int k = 0;
+    bool live = n > 0;
+    // The wave leaves the loop once no lane is live; lanes that are done are
+    // masked off and accumulate nothing more.
+    while (__ballot(live)) {
+        if (live) {
+            const float s = fmaf((float)k, P.step, half_step);
+            float x[C];
+            sample<C, U16, F16>(P.vox, P.g, fmaf(s, d[0], pe[0]), fmaf(s, d[1], pe[1]),
+                                fmaf(s, d[2], pe[2]), x);
+            float amax = 0.0f, r = 0.0f, gg = 0.0f, bb = 0.0f;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float u = __saturatef(fmaf(x[c], tf[c].scale, tf[c].bias));
+                const float g = u * fmaf(tf[c].curve, u, tf[c].one_m_curve);
+                amax = fmaxf(amax, tf[c].alpha_mul * g);
+                r = fmaf(g, tf[c].rgb[0], r);
+                gg = fmaf(g, tf[c].rgb[1], gg);
+                bb = fmaf(g, tf[c].rgb[2], bb);
+            }
+            const float a_s = fminf(amax, 1.0f);
+            const float wgt = (1.0f - A) * a_s;
+            Cr = fmaf(wgt, fminf(r, 1.0f), Cr);
+            Cg = fmaf(wgt, fminf(gg, 1.0f), Cg);
+            Cb = fmaf(wgt, fminf(bb, 1.0f), Cb);
+            A = A + wgt;
+            ++k;
+            live = (k < n) && (A < tau);
+        }
+    }
+
+    if (valid) {
+        const float T = 1.0f - A;
+        float4 o;
+        o.x = fmaf(T, P.bg[0], Cr);
+        o.y = fmaf(T, P.bg[1], Cg);
+        o.z = fmaf(T, P.bg[2], Cb);
+        o.w = fmaf(T, P.bg[3], A);
+        const size_t pix = ((size_t)eye * P.height + py) * P.width + px;
+        reinterpret_cast<float4*>(P.out)[pix] = o;
+        if (P.samples) P.samples[pix] = k;
+    }
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
+// works on a contiguous run of tiles (neighbouring tiles share voxels in that
+// XCD's L2).  The tail beyond a multiple of 8 keeps its order.
+__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+    const int n8 = nblocks & ~7;
+    if (b >= n8) return b;
+    return (b & 7) * (n8 >> 3) + (b >> 3);
+}
+
+}  // namespace vr

@@ -1,0 +1,86 @@
+// Plain-old-data records shared by the host library and the HIP kernels.
+//
+// A ReqParams holds everything one render request needs on the device: the
+// frame's brick-major voxel storage, the per-channel transfer-function
+// coefficients, the per-eye ray basis, the sampling parameters and the output
+// pointers.  The plain path passes it as a kernel argument; the batched path
+// keeps an array of them in device memory.
+#pragma once
+#include <stdint.h>
+
+namespace vr {
+
+constexpr int kMaxChannels = 4;
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kBlockThreads = 256;
+
+// Data variant of a request: channels (1..4), voxel width and sample precision.
+// Index = (channels - 1) + 4 * u16 + 8 * fp16.
+constexpr int kVariants = 16;
+inline constexpr int variant_index(int channels, bool u16, bool fp16) {
+    return (channels - 1) + (u16 ? 4 : 0) + (fp16 ? 8 : 0);
+}
+
+// Bytes of one stored voxel word: all channels of a voxel side by side, the
+// channel count rounded up to 1, 2 or 4.
+inline constexpr int word_bytes(int channels, bool u16) {
+    return (channels == 1 ? 1 : channels == 2 ? 2 : 4) * (u16 ? 2 : 1);
+}
+
+// Brick-major layout of one frame.  Stored coordinates s = i + 1 run over
+// [0, n + 1] per axis (voxel -1 and voxel n are zero padding).  A trilinear
+// sample at index-space p reads the 2x2x2 words starting at s0 = floor(p + 1)
+// in [0, n]; bricks tile those origins B at a time and store B + 1 words per
+// axis (one-word halo on the high side) so all eight taps sit in one brick.
+struct BrickGeom {
+    int32_t n[3];       // voxels per axis
+    int32_t shift[3];   // log2 of the brick edge per axis
+    int32_t nb[3];      // bricks per axis = ceil((n + 1) / B)
+    int32_t row;        // words per brick row   = Bx + 1
+    int32_t plane;      // words per brick plane = (Bx + 1)(By + 1)
+    int32_t brick;      // words per brick       = (Bx + 1)(By + 1)(Bz + 1)
+    int32_t word;       // bytes per word
+    int32_t pad_;
+    uint64_t frame_bytes; // bytes per frame, multiple of 256
+};
+
+// Transfer function of one channel, folded so that u = raw * scale + bias.
+struct ChanTF {
+    float scale, bias;   // 1 / ((2^bits - 1)(hi - lo)),  -lo / (hi - lo)
+    float one_m_curve;   // 1 - curve
+    float curve;
+    float alpha_mul;     // 0 for an invisible channel
+    float rgb[3];        // 0 for an invisible channel
+};
+
+struct ReqParams {
+    const uint8_t* vox;     // this frame's storage
+    BrickGeom g;
+    int32_t channels;
+    int32_t variant;
+    ChanTF tf[kMaxChannels];
+    // Rays.  Index-space origin p0 = o0[eye] + sx * ou + sy * ov; world
+    // direction w = base[eye] + sx * du + sy * dv, unit-normalised, then
+    // index-space direction d = w * inv_sp.
+    float o0[2][3];
+    float ou[3], ov[3];
+    float base[2][3];
+    float du[3], dv[3];
+    float inv_sp[3];
+    float tmin;             // 0 for perspective, -inf for orthographic
+    float step, tau;
+    float bg[4];            // bg_a * bg_rgb, bg_a
+    float sx_scale, sy_scale; // 2 / W, 2 / H
+    int32_t width, height, eyes;
+    int32_t pad_;
+    float* out;             // [eyes][H][W][4]
+    int32_t* samples;       // [eyes][H][W] or null
+};
+
+// Work decomposition: one item = one pixel tile of one eye of one request.
+struct TileShape {
+    int32_t wave_w, wave_h;   // pixels per wave (wave_w * wave_h = 64)
+    int32_t waves_x, waves_y; // waves per block
+};
+
+}  // namespace vr

@@ -1,0 +1,208 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/vr.h, sizes storage by the documented brick
+layout, and rejects invalid arguments with the documented status before
+touching a device (validation-only context, device = -1)."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+import paper_1407_2089_amd as vr
+from paper_1407_2089_amd.synth import Cam
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "vr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vr_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = vr.lib()
+    names = declared_symbols()
+    assert "vr_render" in names and "vr_submit" in names and len(names) == 14
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def desc(nx=64, ny=48, nz=20, ch=2, frames=3, dtype=vr.VR_U16, bits=12, brick=(0, 0, 0),
+         spacing=(1.0, 1.0, 1.0)):
+    return vr.vr_volume_desc(nx, ny, nz, ch, frames, dtype, bits, (C.c_float * 3)(*spacing),
+                             (C.c_float * 3)(0, 0, 0), (C.c_int32 * 3)(*brick))
+
+
+@pytest.mark.parametrize("dims,ch,dtype,brick", [
+    ((64, 48, 20), 2, vr.VR_U16, (16, 16, 16)),
+    ((1, 1, 1), 1, vr.VR_U8, (4, 4, 4)),
+    ((100, 37, 9), 3, vr.VR_U8, (8, 16, 4)),
+    ((512, 512, 64), 4, vr.VR_U16, (32, 32, 8)),
+])
+def test_storage_bytes_follow_brick_layout(dims, ch, dtype, brick):
+    d = desc(*dims, ch=ch, frames=3, dtype=dtype, bits=8 if dtype == vr.VR_U8 else 16,
+             brick=brick)
+    word = {1: 1, 2: 2, 3: 4, 4: 4}[ch] * (1 if dtype == vr.VR_U8 else 2)
+    nb = [math.ceil((n + 1) / b) for n, b in zip(dims, brick)]
+    per_brick = (brick[0] + 1) * (brick[1] + 1) * (brick[2] + 1)
+    frame = nb[0] * nb[1] * nb[2] * per_brick * word
+    frame = (frame + 255) // 256 * 256
+    assert vr.vr_volume_storage_bytes(d) == 3 * frame
+
+
+def test_default_brick_is_sixteen():
+    assert vr.vr_volume_storage_bytes(desc(brick=(0, 0, 0))) == \
+        vr.vr_volume_storage_bytes(desc(brick=(16, 16, 16)))
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("nz", 9000), ("channels", 0), ("channels", 5), ("frames", 0), ("dtype", 3),
+    ("bits", 7),
+])
+def test_invalid_descriptions(field, value):
+    d = desc()
+    setattr(d, field, value)
+    with pytest.raises(vr.VrError) as e:
+        vr.vr_volume_storage_bytes(d)
+    assert e.value.status == vr.VR_ERR_INVALID_ARG
+
+
+def test_invalid_spacing_bits_and_brick():
+    for d in (desc(spacing=(1, 0, 1)), desc(spacing=(1, float("nan"), 1)),
+              desc(dtype=vr.VR_U8, bits=12), desc(dtype=vr.VR_U16, bits=17),
+              desc(brick=(16, 12, 16)), desc(brick=(64, 64, 64))):
+        with pytest.raises(vr.VrError) as e:
+            vr.vr_volume_storage_bytes(d)
+        assert e.value.status == vr.VR_ERR_INVALID_ARG
+    big = desc(8192, 8192, 64, ch=1, frames=1, dtype=vr.VR_U8, bits=8)
+    with pytest.raises(vr.VrError, match="2\\^31"):
+        vr.vr_volume_storage_bytes(big)
+
+
+@pytest.fixture
+def vctx():
+    ctx = vr.vr_init(-1, 1 << 30)
+    yield ctx
+    vr.vr_shutdown(ctx)
+
+
+FAKE = 0x7f0000000000  # never dereferenced by a validation-only context
+
+
+def test_validation_context_budget(vctx):
+    d = desc(frames=1)
+    need = vr.vr_volume_storage_bytes(d)
+    with pytest.raises(vr.VrError) as e:
+        vr.vr_create_volume(vctx, d, FAKE, need - 1)
+    assert e.value.status == vr.VR_ERR_OUT_OF_MEMORY
+    with pytest.raises(vr.VrError) as e:
+        vr.vr_create_volume(vctx, d, FAKE + 16, need)
+    assert e.value.status == vr.VR_ERR_INVALID_ARG and "aligned" in str(e.value)
+    vols = []
+    n = (1 << 30) // need
+    for _ in range(n):
+        vols.append(vr.vr_create_volume(vctx, d, FAKE, need))
+    with pytest.raises(vr.VrError) as e:
+        vr.vr_create_volume(vctx, d, FAKE, need)
+    assert e.value.status == vr.VR_ERR_OUT_OF_MEMORY
+    with pytest.raises(vr.VrError) as e:
+        vr.vr_shutdown(vctx)
+    assert e.value.status == vr.VR_ERR_BUSY
+    for v in vols:
+        vr.vr_destroy_volume(v)
+
+
+def good_request(vol):
+    cam = Cam("perspective", (10, 20, 30), (0, 0, -1), (0, 1, 0), 0.8, 1.0, 1.0, 30.0)
+    return vr.make_request(vol, 0, cam, 64, 32, True, 1.0, 0.99, FAKE)
+
+
+@pytest.fixture
+def vvol(vctx):
+    d = desc(frames=2)
+    v = vr.vr_create_volume(vctx, d, FAKE, vr.vr_volume_storage_bytes(d))
+    yield vctx, v
+    vr.vr_destroy_volume(v)
+
+
+def expect(status, fn, *a):
+    with pytest.raises(vr.VrError) as e:
+        fn(*a)
+    assert e.value.status == status, str(e.value)
+    return str(e.value)
+
+
+def test_valid_request_reaches_the_device_check(vvol):
+    ctx, v = vvol
+    msg = expect(vr.VR_ERR_UNSUPPORTED, vr.vr_render, ctx, good_request(v))
+    assert "validation-only" in msg
+    expect(vr.VR_ERR_UNSUPPORTED, vr.vr_render_batch, ctx, [good_request(v)] * 3)
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda r: setattr(r, "frame", 2), lambda r: setattr(r, "frame", -1),
+    lambda r: setattr(r, "width", -1), lambda r: setattr(r, "height", 20000),
+    lambda r: setattr(r, "stereo", 2), lambda r: setattr(r, "step", 0.0),
+    lambda r: setattr(r, "step", float("inf")), lambda r: setattr(r, "term_alpha", 0.0),
+    lambda r: setattr(r, "term_alpha", 1.5), lambda r: r.background.__setitem__(3, 2.0),
+    lambda r: setattr(r, "precision", 7), lambda r: setattr(r, "out_rgba", None),
+    lambda r: setattr(r, "vol", None),
+    lambda r: setattr(r.cam, "projection", 5),
+    lambda r: setattr(r.cam, "projection", vr.VR_ORTHO),  # stereo needs perspective
+    lambda r: setattr(r.cam, "fov_y", 0.0), lambda r: setattr(r.cam, "fov_y", 3.2),
+    lambda r: setattr(r.cam, "convergence", 0.0),
+    lambda r: setattr(r.cam, "eye_separation", -1.0),
+    lambda r: r.cam.forward.__setitem__(2, 0.0),                   # forward = 0
+    lambda r: [r.cam.up.__setitem__(i, r.cam.forward[i]) for i in range(3)],  # parallel
+    lambda r: r.cam.center.__setitem__(0, float("nan")),
+])
+def test_invalid_requests_are_rejected_before_enqueue(vvol, mutate):
+    ctx, v = vvol
+    r = good_request(v)
+    mutate(r)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_render, ctx, r)
+    msg = expect(vr.VR_ERR_INVALID_ARG, vr.vr_render_batch, ctx, [good_request(v), r])
+    assert msg.split(": ", 1)[1].startswith("request 1")
+
+
+def test_ortho_mono_and_empty_image_are_valid(vvol):
+    ctx, v = vvol
+    r = good_request(v)
+    r.stereo = 0
+    r.cam.projection = vr.VR_ORTHO
+    r.cam.ortho_height = 10.0
+    expect(vr.VR_ERR_UNSUPPORTED, vr.vr_render, ctx, r)
+    r.width = 0
+    r.out_rgba = None  # nothing to write
+    expect(vr.VR_ERR_UNSUPPORTED, vr.vr_render, ctx, r)
+
+
+def test_transfer_validation(vvol):
+    ctx, v = vvol
+    vr.vr_set_transfer(v, 1, vr.make_transfer(0.1, 0.9, -1.0, 2.0, (0, 0.5, 1)))
+    for tf in (vr.make_transfer(0.5, 0.5), vr.make_transfer(-0.1, 0.5),
+               vr.make_transfer(0.0, 1.1), vr.make_transfer(curve=1.5),
+               vr.make_transfer(alpha_mul=2.5), vr.make_transfer(rgb=(0, 2, 0))):
+        expect(vr.VR_ERR_INVALID_ARG, vr.vr_set_transfer, v, 0, tf)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_set_transfer, v, 2, vr.make_transfer())
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_upload_frame, v, 5, FAKE)
+    expect(vr.VR_ERR_UNSUPPORTED, vr.vr_upload_frame, v, 1, FAKE)
+
+
+def test_null_arguments_do_not_crash():
+    L = vr.lib()
+    assert L.vr_init(0, 0, None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_shutdown(None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_volume_storage_bytes(None, None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_render(None, None, None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_render_batch(None, None, 0, None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_destroy_volume(None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_set_transfer(None, 0, None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_upload_frame(None, 0, None, None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_debug_sample(None, 0, None, 0, None, None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_submit(None, None, None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_poll(None, 0, None) == vr.VR_ERR_INVALID_ARG
+    assert L.vr_release(None, 0) == vr.VR_ERR_INVALID_ARG
+    assert vr.vr_last_error() != ""

@@ -81,11 +81,11 @@ def test_p2_two_channel_slab_merge_closed_form():
     # channel colours, capped at 1.
     v0, v1 = 200, 120
     vol = np.zeros((2, 20, 16, 16), np.uint8)
-    vol[0, 4:13] = v0
-    vol[1, 4:13] = v1
+    vol[0, 4:8] = v0
+    vol[1, 4:8] = v1
     lo0 = 0.5 * (v0 / 2 / 255 + v0 / 255)
     lo1 = 0.5 * (v0 / 2 / 255 + v1 / 255)  # above both channels' edge values
-    tfs = [TF(lo0, 1.0, 0.2, 0.6, (0.8, 0.7, 0.1)), TF(lo1, 0.6, -0.3, 0.9, (0.5, 0.2, 0.3))]
+    tfs = [TF(lo0, 0.7, 0.2, 0.6, (0.8, 0.7, 0.1)), TF(lo1, 0.5, -0.3, 1.2, (0.5, 0.2, 0.3))]
     sc = Scene("p2m", vol, 8, tfs, scenes.ortho_down_z(16, 16, 8, 8, 8.0), 8, 8, False,
                1.0, 1.0)
     g = []
@@ -96,7 +96,7 @@ def test_p2_two_channel_slab_merge_closed_form():
     assert abs(tfs[0].alpha_mul * g[0] - tfs[1].alpha_mul * g[1]) > 0.05
     rgb = [min(1.0, g[0] * tfs[0].rgb[q] + g[1] * tfs[1].rgb[q]) for q in range(3)]
     assert rgb[0] == 1.0 and rgb[1] < 1.0  # the cap is exercised on red only
-    A = 1 - (1 - a) ** 8
+    A = 1 - (1 - a) ** 3  # three interior samples: z = 4.5, 5.5, 6.5
     r = orc.render(sc)["rgba"].reshape(-1, 4)
     np.testing.assert_allclose(r, np.broadcast_to([c * A for c in rgb] + [A], r.shape),
                                rtol=0, atol=1e-12)
