@@ -66,6 +66,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", choices=["fp32", "fp16"], default="fp32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--mode", choices=["render", "copy"], default="render",
+                    help="copy: a plain 1 GiB device copy, to calibrate HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -78,6 +80,17 @@ def main():
 
     import paper_1407_2089_amd as vr
     from paper_1407_2089_amd import synth
+
+    if args.mode == "copy":
+        n = 1 << 30
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n,
+                          "copies": 5}), flush=True)
+        return
 
     log("generating workload")
     sc = synth.realistic_scene()

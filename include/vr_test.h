@@ -1,0 +1,35 @@
+/*
+ * vr_test.h — test hooks of libvr (not for production callers).
+ */
+#ifndef VR_TEST_H
+#define VR_TEST_H
+
+#include "vr.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Replace the context's serving backend with a CPU stand-in, so the serving
+ * loop (queueing, memory-based admission, slots, batching, completion,
+ * failures) can be tested without a GPU, also on a validation-only context.
+ * A batch occupies its slot for (sum of its requests' rays) x ns_per_ray
+ * nanoseconds; a batch holding a request of width fail_width completes as
+ * failed (VR_ERR_DEVICE on each of its tickets).  Up to max_batch requests
+ * per batch.  VR_ERR_BUSY if the current serving loop has tickets pending
+ * or running. */
+vr_status vr_test_fake_backend(vr_ctx* ctx, int32_t slots, double ns_per_ray,
+                               int32_t fail_width, int32_t max_batch);
+
+/* Fix the tile shape of batched launches (wave_w x wave_h pixels per wave,
+ * waves_x x waves_y waves per 256-thread block; wave_w * wave_h = 64 and
+ * waves_x * waves_y = 4), bypassing the autotuner; all zeros hands the
+ * choice back to the autotuner. */
+vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h, int32_t waves_x,
+                             int32_t waves_y);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VR_TEST_H */

@@ -99,6 +99,8 @@ def lib():
             "vr_poll": [P, C.c_uint64, C.POINTER(vr_ticket_info)],
             "vr_release": [P, C.c_uint64],
             "vr_debug_sample": [P, C.c_int32, P, C.c_int32, P, P],
+            "vr_test_fake_backend": [P, C.c_int32, C.c_double, C.c_int32, C.c_int32],
+            "vr_test_batch_tile": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -202,6 +204,15 @@ def vr_release(ctx, ticket: int):
 
 def vr_debug_sample(vol, frame: int, pts, n: int, out, stream=None):
     _check(lib().vr_debug_sample(vol, frame, _ptr(pts), n, _ptr(out), _stream(stream)))
+
+
+def vr_test_batch_tile(ctx, wave_w=0, wave_h=0, waves_x=0, waves_y=0):
+    _check(lib().vr_test_batch_tile(ctx, wave_w, wave_h, waves_x, waves_y))
+
+
+def vr_test_fake_backend(ctx, slots: int, ns_per_ray: float, fail_width: int = -1,
+                         max_batch: int = 32):
+    _check(lib().vr_test_fake_backend(ctx, slots, ns_per_ray, fail_width, max_batch))
 
 
 # ---------------------------------------------------------- record helpers

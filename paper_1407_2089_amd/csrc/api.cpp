@@ -60,6 +60,7 @@ BrickGeom make_geom(const vr_volume_desc& d) {
         g.n[a] = n[a];
         g.shift[a] = log2_exact(b[a]);
         g.nb[a] = (n[a] + 1 + b[a] - 1) / b[a];
+        g.clamp_hi[a] = std::nextafter((float)n[a], 0.0f);
     }
     g.row = b[0] + 1;
     g.plane = (b[0] + 1) * (b[1] + 1);
@@ -98,9 +99,10 @@ vr_status check_desc(const vr_volume_desc* d) {
                             d->brick[a]);
     const BrickGeom g = make_geom(*d);
     const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
-    if (words >= (1ull << 31))
-        return fail(VR_ERR_INVALID_ARG, "one frame needs %llu stored voxels (limit 2^31)",
-                    (unsigned long long)words);
+    if (words >= (1ull << 31) || g.frame_bytes >= (1ull << 32))
+        return fail(VR_ERR_INVALID_ARG,
+                    "one frame needs %llu stored voxels, %llu bytes (limits 2^31, 2^32)",
+                    (unsigned long long)words, (unsigned long long)g.frame_bytes);
     return VR_OK;
 }
 

@@ -9,6 +9,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <vector>
@@ -130,8 +132,116 @@ static vr_status capture(BatchSlot* s) {
     return VR_OK;
 }
 
-vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n) {
+// ----------------------------------------------------------------- tuning
+// Candidate tile shapes of a 256-thread block (pixels per wave x waves).
+// Per-ray arithmetic does not depend on the tiling, so every candidate gives
+// the same image bit for bit; only the speed differs.
+static const TileShape kCandidates[] = {
+    {8, 8, 2, 2}, {8, 8, 4, 1}, {8, 8, 1, 4}, {16, 4, 1, 4},
+    {16, 4, 2, 2}, {4, 16, 4, 1}, {32, 2, 1, 4}, {64, 1, 1, 4},
+};
+
+// Shape class: the set of data variants in the batch and the order of
+// magnitude of its ray count.
+static uint64_t shape_class(const ReqParams* params, int n) {
+    uint32_t variants = 0;
+    double rays = 0.0;
+    for (int q = 0; q < n; ++q) {
+        variants |= 1u << params[q].variant;
+        rays += (double)params[q].eyes * params[q].width * params[q].height;
+    }
+    const int mag = rays > 1.0 ? (int)std::floor(std::log2(rays)) : 0;
+    return ((uint64_t)variants << 8) | (uint64_t)mag;
+}
+
+static void load_tuning_cache(vr_ctx* ctx) {
+    const char* path = std::getenv("VR_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    unsigned long long key;
+    int a, b, c, d;
+    while (std::fscanf(f, "%llx %d %d %d %d", &key, &a, &b, &c, &d) == 5)
+        if (a * b == kWave && c * d * kWave == kBlockThreads) ctx->tuned[key] = TileShape{a, b, c, d};
+    std::fclose(f);
+}
+
+static void save_tuning(uint64_t key, const TileShape& t) {
+    const char* path = std::getenv("VR_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%llx %d %d %d %d\n", (unsigned long long)key, t.wave_w, t.wave_h, t.waves_x,
+                 t.waves_y);
+    std::fclose(f);
+}
+
+static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
+                              const TileShape& ts);
+
+// Times every candidate on this batch (synchronously, on the slot's stream)
+// and keeps the fastest for the batch's shape class.
+static vr_status tune(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n, uint64_t key,
+                      TileShape* best) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return fail(VR_ERR_DEVICE, "autotune event");
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return fail(VR_ERR_DEVICE, "autotune event");
+    }
+    float best_ms = 1e30f;
+    vr_status st = VR_OK;
+    for (const TileShape& c : kCandidates) {
+        float ms_total = 0.0f;
+        for (int rep = 0; rep < 2 && st == VR_OK; ++rep) {  // first run warms caches
+            (void)hipEventRecord(a, s->stream);
+            st = enqueue_with(ctx, s, params, n, c);
+            (void)hipEventRecord(b, s->stream);
+            if (st == VR_OK && hipEventSynchronize(b) != hipSuccess)
+                st = fail(VR_ERR_DEVICE, "autotune sync");
+            float ms = 0.0f;
+            if (st == VR_OK && rep == 1) {
+                (void)hipEventElapsedTime(&ms, a, b);
+                ms_total = ms;
+            }
+        }
+        if (st != VR_OK) break;
+        if (ms_total < best_ms) {
+            best_ms = ms_total;
+            *best = c;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st == VR_OK) {
+        ctx->tuned[key] = *best;
+        save_tuning(key, *best);
+    }
+    return st;
+}
+
+vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
+                        bool allow_tuning) {
     if (n <= 0) return VR_OK;
+    TileShape ts = ctx->batch_tile;
+    if (!ctx->forced_tile && ctx->autotune) {
+        const uint64_t key = shape_class(params, n);
+        std::unique_lock<std::mutex> lk(ctx->mu);
+        static std::once_flag once;
+        std::call_once(once, [&] { load_tuning_cache(ctx); });
+        auto it = ctx->tuned.find(key);
+        if (it != ctx->tuned.end()) {
+            ts = it->second;
+        } else if (allow_tuning) {
+            vr_status st = tune(ctx, s, params, n, key, &ts);
+            if (st != VR_OK) return st;
+        }
+    }
+    return enqueue_with(ctx, s, params, n, ts);
+}
+
+static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
+                              const TileShape& ts) {
     hipError_t e;
     // Most expensive first.
     std::vector<int> order(n);
@@ -152,7 +262,6 @@ vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int 
         if ((e = hipEventSynchronize(s->staged)) != hipSuccess) return hip_fail(e, "staging wait");
         s->staged_pending = false;
     }
-    const TileShape ts = ctx->batch_tile;
     const int bw = ts.wave_w * ts.waves_x, bh = ts.wave_h * ts.waves_y;
     int64_t items = 0;
     for (int q = 0; q < n; ++q) {
@@ -199,6 +308,21 @@ vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int 
 }  // namespace vr
 
 using namespace vr;
+
+extern "C" vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h,
+                                        int32_t waves_x, int32_t waves_y) {
+    if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    if (wave_w == 0 && wave_h == 0 && waves_x == 0 && waves_y == 0) {
+        ctx->forced_tile = false;
+        return ok();
+    }
+    if (wave_w <= 0 || wave_h <= 0 || waves_x <= 0 || waves_y <= 0 || wave_w * wave_h != kWave ||
+        waves_x * waves_y * kWave != kBlockThreads)
+        return fail(VR_ERR_INVALID_ARG, "a tile is 64 pixels per wave and 4 waves per block");
+    ctx->batch_tile = TileShape{wave_w, wave_h, waves_x, waves_y};
+    ctx->forced_tile = true;
+    return ok();
+}
 
 extern "C" vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
                                      void* hip_stream) {

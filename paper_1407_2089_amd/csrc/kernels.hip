@@ -152,7 +152,8 @@ __global__ __launch_bounds__(256) void debug_sample_kernel(ReqParams P, const fl
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float x[C];
-    sample<C, Variant<V>::U16, Variant<V>::F16>(P.vox, P.g, pts[3 * i], pts[3 * i + 1],
+    const Sampler S = make_sampler(P.vox, P.g);
+    sample<C, Variant<V>::U16, Variant<V>::F16>(P.g, S, pts[3 * i], pts[3 * i + 1],
                                                 pts[3 * i + 2], x);
 #pragma unroll
     for (int c = 0; c < C; ++c) out[(size_t)i * C + c] = x[c];

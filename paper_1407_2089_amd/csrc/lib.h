@@ -66,8 +66,12 @@ struct vr_ctx {
     std::mutex mu;
     // Batched-launch workspaces keyed by stream (batch.cpp).
     std::map<hipStream_t, vr::BatchSlot*> batch_slots;
-    vr::TileShape batch_tile{8, 8, 2, 2};
     bool use_graphs = true;
+    // Autotuner: chosen tile shape per shape class (batch.cpp).
+    bool autotune = true;
+    bool forced_tile = false;          // a test fixed the tile shape
+    vr::TileShape batch_tile{8, 8, 2, 2};
+    std::map<uint64_t, vr::TileShape> tuned;
     vr::Server* server = nullptr;   // created by the first vr_submit (server.cpp)
     std::mutex server_mu;
 };
@@ -84,7 +88,8 @@ void make_params(const vr_render_req& r, const vr_transfer* tf, ReqParams* P);
 TileShape default_tile();
 
 // Batched path (batch.cpp).
-vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* slot, const ReqParams* params, int n);
+vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* slot, const ReqParams* params, int n,
+                        bool allow_tuning = true);
 BatchSlot* batch_slot_for(vr_ctx* ctx, hipStream_t stream, vr_status* st);
 BatchSlot* batch_slot_create(vr_ctx* ctx, hipStream_t stream, vr_status* st);
 void batch_slot_destroy(BatchSlot* slot);

