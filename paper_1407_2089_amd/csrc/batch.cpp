@@ -227,8 +227,10 @@ vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int 
     if (!ctx->forced_tile && ctx->autotune) {
         const uint64_t key = shape_class(params, n);
         std::unique_lock<std::mutex> lk(ctx->mu);
-        static std::once_flag once;
-        std::call_once(once, [&] { load_tuning_cache(ctx); });
+        if (!ctx->tuning_cache_loaded) {
+            load_tuning_cache(ctx);
+            ctx->tuning_cache_loaded = true;
+        }
         auto it = ctx->tuned.find(key);
         if (it != ctx->tuned.end()) {
             ts = it->second;

@@ -70,6 +70,7 @@ struct vr_ctx {
     // Autotuner: chosen tile shape per shape class (batch.cpp).
     bool autotune = true;
     bool forced_tile = false;          // a test fixed the tile shape
+    bool tuning_cache_loaded = false;
     vr::TileShape batch_tile{8, 8, 2, 2};
     std::map<uint64_t, vr::TileShape> tuned;
     vr::Server* server = nullptr;   // created by the first vr_submit (server.cpp)

@@ -90,7 +90,10 @@ class HipBackend : public Backend {
     vr_status launch(int slot, const std::vector<Job*>& jobs) override {
         params_.resize(jobs.size());
         for (size_t q = 0; q < jobs.size(); ++q) params_[q] = jobs[q]->params;
-        vr_status st = batch_enqueue(ctx_, slots_[slot], params_.data(), (int)jobs.size());
+        // The loop never stops to tune: a shape class tuned by vr_render_batch
+        // (or loaded from the cache file) is used, else the default tile.
+        vr_status st = batch_enqueue(ctx_, slots_[slot], params_.data(), (int)jobs.size(),
+                                     /*allow_tuning=*/false);
         if (st != VR_OK) return st;
         hipError_t e = hipEventRecord(events_[slot], streams_[slot]);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
