@@ -68,6 +68,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--mode", choices=["render", "copy"], default="render",
                     help="copy: a plain 1 GiB device copy, to calibrate HBM byte counters")
+    ap.add_argument("--workload", choices=["realistic", "batch", "serve", "precision"],
+                    default="realistic",
+                    help="realistic (default): one stereo 1920x1080 frame per step; batch: 64 "
+                         "mixed requests, batched vs plain launches; serve: Poisson arrivals "
+                         "on resident datasets, p50/p99; precision: 48-frame series FP32/FP16")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-gb", type=float, default=150.0)
+    ap.add_argument("--serve-rates", default="25,50,100,200,400")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -90,6 +98,23 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read_per_copy": n, "bytes_written_per_copy": n,
                           "copies": 5}), flush=True)
+        return
+
+    if args.workload != "realistic":
+        from paper_1407_2089_amd import workloads
+        ctx = vr.Context(0)
+        if args.workload == "batch":
+            res = workloads.batching(ctx)
+        elif args.workload == "precision":
+            res = workloads.precision(ctx)
+        else:
+            rates = tuple(int(r) for r in args.serve_rates.split(","))
+            res = workloads.serving(ctx, total_gb=args.serve_gb, seconds=args.serve_seconds,
+                                    rates=rates)
+        ctx.close()
+        res["n_gpus"] = 1
+        res["data"] = "synthetic"
+        print(json.dumps(res), flush=True)
         return
 
     log("generating workload")

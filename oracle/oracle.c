@@ -67,7 +67,9 @@ typedef struct {
     int32_t* nominal;      /* [npix]     samples in the box, ignoring stopping   */
     double* count_margin;  /* [npix]     distance of the real-valued sample count
                                          to the nearest integer (1 if no hit)    */
-    double* band_lo;       /* [npix][4]  componentwise min over the band         */
+    double* band_lo;       /* [npix][4]  componentwise min over the band: results of
+                                         the stops k with |A_k - tau| <= eps and
+                                         of the stop right after each of them    */
     double* band_hi;       /* [npix][4]  componentwise max over the band         */
     int32_t* band_k;       /* [npix][2]  smallest and largest band member count,
                                          -1 when the band is empty               */
@@ -297,14 +299,18 @@ static void render_pixel(const job_t* jb, int64_t slot)
         double span = (t_exit - t_enter) / view->step - 0.5;
         margin = fabs(span - nearbyint(span));
         finish(view, C, A, out);
-        if (fabs(A - tau) <= eps) band_add(blo, bhi, bk, out, 0);
+        /* Band: stops k with |A_k - tau| <= eps, and the stop one sample
+         * after each of them (a ray whose opacity is that close to tau may
+         * decide A >= tau either way, and then stops at the next sample). */
+        int prev_in = fabs(A - tau) <= eps;
+        if (prev_in) band_add(blo, bhi, bk, out, 0);
 
         double field[4];
         for (int k = 0;; ++k) {
             double t = t_enter + (k + 0.5) * view->step;
             if (!(t < t_exit)) break;
             nominal = k + 1;
-            if (stopped && A > tau + eps) continue; /* only counting now */
+            if (stopped && A > tau + eps && !prev_in) continue; /* only counting now */
             double p[3];
             for (int a = 0; a < 3; ++a) p[a] = p0[a] + t * d[a];
             orc_sample(v, p, field);
@@ -313,7 +319,9 @@ static void render_pixel(const job_t* jb, int64_t slot)
             for (int q = 0; q < 3; ++q) C[q] += (1.0 - A) * a_s * rgb_s[q];
             A += (1.0 - A) * a_s;
             finish(view, C, A, out);
-            if (fabs(A - tau) <= eps) band_add(blo, bhi, bk, out, k + 1);
+            const int in = fabs(A - tau) <= eps;
+            if (in || prev_in) band_add(blo, bhi, bk, out, k + 1);
+            prev_in = in;
             if (!stopped) {
                 memcpy(rgba, out, sizeof out);
                 k_stop = k + 1;

@@ -60,7 +60,7 @@ BrickGeom make_geom(const vr_volume_desc& d) {
         g.n[a] = n[a];
         g.shift[a] = log2_exact(b[a]);
         g.nb[a] = (n[a] + 1 + b[a] - 1) / b[a];
-        g.clamp_hi[a] = std::nextafter((float)n[a], 0.0f);
+        g.clamp_hi[a] = std::nextafter((float)(n[a] + 1), 0.0f);
     }
     g.row = b[0] + 1;
     g.plane = (b[0] + 1) * (b[1] + 1);

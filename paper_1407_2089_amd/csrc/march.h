@@ -93,10 +93,17 @@ template <> __device__ __forceinline__ uint2 load_word<uint2>(__amdgpu_buffer_rs
     return make_uint2(w.x, w.y);
 }
 
+// floor(x) converted to int in one instruction (register-only).
+__device__ __forceinline__ int cvt_floor(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 // Per-frame constants of the sampler, kept in scalar registers.
 struct Sampler {
     __amdgpu_buffer_rsrc_t rsrc;
-    float hi[3];        // largest float below n per axis (clamp bound)
+    float hi[3];        // largest float below n + 1 per axis (clamp bound)
     uint32_t row_b;     // bytes per brick row
     uint32_t plane_b;   // bytes per brick plane
     uint32_t diag_b;    // row_b + plane_b
@@ -106,44 +113,62 @@ __device__ __forceinline__ Sampler make_sampler(const uint8_t* vox, const BrickG
     Sampler S;
     S.rsrc = frame_rsrc(vox, (uint32_t)g.frame_bytes);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) S.hi[a] = g.clamp_hi[a];
+    for (int a = 0; a < 3; ++a) S.hi[a] = g.clamp_hi[a];  // below n + 1
     S.row_b = (uint32_t)(g.row * g.word);
     S.plane_b = (uint32_t)(g.plane * g.word);
     S.diag_b = S.row_b + S.plane_b;
     return S;
 }
 
-// Locate the 2x2x2 words around index-space point p: returns the word index
-// of the lowest corner within the frame and the fractional offsets.  The
-// point is first clamped into [-1, n) per axis (it lies in the box [-1, n]
-// already, up to rounding); the stored coordinate of the low corner,
-// floor(p) + 1, then lies in [0, n], so every tap is inside the frame.
-__device__ __forceinline__ uint32_t corner_offset(const BrickGeom& g, const Sampler& S,
-                                                  float px, float py, float pz, float& fx,
-                                                  float& fy, float& fz) {
-    float p[3] = {px, py, pz};
+// The 2x2x2 taps around one sample point, in flight or landed.
+template <typename T> struct Taps {
+    T w000, w100, w010, w110, w001, w101, w011, w111;
+    float fx, fy, fz;
+};
+
+// Locate the taps around a point given in stored coordinates (index-space
+// position + 1) and issue their loads.  The point is clamped into [0, n + 1)
+// per axis (it lies in the box [0, n + 1] up to rounding; a point on the
+// upper face is evaluated at the largest float below n + 1, where the field
+// is within 1e-7 relative of its zero there).  The low corner floor(q) then
+// lies in [0, n], so every tap is inside the frame; floor and fraction come
+// from the same value, so they always agree.  Every factor and partial sum of
+// the word index is below 2^24 (a frame holds < 2^31 words and a brick >= 125
+// of them), so 24-bit multiply-adds are exact.
+template <typename T>
+__device__ __forceinline__ Taps<T> fetch(const BrickGeom& g, const Sampler& S, float qx,
+                                         float qy, float qz) {
+    Taps<T> t;
+    const float p[3] = {qx, qy, qz};
     float f[3];
     uint32_t s[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const float q = fminf(fmaxf(p[a], -1.0f), S.hi[a]);
-        const float fl = floorf(q);
-        f[a] = q - fl;
-        s[a] = (uint32_t)(int)(fl + 1.0f);
+        const float q = __builtin_amdgcn_fmed3f(p[a], 0.0f, S.hi[a]);
+        s[a] = (uint32_t)cvt_floor(q);
+        f[a] = __builtin_amdgcn_fractf(q);
     }
-    fx = f[0];
-    fy = f[1];
-    fz = f[2];
+    t.fx = f[0];
+    t.fy = f[1];
+    t.fz = f[2];
     const uint32_t bx = s[0] >> g.shift[0], lx = s[0] & ((1u << g.shift[0]) - 1u);
     const uint32_t by = s[1] >> g.shift[1], ly = s[1] & ((1u << g.shift[1]) - 1u);
     const uint32_t bz = s[2] >> g.shift[2], lz = s[2] & ((1u << g.shift[2]) - 1u);
-    // Every factor and partial sum is below 2^24 (a frame holds < 2^31 words
-    // and a brick >= 125 of them), so 24-bit multiply-adds are exact here.
     uint32_t brick = __umul24(bz, (uint32_t)g.nb[1]) + by;
     brick = __umul24(brick, (uint32_t)g.nb[0]) + bx;
     uint32_t local = __umul24(lz, (uint32_t)g.plane) + lx;
     local = __umul24(ly, (uint32_t)g.row) + local;
-    return __umul24(brick, (uint32_t)g.brick) + local;
+    constexpr uint32_t W = sizeof(T);
+    const uint32_t o = (__umul24(brick, (uint32_t)g.brick) + local) * W;
+    t.w000 = load_word<T>(S.rsrc, o, 0);
+    t.w100 = load_word<T>(S.rsrc, o + W, 0);
+    t.w010 = load_word<T>(S.rsrc, o, S.row_b);
+    t.w110 = load_word<T>(S.rsrc, o + W, S.row_b);
+    t.w001 = load_word<T>(S.rsrc, o, S.plane_b);
+    t.w101 = load_word<T>(S.rsrc, o + W, S.plane_b);
+    t.w011 = load_word<T>(S.rsrc, o, S.diag_b);
+    t.w111 = load_word<T>(S.rsrc, o + W, S.diag_b);
+    return t;
 }
 
 __device__ __forceinline__ float lerp(float a, float b, float f) { return fmaf(f, b - a, a); }
@@ -151,28 +176,20 @@ __device__ __forceinline__ half2_t lerp(half2_t a, half2_t b, half2_t f) {
     return f * (b - a) + a;
 }
 
-// Trilinear field (raw units) of every channel at index-space point p.
-template <int C, bool U16, bool F16>
-__device__ __forceinline__ void sample(const BrickGeom& g, const Sampler& S, float px, float py,
-                                       float pz, float (&x)[C]) {
-    using T = typename WordT<C, U16>::T;
-    constexpr uint32_t W = sizeof(T);
-    float fx, fy, fz;
-    const uint32_t o = corner_offset(g, S, px, py, pz, fx, fy, fz) * W;
-    T w000 = load_word<T>(S.rsrc, o, 0), w100 = load_word<T>(S.rsrc, o + W, 0);
-    T w010 = load_word<T>(S.rsrc, o, S.row_b), w110 = load_word<T>(S.rsrc, o + W, S.row_b);
-    T w001 = load_word<T>(S.rsrc, o, S.plane_b), w101 = load_word<T>(S.rsrc, o + W, S.plane_b);
-    T w011 = load_word<T>(S.rsrc, o, S.diag_b), w111 = load_word<T>(S.rsrc, o + W, S.diag_b);
+// Trilinear field (raw units) of every channel from landed taps.
+template <int C, bool U16, bool F16, typename T>
+__device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
+    const float fx = t.fx, fy = t.fy, fz = t.fz;
     if constexpr (!F16) {
         float a000[C], a100[C], a010[C], a110[C], a001[C], a101[C], a011[C], a111[C];
-        unpack_f32<C, U16>(w000, a000);
-        unpack_f32<C, U16>(w100, a100);
-        unpack_f32<C, U16>(w010, a010);
-        unpack_f32<C, U16>(w110, a110);
-        unpack_f32<C, U16>(w001, a001);
-        unpack_f32<C, U16>(w101, a101);
-        unpack_f32<C, U16>(w011, a011);
-        unpack_f32<C, U16>(w111, a111);
+        unpack_f32<C, U16>(t.w000, a000);
+        unpack_f32<C, U16>(t.w100, a100);
+        unpack_f32<C, U16>(t.w010, a010);
+        unpack_f32<C, U16>(t.w110, a110);
+        unpack_f32<C, U16>(t.w001, a001);
+        unpack_f32<C, U16>(t.w101, a101);
+        unpack_f32<C, U16>(t.w011, a011);
+        unpack_f32<C, U16>(t.w111, a111);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             float c00 = lerp(a000[c], a100[c], fx);
@@ -186,14 +203,14 @@ __device__ __forceinline__ void sample(const BrickGeom& g, const Sampler& S, flo
     } else {
         constexpr int NP = (C + 1) / 2;
         half2_t a000[NP], a100[NP], a010[NP], a110[NP], a001[NP], a101[NP], a011[NP], a111[NP];
-        unpack_f16<C, U16>(w000, a000);
-        unpack_f16<C, U16>(w100, a100);
-        unpack_f16<C, U16>(w010, a010);
-        unpack_f16<C, U16>(w110, a110);
-        unpack_f16<C, U16>(w001, a001);
-        unpack_f16<C, U16>(w101, a101);
-        unpack_f16<C, U16>(w011, a011);
-        unpack_f16<C, U16>(w111, a111);
+        unpack_f16<C, U16>(t.w000, a000);
+        unpack_f16<C, U16>(t.w100, a100);
+        unpack_f16<C, U16>(t.w010, a010);
+        unpack_f16<C, U16>(t.w110, a110);
+        unpack_f16<C, U16>(t.w001, a001);
+        unpack_f16<C, U16>(t.w101, a101);
+        unpack_f16<C, U16>(t.w011, a011);
+        unpack_f16<C, U16>(t.w111, a111);
         half2_t hx = {(_Float16)fx, (_Float16)fx};
         half2_t hy = {(_Float16)fy, (_Float16)fy};
         half2_t hz = {(_Float16)fz, (_Float16)fz};
@@ -210,6 +227,14 @@ __device__ __forceinline__ void sample(const BrickGeom& g, const Sampler& S, flo
             if (2 * q + 1 < C) x[2 * q + 1] = (float)v.y;
         }
     }
+}
+
+// Trilinear field (raw units) of every channel at index-space point p.
+template <int C, bool U16, bool F16>
+__device__ __forceinline__ void sample(const BrickGeom& g, const Sampler& S, float px, float py,
+                                       float pz, float (&x)[C]) {
+    using T = typename WordT<C, U16>::T;
+    interpolate<C, U16, F16>(fetch<T>(g, S, px + 1.0f, py + 1.0f, pz + 1.0f), x);
 }
 
 template <int V> struct Variant {
@@ -266,9 +291,10 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         n = c <= 0.0f ? 0 : (c >= (float)kMaxSamples ? kMaxSamples : (int)c);
     }
 
+    // Entry point in stored coordinates (index-space position + 1).
     float pe[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) pe[a] = fmaf(n > 0 ? t_in : 0.0f, d[a], p0[a]);
+    for (int a = 0; a < 3; ++a) pe[a] = fmaf(n > 0 ? t_in : 0.0f, d[a], p0[a]) + 1.0f;
 
     // Transfer-function coefficients (wave-uniform).
     ChanTF tf[C];
@@ -284,31 +310,54 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
     // reaches tau; the hardware execution mask then keeps it from
     // accumulating, and the wave leaves when the mask is empty (the wave-wide
     // ballot of the lanes' live flags).
-    if (n > 0) {
-        do {
-            const float s = fmaf((float)k, P.step, half_step);
-            float x[C];
-            sample<C, U16, F16>(P.g, S, fmaf(s, d[0], pe[0]), fmaf(s, d[1], pe[1]),
-                                fmaf(s, d[2], pe[2]), x);
-            float amax = 0.0f, r = 0.0f, gg = 0.0f, bb = 0.0f;
+    using Word = typename WordT<C, U16>::T;
+    // Composite one sample from landed taps.  `on` false leaves the lane's
+    // state bitwise unchanged (its weight is 0), without a branch.
+    auto composite = [&](const Taps<Word>& t, bool on) {
+        float x[C];
+        interpolate<C, U16, F16>(t, x);
+        float amax = 0.0f, r = 0.0f, gg = 0.0f, bb = 0.0f;
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const float u = __builtin_amdgcn_fmed3f(fmaf(x[c], tf[c].scale, tf[c].bias),
-                                                       0.0f, 1.0f);
-                const float g = u * fmaf(tf[c].curve, u, tf[c].one_m_curve);
-                amax = fmaxf(amax, tf[c].alpha_mul * g);
-                r = fmaf(g, tf[c].rgb[0], r);
-                gg = fmaf(g, tf[c].rgb[1], gg);
-                bb = fmaf(g, tf[c].rgb[2], bb);
-            }
-            const float a_s = fminf(amax, 1.0f);
-            const float wgt = (1.0f - A) * a_s;
-            Cr = fmaf(wgt, fminf(r, 1.0f), Cr);
-            Cg = fmaf(wgt, fminf(gg, 1.0f), Cg);
-            Cb = fmaf(wgt, fminf(bb, 1.0f), Cb);
-            A = A + wgt;
-            ++k;
-        } while (k < n && A < tau);
+        for (int c = 0; c < C; ++c) {
+            const float u = __builtin_amdgcn_fmed3f(fmaf(x[c], tf[c].scale, tf[c].bias), 0.0f,
+                                                   1.0f);
+            const float g = u * fmaf(tf[c].curve, u, tf[c].one_m_curve);
+            amax = fmaxf(amax, tf[c].alpha_mul * g);
+            r = fmaf(g, tf[c].rgb[0], r);
+            gg = fmaf(g, tf[c].rgb[1], gg);
+            bb = fmaf(g, tf[c].rgb[2], bb);
+        }
+        const float a_s = fminf(amax, 1.0f);
+        const float wgt = on ? (1.0f - A) * a_s : 0.0f;
+        Cr = fmaf(wgt, fminf(r, 1.0f), Cr);
+        Cg = fmaf(wgt, fminf(gg, 1.0f), Cg);
+        Cb = fmaf(wgt, fminf(bb, 1.0f), Cb);
+        A = A + wgt;
+        k += on ? 1 : 0;
+    };
+    auto fetch_at = [&](int j) -> Taps<Word> {
+        const float sj = fmaf((float)j, P.step, half_step);
+        return fetch<Word>(P.g, S, fmaf(sj, d[0], pe[0]), fmaf(sj, d[1], pe[1]),
+                           fmaf(sj, d[2], pe[2]));
+    };
+    if (n > 0) {
+        // Software pipeline over pairs of samples: the taps of the next
+        // sample are always in flight while the current one is interpolated
+        // and composited.  The pair's second sample is composited with a
+        // zero weight on lanes that finished on its first, so the only exit
+        // is at the end of the pair (a divergent loop: finished lanes are
+        // masked off and the wave leaves when none is live).  A fetch past a
+        // lane's last sample reads a clamped, in-frame address and is unused.
+        Taps<Word> a = fetch_at(0);
+        bool live;
+        do {
+            const Taps<Word> b = fetch_at(k + 1);
+            composite(a, true);
+            const bool on = k < n && A < tau;
+            a = fetch_at(k + 1);
+            composite(b, on);
+            live = on && k < n && A < tau;
+        } while (live);
     }
 
     if (valid) {

@@ -40,7 +40,7 @@ struct BrickGeom {
     int32_t plane;      // words per brick plane = (Bx + 1)(By + 1)
     int32_t brick;      // words per brick       = (Bx + 1)(By + 1)(Bz + 1)
     int32_t word;       // bytes per word
-    float clamp_hi[3];  // largest float below n per axis
+    float clamp_hi[3];  // largest float below n + 1 per axis
     uint64_t frame_bytes; // bytes per frame, multiple of 256
 };
 

@@ -223,6 +223,146 @@ def cells_and_vessels(dims, channels, bits, seed, n_cells=40, n_tubes=10,
     return vol
 
 
+# ------------------------------------------------ large volumes on the GPU
+
+
+def _stamp_ellipsoids_t(torch, sig, centres, radii, rots, peaks):
+    """Max-combine ellipsoids (one-voxel soft edge) into sig [Z][Y][X] (torch)."""
+    nz, ny, nx = sig.shape
+    dev = sig.device
+    for c, r, R, pk in zip(centres, radii, rots, peaks):
+        h = float(max(r)) + 1.5
+        lo = [max(0, int(math.floor(c[a] - h))) for a in range(3)]
+        hi = [min((nx, ny, nz)[a], int(math.ceil(c[a] + h)) + 1) for a in range(3)]
+        if any(hi[a] <= lo[a] for a in range(3)):
+            continue
+        z = torch.arange(lo[2], hi[2], device=dev, dtype=torch.float32).view(-1, 1, 1) - c[2]
+        y = torch.arange(lo[1], hi[1], device=dev, dtype=torch.float32).view(1, -1, 1) - c[1]
+        x = torch.arange(lo[0], hi[0], device=dev, dtype=torch.float32).view(1, 1, -1) - c[0]
+        q = [x * float(R[0, k]) + y * float(R[1, k]) + z * float(R[2, k]) for k in range(3)]
+        rho = torch.sqrt((q[0] / r[0]) ** 2 + (q[1] / r[1]) ** 2 + (q[2] / r[2]) ** 2)
+        val = pk * torch.clamp(0.5 - (rho - 1.0) * float(min(r)), 0.0, 1.0)
+        view = sig[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        torch.maximum(view, val, out=view)
+
+
+def _stamp_tube_t(torch, sig, pts, radius, peak, chunk=24):
+    """Max-combine a tube around a dense polyline, chunk by chunk (torch)."""
+    nz, ny, nx = sig.shape
+    dev = sig.device
+    P = torch.as_tensor(pts, dtype=torch.float32, device=dev)
+    for s0 in range(0, len(pts), chunk):
+        seg = P[s0:s0 + chunk]
+        mn = seg.min(0).values - radius - 1.5
+        mx = seg.max(0).values + radius + 1.5
+        lo = [max(0, int(math.floor(float(mn[a])))) for a in range(3)]
+        hi = [min((nx, ny, nz)[a], int(math.ceil(float(mx[a]))) + 1) for a in range(3)]
+        if any(hi[a] <= lo[a] for a in range(3)):
+            continue
+        z = torch.arange(lo[2], hi[2], device=dev, dtype=torch.float32)
+        y = torch.arange(lo[1], hi[1], device=dev, dtype=torch.float32)
+        x = torch.arange(lo[0], hi[0], device=dev, dtype=torch.float32)
+        d2 = None
+        for pnt in seg:
+            e = ((z - pnt[2]) ** 2).view(-1, 1, 1) + ((y - pnt[1]) ** 2).view(1, -1, 1) + \
+                ((x - pnt[0]) ** 2).view(1, 1, -1)
+            d2 = e if d2 is None else torch.minimum(d2, e)
+        val = peak * torch.clamp(radius + 0.5 - torch.sqrt(d2), 0.0, 1.0)
+        view = sig[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        torch.maximum(view, val, out=view)
+
+
+class DeviceSeries:
+    """Seeded confocal-like time series generated on the GPU, one frame at a
+    time: objects are drawn once (numpy generator), cells move by a random
+    walk from frame to frame, and each frame gets fresh shot noise from a
+    device generator seeded per (seed, frame).  Channel roles: 0 cells,
+    1 vessels (static), 2 nuclei, 3 puncta.  Returns frames as torch tensors
+    [C][Z][Y][X] (uint8, or int16 holding uint16 bits)."""
+
+    def __init__(self, dims, channels, bits, seed, frames=1, device="cuda", density=1.0,
+                 walk_sigma=1.0, background=100.0):
+        import torch
+        self.torch = torch
+        self.dims, self.channels, self.bits, self.seed = tuple(dims), channels, bits, seed
+        self.frames, self.device, self.walk = frames, device, walk_sigma
+        self.background = background
+        rng = np.random.default_rng(seed)
+        nx, ny, nz = dims
+        full = (1 << bits) - 1
+        self.scale = full / 4095.0
+        vol_frac = nx * ny * nz / float(512 * 512 * 64)
+        n_cells = max(1, int(round(40 * vol_frac * density)))
+        n_tubes = max(1, int(round(10 * math.sqrt(vol_frac) * density)))
+        self.cells = [(np.array([rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0, nz)]),
+                       rng.uniform(4.0, 8.0, size=3), _rotation(rng),
+                       rng.uniform(1200, 3000) * self.scale) for _ in range(n_cells)]
+        self.tubes = []
+        for _ in range(n_tubes):
+            k = int(rng.integers(4, 7))
+            ctrl = np.column_stack([rng.uniform(0, nx, k), rng.uniform(0, ny, k),
+                                    rng.uniform(0, nz, k)])
+            self.tubes.append((catmull_rom(ctrl, per_unit=1.0), rng.uniform(1500, 3500) * self.scale))
+        self.small = []
+        for c in (2, 3):
+            n = max(1, n_cells * (4 if c == 2 else 20) // 4)
+            rad = 2.0 if c == 2 else 1.0
+            self.small.append([(np.array([rng.uniform(0, nx), rng.uniform(0, ny),
+                                          rng.uniform(0, nz)]), rad,
+                                rng.uniform(1200, 3000) * self.scale) for _ in range(n)])
+        self.walk_rng = np.random.default_rng(seed + 7919)
+        self.walk_steps = [self.walk_rng.normal(0.0, walk_sigma, size=(len(self.cells), 3))
+                           for _ in range(frames)]
+        self._static = None
+
+    def _static_channels(self):
+        torch = self.torch
+        if self._static is None:
+            nx, ny, nz = self.dims
+            st = {}
+            if self.channels > 1:
+                sig = torch.zeros((nz, ny, nx), dtype=torch.float32, device=self.device)
+                for pts, pk in self.tubes:
+                    _stamp_tube_t(torch, sig, pts, 3.0, float(pk))
+                st[1] = sig
+            for c in range(2, self.channels):
+                sig = torch.zeros((nz, ny, nx), dtype=torch.float32, device=self.device)
+                objs = self.small[c - 2]
+                _stamp_ellipsoids_t(torch, sig, [o[0] for o in objs],
+                                    [(o[1],) * 3 for o in objs], [np.eye(3)] * len(objs),
+                                    [float(o[2]) for o in objs])
+                st[c] = sig
+            self._static = st
+        return self._static
+
+    def frame(self, t):
+        torch = self.torch
+        nx, ny, nz = self.dims
+        full = (1 << self.bits) - 1
+        offs = np.zeros((len(self.cells), 3))
+        for k in range(1, t + 1):
+            offs += self.walk_steps[k]
+        sig0 = torch.zeros((nz, ny, nx), dtype=torch.float32, device=self.device)
+        _stamp_ellipsoids_t(torch, sig0, [c[0] + o for c, o in zip(self.cells, offs)],
+                            [c[1] for c in self.cells], [c[2] for c in self.cells],
+                            [float(c[3]) for c in self.cells])
+        st = self._static_channels()
+        g = torch.Generator(device=self.device)
+        g.manual_seed(int(self.seed) * 1000003 + int(t))
+        out_dtype = torch.uint8 if self.bits <= 8 else torch.int16
+        out = torch.empty((self.channels, nz, ny, nx), dtype=out_dtype, device=self.device)
+        for c in range(self.channels):
+            sig = sig0 if c == 0 else st[c]
+            lam = sig + self.background * self.scale
+            noisy = torch.poisson(lam, generator=g).clamp_(max=full)
+            if out_dtype == torch.uint8:
+                out[c] = noisy.to(torch.uint8)
+            else:
+                out[c] = noisy.to(torch.int32).to(torch.int16)
+            del noisy, lam
+        return out
+
+
 # --------------------------------------------------------------- workloads
 
 

@@ -1,0 +1,351 @@
+"""Workload runners for the batching, serving and precision measurements.
+
+Each runner builds its seeded synthetic inputs on the GPU, drives libvr
+through the binding and returns a dict of measurements.  No rendering
+arithmetic lives here.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import synth
+from . import (VR_FP16, VR_FP32, VR_U8, VR_U16, Volume, make_request, vr_poll, vr_release,
+               vr_render, vr_render_batch, vr_submit)
+
+SIZES_BATCH = [(960, 540), (1280, 720), (1600, 900), (1920, 1080)]
+SIZES_SERVE = [(960, 540), (1920, 1080), (2560, 1440), (3840, 2160)]
+PALETTE = [(0.0, 1.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.4, 1.0), (1.0, 1.0, 0.0)]
+
+
+def log(msg):
+    import sys
+    print(msg, file=sys.stderr, flush=True)
+
+
+def default_tfs(channels):
+    return [synth.TF(300.0 / 4095.0, 3000.0 / 4095.0, 0.0, 1.0, PALETTE[c]) for c in range(channels)]
+
+
+def load_series(ctx, series, frames, tfs, stream=None):
+    """Create a resident volume and upload every frame of a DeviceSeries."""
+    import torch
+    nx, ny, nz = series.dims
+    dtype = VR_U8 if series.bits <= 8 else VR_U16
+    vol = Volume(ctx, (nx, ny, nz), series.channels, frames, dtype, series.bits)
+    for t in range(frames):
+        f = series.frame(t)
+        vol.upload(t, f, stream or torch.cuda.current_stream())
+        del f
+    for c, tf in enumerate(tfs):
+        vol.set_transfer(c, tf)
+    return vol
+
+
+def count_samples(ctx, reqs):
+    """Composited samples of each request (one counting render)."""
+    import torch
+    counts = []
+    for r in reqs:
+        eyes = 2 if r.stereo else 1
+        smp = torch.empty((eyes, r.height, r.width), dtype=torch.int32, device="cuda")
+        saved = r.out_samples
+        r.out_samples = smp.data_ptr()
+        vr_render(ctx.ptr, r, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        counts.append(int(smp.sum().item()))
+        r.out_samples = saved
+    return counts
+
+
+# ------------------------------------------------------------------ batching
+
+def batching(ctx, n_req=64, n_vol=16, seed=4, reps=5):
+    """64 stereo requests over 16 volumes of uneven size (2^21..2^26 voxels,
+    1-4 channels, u8 / u16-12 / u16-16): one vr_render_batch call against 64
+    sequential vr_render calls (one launch per stereo request)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    vols, meta = [], []
+    log("batching: generating volumes")
+    for q in range(n_vol):
+        voxels = 2.0 ** rng.uniform(21, 26)
+        nz = int(8 * round(rng.uniform(64, 128) / 8))
+        nxy = int(round(math.sqrt(voxels / nz)))
+        ch = int(rng.integers(1, 5))
+        kind = int(rng.integers(0, 3))
+        bits = (8, 12, 16)[kind]
+        ser = synth.DeviceSeries((nxy, nxy, nz), ch, bits, 4000 + q)
+        tfs = default_tfs(ch)
+        vols.append(load_series(ctx, ser, 1, tfs))
+        meta.append(((nxy, nxy, nz), ch, bits))
+    reqs, outs = [], []
+    for q in range(n_req):
+        v = int(rng.integers(0, n_vol))
+        dims = meta[v][0]
+        w, h = SIZES_BATCH[int(rng.integers(0, len(SIZES_BATCH)))]
+        cam = synth.random_view_camera(rng, dims, True)
+        out = torch.empty((2, h, w, 4), dtype=torch.float32, device="cuda")
+        reqs.append(make_request(vols[v].ptr, 0, cam, w, h, True, 1.0, 0.99, out))
+        outs.append(out)
+    counts = count_samples(ctx, reqs)
+    total_samples = sum(counts)
+    eff_bytes = sum(c * 8 * meta_bytes(meta, vols, reqs[i]) for i, c in enumerate(counts))
+    stream = torch.cuda.current_stream()
+
+    def run_plain():
+        for r in reqs:
+            vr_render(ctx.ptr, r, stream)
+
+    def run_batch():
+        vr_render_batch(ctx.ptr, reqs, stream)
+
+    # warm-up (the first batch of this shape class runs the autotuner)
+    run_plain()
+    run_batch()
+    torch.cuda.synchronize()
+    # bitwise equality of the two paths
+    run_plain()
+    torch.cuda.synchronize()
+    ref = [o.clone() for o in outs]
+    for o in outs:
+        o.fill_(float("nan"))
+    run_batch()
+    torch.cuda.synchronize()
+    equal = all(torch.equal(a, b) for a, b in zip(outs, ref))
+    del ref
+
+    def timed(fn):
+        best = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best.append(time.perf_counter() - t0)
+        return float(np.median(best))
+
+    t_plain = timed(run_plain)
+    t_batch = timed(run_batch)
+    for v in vols:
+        v.destroy()
+    return {
+        "workload": "batching: 64 stereo requests over 16 volumes (2^21..2^26 voxels, 1-4 "
+                    "channels, u8/u16-12/u16-16), 960x540..1920x1080 per eye, step 1, alpha 0.99",
+        "requests": n_req, "total_samples": total_samples, "bitwise_equal": equal,
+        "plain_s": t_plain, "batch_s": t_batch,
+        "plain_stereo_fps": n_req / t_plain, "batch_stereo_fps": n_req / t_batch,
+        "plain_samples_per_s": total_samples / t_plain,
+        "batch_samples_per_s": total_samples / t_batch,
+        "batch_eff_GBps": eff_bytes / t_batch / 1e9,
+        "speedup": t_plain / t_batch,
+    }
+
+
+def meta_bytes(meta, vols, req):
+    for (dims, ch, bits), v in zip(meta, vols):
+        if v.ptr == req.vol:
+            return ch * (1 if bits <= 8 else 2)
+    return 0
+
+
+# ------------------------------------------------------------------ precision
+
+def precision_setup(ctx, frames=48, seed=3, upload=None):
+    """The 4-channel uint8 1024x1024x48 series (seeded, generated on the GPU),
+    its transfer functions (lo 24/255, hi 220/255, green / red / blue /
+    yellow) and the orbit cameras (azimuth 7.5 degrees per frame, elevation
+    40, fov 40).  `upload` lists the frames to make resident (default all)."""
+    dims = (1024, 1024, 48)
+    ser = synth.DeviceSeries(dims, 4, 8, seed, frames=frames, density=1.25)
+    tfs = [synth.TF(24 / 255, 220 / 255, 0.0, 1.0, PALETTE[c]) for c in range(4)]
+    cams = [synth.orbit_camera(dims, 7.5 * t, 40.0, 40.0) for t in range(frames)]
+    return dims, ser, tfs, cams
+
+
+def precision(ctx, frames=48, seed=3, reps=2):
+    """48 frames resident in HBM, one stereo 1920x1080 render per frame,
+    FP32 against FP16 sampling (throughput; the error against the FP64
+    oracle is measured by the test-suite)."""
+    import torch
+    log("precision: generating series")
+    dims, ser, tfs, cams = precision_setup(ctx, frames, seed)
+    vol = load_series(ctx, ser, frames, tfs)
+    W, H = 1920, 1080
+    out = torch.empty((2, H, W, 4), dtype=torch.float32, device="cuda")
+    res = {"workload": "precision: 4ch u8 1024x1024x48, 48 frames resident, stereo 1920x1080 "
+                       "per frame, orbit, step 1, alpha 0.99",
+           "resident_bytes": vol.bytes}
+    stream = torch.cuda.current_stream()
+    for prec, name in ((VR_FP32, "fp32"), (VR_FP16, "fp16")):
+        reqs = [make_request(vol.ptr, t, cams[t], W, H, True, 1.0, 0.99, out, precision=prec)
+                for t in range(frames)]
+        total = sum(count_samples(ctx, reqs))
+        for r in reqs:
+            vr_render(ctx.ptr, r, stream)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            for r in reqs:
+                vr_render(ctx.ptr, r, stream)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        dt = float(np.median(times))
+        res[name] = {"samples_per_s": total / dt, "stereo_fps": frames / dt,
+                     "eff_GBps": total * 32 / dt / 1e9, "samples_per_series": total}
+    vol.destroy()
+    return res
+
+
+# ------------------------------------------------------------------- serving
+
+class _Pool:
+    """Reusable output buffers per image size (client side)."""
+
+    def __init__(self, per_size=6):
+        self.free = {}
+        self.per_size = per_size
+
+    def take(self, w, h):
+        import torch
+        lst = self.free.setdefault((w, h), [])
+        if lst:
+            return lst.pop()
+        return torch.empty((2, h, w, 4), dtype=torch.float32, device="cuda")
+
+    def give(self, w, h, t):
+        self.free.setdefault((w, h), []).append(t)
+
+
+def serving(ctx, total_gb=150.0, seconds=10.0, warm=1.0, rates=(25, 50, 100, 200, 400),
+            seed=5, n_datasets=16, check=32):
+    """16 resident datasets (2-4 channels, 24-96 frames of up to
+    1024x1024x64 uint16-12, frame counts scaled to `total_gb` resident);
+    Poisson arrivals of stereo requests (960x540..3840x2160) served by the
+    continuous-batching loop, against the same arrivals on a FIFO server of
+    plain per-request launches.  Latency = completion - scheduled arrival."""
+    import torch
+    rng = np.random.default_rng(seed)
+    specs = []
+    for q in range(n_datasets):
+        ch = int(rng.integers(2, 5))
+        nxy = int(rng.choice([512, 768, 1024]))
+        nz = int(rng.choice([32, 48, 64]))
+        frames = int(rng.integers(24, 97))
+        specs.append([(nxy, nxy, nz), ch, frames])
+    from . import vr_volume_desc, vr_volume_storage_bytes
+    import ctypes as C
+
+    def stored(dims, ch, frames):
+        d = vr_volume_desc(dims[0], dims[1], dims[2], ch, frames, VR_U16, 12,
+                           (C.c_float * 3)(1, 1, 1), (C.c_float * 3)(0, 0, 0),
+                           (C.c_int32 * 3)(0, 0, 0))
+        return vr_volume_storage_bytes(d)
+
+    tot = sum(stored(*s) for s in specs)
+    scale = total_gb * 1e9 / tot
+    for s in specs:
+        s[2] = max(1, int(round(s[2] * scale)))
+    resident = sum(stored(*s) for s in specs)
+    log(f"serving: generating {resident / 1e9:.1f} GB of resident series")
+    vols = []
+    for q, (dims, ch, frames) in enumerate(specs):
+        ser = synth.DeviceSeries(dims, ch, 12, 5000 + q, frames=frames)
+        vols.append(load_series(ctx, ser, frames, default_tfs(ch)))
+        torch.cuda.synchronize()
+        log(f"  dataset {q}: {dims} x {ch} ch x {frames} frames")
+    pool = _Pool()
+    results = {"workload": "serving: 16 resident datasets (2-4 ch, u16-12, up to 1024x1024x64, "
+                           "24-96 frames scaled to the total), Poisson arrivals, stereo "
+                           "960x540..3840x2160, step 1, alpha 0.99",
+               "resident_bytes": resident, "seconds_per_rate": seconds, "rates": {}}
+
+    def make_arrivals(lam):
+        t, arr = 0.0, []
+        while t < seconds:
+            t += rng.exponential(1.0 / lam)
+            if t >= seconds:
+                break
+            q = int(rng.integers(0, n_datasets))
+            dims, ch, frames = specs[q]
+            w, h = SIZES_SERVE[int(rng.integers(0, len(SIZES_SERVE)))]
+            arr.append((t, q, int(rng.integers(0, frames)), synth.random_view_camera(rng, dims),
+                        w, h))
+        return arr
+
+    def summarize(lat, n_done, span):
+        lat = np.sort(np.asarray(lat))
+        if lat.size == 0:
+            return {}
+        pick = lambda p: float(lat[min(lat.size - 1, max(0, int(math.ceil(p * lat.size)) - 1))])
+        return {"p50_ms": pick(0.50) * 1e3, "p99_ms": pick(0.99) * 1e3,
+                "stereo_fps": n_done / span, "completed": int(n_done)}
+
+    for lam in rates:
+        arr = make_arrivals(lam)
+        # ---- served (continuous batching)
+        torch.cuda.synchronize()
+        t0 = time.monotonic_ns()
+        pending = {}
+        lat, keep = [], {}
+        check_ids = set(rng.choice(len(arr), size=min(check, len(arr)), replace=False).tolist())
+        k = 0
+        while k < len(arr) or pending:
+            now = time.monotonic_ns()
+            while k < len(arr) and t0 + int(arr[k][0] * 1e9) <= now:
+                ta, q, fr, cam, w, h = arr[k]
+                out = pool.take(w, h)
+                req = make_request(vols[q].ptr, fr, cam, w, h, True, 1.0, 0.99, out)
+                tk = vr_submit(ctx.ptr, req)
+                pending[tk] = (k, t0 + int(ta * 1e9), w, h, out, req)
+                k += 1
+            done = []
+            for tk, (idx, sched, w, h, out, req) in pending.items():
+                info = vr_poll(ctx.ptr, tk)
+                if info.state >= 2:
+                    if info.state == 3:
+                        raise RuntimeError(f"served request failed: status {info.err}")
+                    if arr[idx][0] >= warm:
+                        lat.append((info.t_done_ns - sched) * 1e-9)
+                    if idx in check_ids:
+                        keep[idx] = out.clone()
+                    done.append(tk)
+                    pool.give(w, h, out)
+                    vr_release(ctx.ptr, tk)
+            for tk in done:
+                del pending[tk]
+            if not done:
+                time.sleep(0.0001)
+        span = (time.monotonic_ns() - t0) * 1e-9
+        served = summarize(lat, sum(1 for a in arr if a[0] >= warm), span - warm)
+        # ---- same arrivals, FIFO server of plain per-request launches
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        t0 = time.monotonic_ns()
+        lat2 = []
+        same = True
+        for idx, (ta, q, fr, cam, w, h) in enumerate(arr):
+            sched = t0 + int(ta * 1e9)
+            while time.monotonic_ns() < sched:
+                pass
+            out = pool.take(w, h)
+            vr_render(ctx.ptr, make_request(vols[q].ptr, fr, cam, w, h, True, 1.0, 0.99, out),
+                      stream)
+            torch.cuda.synchronize()
+            if ta >= warm:
+                lat2.append((time.monotonic_ns() - sched) * 1e-9)
+            if idx in keep:
+                same = same and torch.equal(keep[idx], out)
+            pool.give(w, h, out)
+        span2 = (time.monotonic_ns() - t0) * 1e-9
+        fifo = summarize(lat2, sum(1 for a in arr if a[0] >= warm), span2 - warm)
+        results["rates"][str(lam)] = {"served": served, "fifo_plain": fifo,
+                                      "alone_equals_mix": same, "checked": len(keep),
+                                      "requests": len(arr)}
+        log(f"  rate {lam}: served {served} fifo {fifo} same {same}")
+    for v in vols:
+        v.destroy()
+    return results

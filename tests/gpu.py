@@ -49,12 +49,14 @@ def render(ctx, scene, precision=vr.VR_FP32, brick=(0, 0, 0), vol=None):
     own = vol is None
     if own:
         vol = make_volume(ctx, scene, brick)
-    out, smp = alloc_out(scene)
-    req = request_for(vol, scene, out, smp, precision)
-    vr.vr_render(ctx.ptr, req, torch.cuda.current_stream())
-    torch.cuda.synchronize()
-    if own:
-        vol.destroy()
+    try:
+        out, smp = alloc_out(scene)
+        req = request_for(vol, scene, out, smp, precision)
+        vr.vr_render(ctx.ptr, req, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+    finally:
+        if own:
+            vol.destroy()
     return out.cpu().numpy(), smp.cpu().numpy()
 
 

@@ -24,7 +24,10 @@ def ctx():
     torch.cuda.init()
     c = vr.Context(0)
     yield c
-    c.close()
+    try:
+        c.close()
+    except vr.VrError:
+        pass  # a failed test may leave volumes alive
 
 
 def log(msg):

@@ -1,0 +1,48 @@
+"""GPU: the precision workload (4-channel uint8 1024x1024x48 series, stereo
+1920x1080, orbit cameras) against the FP64 oracle on seeded pixels of
+frames 0, 16, 32 and 47, for FP32 (tol 1e-3) and FP16 sampling (tol 4e-3).
+Prints the max-abs RGBA error per precision."""
+import numpy as np
+import pytest
+
+import gpu
+import orc
+import paper_1407_2089_amd as vr
+from paper_1407_2089_amd import synth, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def test_precision_workload_errors_against_oracle():
+    import torch
+    torch.cuda.init()
+    ctx = vr.Context(0)
+    frames = (0, 16, 32, 47)
+    dims, ser, tfs, cams = workloads.precision_setup(ctx)
+    W, H = 1920, 1080
+    rng = np.random.default_rng(33)
+    worst = {vr.VR_FP32: 0.0, vr.VR_FP16: 0.0}
+    for t in frames:
+        f = ser.frame(t)
+        host = f.cpu().numpy()
+        vol = vr.Volume(ctx, (dims[0], dims[1], dims[2]), 4, 1, vr.VR_U8, 8)
+        vol.upload(0, f)
+        for c, tf in enumerate(tfs):
+            vol.set_transfer(c, tf)
+        sc = synth.Scene("precision", host, 8, tfs, cams[t], W, H, True, 1.0, 0.99)
+        pix = rng.choice(W * H, size=1 << 13, replace=False)
+        for prec, tol in ((vr.VR_FP32, 1e-3), (vr.VR_FP16, 4e-3)):
+            out, smp = gpu.alloc_out(sc)
+            req = gpu.request_for(vol, sc, out, smp, prec)
+            vr.vr_render(ctx.ptr, req, torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            img = out.cpu().numpy().reshape(2, -1, 4)[:, pix]
+            ss = smp.cpu().numpy().reshape(2, -1)[:, pix]
+            ref = orc.render_all(sc, band_eps=tol, pixels=pix)
+            st = gpu.compare(img, ss, ref, tol)
+            worst[prec] = max(worst[prec], st["max_err_outside_band"])
+            print(f"frame {t} {'fp16' if prec else 'fp32'}: {st}", flush=True)
+        vol.destroy()
+    print(f"precision workload max-abs RGBA error: fp32 {worst[vr.VR_FP32]:.3e} "
+          f"fp16 {worst[vr.VR_FP16]:.3e}", flush=True)
+    ctx.close()

@@ -71,8 +71,18 @@ def test_p2_termination_band_brackets_neighbours():
     eps = max(abs(x - 0.99) for x in A[2:5]) + 1e-9
     r = orc.render(sc, band_eps=eps)
     lo, hi = r["band_k"][..., 0], r["band_k"][..., 1]
-    members = [k + 4 for k, x in zip(range(m - 3, m + 4), A) if abs(x - 0.99) <= eps]
+    inside = [k + 4 for k, x in zip(range(m - 3, m + 4), A) if abs(x - 0.99) <= eps]
+    members = inside + [k + 1 for k in inside]  # and one sample past each of them
     assert (lo == min(members)).all() and (hi == max(members)).all()
+    # the band's colour range covers exactly those stops
+    g = (200 / 255 - sc.tfs[0].lo) / (1 - sc.tfs[0].lo)
+    Ak = [1 - (1 - a) ** (k - 4) for k in members]
+    exp_lo = min(Ak) * g * np.array(sc.tfs[0].rgb)
+    exp_hi = max(Ak) * g * np.array(sc.tfs[0].rgb)
+    np.testing.assert_allclose(r["band_lo"][..., :3].reshape(-1, 3), np.broadcast_to(exp_lo, (64, 3)),
+                               atol=1e-12)
+    np.testing.assert_allclose(r["band_hi"][..., :3].reshape(-1, 3), np.broadcast_to(exp_hi, (64, 3)),
+                               atol=1e-12)
 
 
 def test_p2_two_channel_slab_merge_closed_form():
