@@ -73,6 +73,8 @@ def main():
                     help="realistic (default): one stereo 1920x1080 frame per step; batch: 64 "
                          "mixed requests, batched vs plain launches; serve: Poisson arrivals "
                          "on resident datasets, p50/p99; precision: 48-frame series FP32/FP16")
+    ap.add_argument("--brick", default="0,0,0", help="brick edge per axis (0,0,0 = default)")
+    ap.add_argument("--tile", default="", help="wave_w,wave_h,waves_x,waves_y of vr_render")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-gb", type=float, default=150.0)
     ap.add_argument("--serve-rates", default="25,50,100,200,400")
@@ -121,7 +123,10 @@ def main():
     sc = synth.realistic_scene()
     ctx = vr.Context(0)
     c, nz, ny, nx = sc.volume.shape
-    vol = vr.Volume(ctx, (nx, ny, nz), c, 1, vr.VR_U16, sc.bits)
+    brick = tuple(int(b) for b in args.brick.split(","))
+    vol = vr.Volume(ctx, (nx, ny, nz), c, 1, vr.VR_U16, sc.bits, brick=brick)
+    if args.tile:
+        vr.vr_test_plain_tile(ctx.ptr, *[int(t) for t in args.tile.split(",")])
     stream = torch.cuda.current_stream()
     vol.upload(0, torch.from_numpy(sc.volume.view(np.int16)).cuda(), stream)
     for ch, tf in enumerate(sc.tfs):
@@ -177,7 +182,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "realistic frame: 2ch u16-12 512x512x64 cells+vessels, "
                                "perspective stereo 1920x1080 per eye, step 1, alpha 0.99",
-                   "eyes": 2, "width": sc.width, "height": sc.height,
+                   "eyes": 2, "width": sc.width, "height": sc.height, "brick": list(brick),
+                   "tile": args.tile or "8,8,2,2",
                    "samples_per_step": samples_per_step},
         "stereo_fps": args.steps / wall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,

@@ -28,6 +28,11 @@ vr_status vr_test_fake_backend(vr_ctx* ctx, int32_t slots, double ns_per_ray,
 vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h, int32_t waves_x,
                              int32_t waves_y);
 
+/* The same for plain vr_render launches (default 8 x 8 pixels per wave, 2 x 2
+ * waves); all zeros restores the default. */
+vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h, int32_t waves_x,
+                             int32_t waves_y);
+
 #ifdef __cplusplus
 }
 #endif

@@ -101,6 +101,7 @@ def lib():
             "vr_debug_sample": [P, C.c_int32, P, C.c_int32, P, P],
             "vr_test_fake_backend": [P, C.c_int32, C.c_double, C.c_int32, C.c_int32],
             "vr_test_batch_tile": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
+            "vr_test_plain_tile": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -208,6 +209,10 @@ def vr_debug_sample(vol, frame: int, pts, n: int, out, stream=None):
 
 def vr_test_batch_tile(ctx, wave_w=0, wave_h=0, waves_x=0, waves_y=0):
     _check(lib().vr_test_batch_tile(ctx, wave_w, wave_h, waves_x, waves_y))
+
+
+def vr_test_plain_tile(ctx, wave_w=0, wave_h=0, waves_x=0, waves_y=0):
+    _check(lib().vr_test_plain_tile(ctx, wave_w, wave_h, waves_x, waves_y))
 
 
 def vr_test_fake_backend(ctx, slots: int, ns_per_ray: float, fail_width: int = -1,

@@ -437,7 +437,7 @@ vr_status vr_render(vr_ctx* ctx, const vr_render_req* req, void* hip_stream) {
         std::lock_guard<std::mutex> lk(req->vol->tf_mu);
         make_params(*req, req->vol->tf, &P);
     }
-    hipError_t e = launch_render(P, default_tile(), (hipStream_t)hip_stream);
+    hipError_t e = launch_render(P, ctx->plain_tile, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return ok();
 }

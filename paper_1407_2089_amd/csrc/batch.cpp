@@ -326,6 +326,20 @@ extern "C" vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wav
     return ok();
 }
 
+extern "C" vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h,
+                                        int32_t waves_x, int32_t waves_y) {
+    if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    if (wave_w == 0 && wave_h == 0 && waves_x == 0 && waves_y == 0) {
+        ctx->plain_tile = default_tile();
+        return ok();
+    }
+    if (wave_w <= 0 || wave_h <= 0 || waves_x <= 0 || waves_y <= 0 || wave_w * wave_h != kWave ||
+        waves_x * waves_y * kWave != kBlockThreads)
+        return fail(VR_ERR_INVALID_ARG, "a tile is 64 pixels per wave and 4 waves per block");
+    ctx->plain_tile = TileShape{wave_w, wave_h, waves_x, waves_y};
+    return ok();
+}
+
 extern "C" vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
                                      void* hip_stream) {
     if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");

@@ -129,8 +129,8 @@ template <typename T> struct Taps {
 // Locate the taps around a point given in stored coordinates (index-space
 // position + 1) and issue their loads.  The point is clamped into [0, n + 1)
 // per axis (it lies in the box [0, n + 1] up to rounding; a point on the
-// upper face is evaluated at the largest float below n + 1, where the field
-// is within 1e-7 relative of its zero there).  The low corner floor(q) then
+// upper face is evaluated at the largest float below n + 1: one float step,
+// about (n + 1) * 6e-8 voxels, inside the face where the field is zero).  The low corner floor(q) then
 // lies in [0, n], so every tap is inside the frame; floor and fraction come
 // from the same value, so they always agree.  Every factor and partial sum of
 // the word index is below 2^24 (a frame holds < 2^31 words and a brick >= 125
@@ -333,29 +333,43 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         Cg = fmaf(wgt, fminf(gg, 1.0f), Cg);
         Cb = fmaf(wgt, fminf(bb, 1.0f), Cb);
         A = A + wgt;
-        k += on ? 1 : 0;
     };
     auto fetch_at = [&](int j) -> Taps<Word> {
         const float sj = fmaf((float)j, P.step, half_step);
         return fetch<Word>(P.g, S, fmaf(sj, d[0], pe[0]), fmaf(sj, d[1], pe[1]),
                            fmaf(sj, d[2], pe[2]));
     };
+    // Depth-synchronous schedule.  Rays of one wave enter the volume at
+    // different depths, so at equal sample index their sample points are
+    // spread along the view and each tap load touches many cache lines.  A
+    // lane therefore starts its first sample at the wave iteration that
+    // matches its entry depth (offset from the wave's shallowest entry, in
+    // steps), and at every iteration all lanes sample near one depth.  Only
+    // the iteration at which a sample is taken moves: each lane composites
+    // the same samples, in order, with the same arithmetic.
+    float t_first = n > 0 ? t_in : INFINITY;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) t_first = fminf(t_first, __shfl_xor(t_first, m, kWave));
+    if (n > 0) k = -(int)fminf((t_in - t_first) / P.step, 64.0f);
     if (n > 0) {
         // Software pipeline over pairs of samples: the taps of the next
         // sample are always in flight while the current one is interpolated
         // and composited.  The pair's second sample is composited with a
         // zero weight on lanes that finished on its first, so the only exit
         // is at the end of the pair (a divergent loop: finished lanes are
-        // masked off and the wave leaves when none is live).  A fetch past a
-        // lane's last sample reads a clamped, in-frame address and is unused.
-        Taps<Word> a = fetch_at(0);
+        // masked off and the wave leaves when none is live).  A fetch before
+        // a lane's first or past its last sample reads a clamped, in-frame
+        // address and is unused.
+        Taps<Word> a = fetch_at(k);
         bool live;
         do {
             const Taps<Word> b = fetch_at(k + 1);
-            composite(a, true);
+            composite(a, k >= 0);
+            ++k;  // every lane in the loop moves on to its next sample index
             const bool on = k < n && A < tau;
             a = fetch_at(k + 1);
-            composite(b, on);
+            composite(b, on && k >= 0);
+            k += on ? 1 : 0;
             live = on && k < n && A < tau;
         } while (live);
     }

@@ -92,10 +92,13 @@ def test_sampler_matches_oracle_everywhere_in_box(ctx, ch, dtype, bits):
     got = out.cpu().numpy().reshape(-1, ch)
     exp = oracle.sample(orc.volume(sc), pts.astype(np.float64))
     np.testing.assert_allclose(got, exp, rtol=0, atol=2e-6 * (1 << bits))
-    # faces of [-1, n]: exactly 0 on the lower faces; the upper faces are
-    # evaluated at the largest float below n (within 1e-7 of full scale)
+    # faces of [-1, n]: exactly 0 on the lower faces; an upper face is
+    # evaluated one float step inside it (at the largest float below n + 1 in
+    # stored coordinates), where the field is at most that step times full scale
     assert np.all(got[[0, 2, 4]] == 0)
-    assert np.all(np.abs(got[[1, 3, 5]]) <= 1e-6 * ((1 << bits) - 1))
+    for row, n in zip((1, 3, 5), (nx, ny, nz)):
+        step = float(np.spacing(np.float32(n + 1)))
+        assert np.all(np.abs(got[row]) <= 1.01 * step * ((1 << bits) - 1))
     v.destroy()
 
 
