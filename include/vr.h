@@ -71,7 +71,11 @@ typedef struct {
     float spacing[3];   /* > 0, world units per voxel along x, y, z          */
     float origin[3];    /* world position of voxel (0, 0, 0)                 */
     int32_t brick[3];   /* brick edge per axis, each 4, 8, 16 or 32; all 0
-                           selects the library default.  Fixed at creation.  */
+                           selects the library default for the voxel word
+                           (all channels of a voxel, 1, 2, 4 or 8 bytes):
+                           16 x 16 x 8 for 1-byte, 8 x 16 x 8 for 2- and
+                           4-byte, 8 x 8 x 8 for 8-byte words.  Fixed at
+                           creation.                                          */
 } vr_volume_desc;
 
 /* One channel's transfer function (User Interface, transfer-function

@@ -44,11 +44,23 @@ static int log2_exact(int v) {
     return (1 << s) == v ? s : -1;
 }
 
-constexpr int kDefaultBrick = 16;
-
+// Default brick edges by voxel-word size.  A wave's taps at one sample index
+// cover a small patch parallel to the face its rays entered through; brick
+// rows of about 16-36 bytes let one cache line serve several rows of that
+// patch.  Measured on MI355X (2-channel uint16: 8 x 16 x 8 bricks 0.318 ms
+// against 0.396 ms for 16^3 on a 1920x1080 stereo pair; 1-byte words prefer
+// 16-wide rows; 8-byte words 8-wide).  The z edge of 8 keeps the halo
+// overhead at 1.28-1.42x.
 static void brick_edges(const vr_volume_desc& d, int b[3]) {
     const bool dflt = d.brick[0] == 0 && d.brick[1] == 0 && d.brick[2] == 0;
-    for (int a = 0; a < 3; ++a) b[a] = dflt ? kDefaultBrick : d.brick[a];
+    if (!dflt) {
+        for (int a = 0; a < 3; ++a) b[a] = d.brick[a];
+        return;
+    }
+    const int w = word_bytes(d.channels, d.dtype == VR_U16);
+    b[0] = w == 1 ? 16 : 8;
+    b[1] = w == 8 ? 8 : 16;
+    b[2] = 8;
 }
 
 BrickGeom make_geom(const vr_volume_desc& d) {

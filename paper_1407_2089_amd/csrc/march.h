@@ -339,36 +339,26 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         return fetch<Word>(P.g, S, fmaf(sj, d[0], pe[0]), fmaf(sj, d[1], pe[1]),
                            fmaf(sj, d[2], pe[2]));
     };
-    // Depth-synchronous schedule.  Rays of one wave enter the volume at
-    // different depths, so at equal sample index their sample points are
-    // spread along the view and each tap load touches many cache lines.  A
-    // lane therefore starts its first sample at the wave iteration that
-    // matches its entry depth (offset from the wave's shallowest entry, in
-    // steps), and at every iteration all lanes sample near one depth.  Only
-    // the iteration at which a sample is taken moves: each lane composites
-    // the same samples, in order, with the same arithmetic.
-    float t_first = n > 0 ? t_in : INFINITY;
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) t_first = fminf(t_first, __shfl_xor(t_first, m, kWave));
-    if (n > 0) k = -(int)fminf((t_in - t_first) / P.step, 64.0f);
     if (n > 0) {
         // Software pipeline over pairs of samples: the taps of the next
         // sample are always in flight while the current one is interpolated
         // and composited.  The pair's second sample is composited with a
         // zero weight on lanes that finished on its first, so the only exit
         // is at the end of the pair (a divergent loop: finished lanes are
-        // masked off and the wave leaves when none is live).  A fetch before
-        // a lane's first or past its last sample reads a clamped, in-frame
-        // address and is unused.
+        // masked off and the wave leaves when none is live).  At equal
+        // sample index a wave's sample points lie on a patch parallel to the
+        // face its rays entered through, which the brick layout serves with
+        // few cache lines.  A fetch past a lane's last sample reads a clamped,
+        // in-frame address and is unused.
         Taps<Word> a = fetch_at(k);
         bool live;
         do {
             const Taps<Word> b = fetch_at(k + 1);
-            composite(a, k >= 0);
-            ++k;  // every lane in the loop moves on to its next sample index
+            composite(a, true);
+            ++k;
             const bool on = k < n && A < tau;
             a = fetch_at(k + 1);
-            composite(b, on && k >= 0);
+            composite(b, on);
             k += on ? 1 : 0;
             live = on && k < n && A < tau;
         } while (live);

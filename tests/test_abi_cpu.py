@@ -52,9 +52,13 @@ def test_storage_bytes_follow_brick_layout(dims, ch, dtype, brick):
     assert vr.vr_volume_storage_bytes(d) == 3 * frame
 
 
-def test_default_brick_is_sixteen():
-    assert vr.vr_volume_storage_bytes(desc(brick=(0, 0, 0))) == \
-        vr.vr_volume_storage_bytes(desc(brick=(16, 16, 16)))
+@pytest.mark.parametrize("ch,dtype,bits,brick", [
+    (1, vr.VR_U8, 8, (16, 16, 8)), (2, vr.VR_U8, 8, (8, 16, 8)), (1, vr.VR_U16, 12, (8, 16, 8)),
+    (2, vr.VR_U16, 12, (8, 16, 8)), (4, vr.VR_U8, 8, (8, 16, 8)), (3, vr.VR_U8, 8, (8, 16, 8)),
+    (3, vr.VR_U16, 16, (8, 8, 8)), (4, vr.VR_U16, 16, (8, 8, 8))])
+def test_default_brick_depends_on_word_size(ch, dtype, bits, brick):
+    assert vr.vr_volume_storage_bytes(desc(ch=ch, dtype=dtype, bits=bits, brick=(0, 0, 0))) == \
+        vr.vr_volume_storage_bytes(desc(ch=ch, dtype=dtype, bits=bits, brick=brick))
 
 
 @pytest.mark.parametrize("field,value", [

@@ -237,10 +237,10 @@ def test_p7_channel_permutation_on_gpu(ctx):
 
 # --------------------------------------------------------- layouts
 
-@pytest.mark.parametrize("brick", [(4, 4, 4), (8, 8, 8), (32, 32, 32), (16, 16, 4)])
+@pytest.mark.parametrize("brick", [(4, 4, 4), (16, 16, 16), (32, 32, 32), (16, 16, 4)])
 def test_brick_shape_does_not_change_the_image(ctx, realistic, brick):
     sc = Scene("small", realistic.volume[:, :32, :160, :192].copy(), 12, realistic.tfs,
                synth.orbit_camera((192, 160, 32), 30.0, 50.0, 45.0), 160, 96, True, 1.0, 0.99)
-    a, sa = gpu.render(ctx, sc, brick=(16, 16, 16))
+    a, sa = gpu.render(ctx, sc, brick=(0, 0, 0))
     b, sb = gpu.render(ctx, sc, brick=brick)
     assert np.array_equal(a, b) and np.array_equal(sa, sb)
