@@ -54,14 +54,35 @@ __device__ __forceinline__ void unpack_f32(T w, float (&x)[C]) {
 }
 
 // Raw channel values of one stored word as FP16 pairs (channel 2q, 2q + 1).
+// uint8 channels convert exactly with one byte permute per pair: each byte b
+// is placed under the FP16 pattern 0x64.. (the value 1024 + b), then 1024 is
+// subtracted from both halves at once.  uint16 channels convert with the
+// FP16 rounding of the value (exact up to 2048).
+__device__ __forceinline__ half2_t bytes_to_half2(uint32_t w, uint32_t sel) {
+    const uint32_t v = __builtin_amdgcn_perm(0x64646464u, w, sel);
+    const half2_t bias = {(_Float16)1024.0f, (_Float16)1024.0f};
+    return __builtin_bit_cast(half2_t, v) - bias;
+}
+
 template <int C, bool U16, typename T>
 __device__ __forceinline__ void unpack_f16(T w, half2_t (&h)[(C + 1) / 2]) {
-    float x[C];
-    unpack_f32<C, U16>(w, x);
-#pragma unroll
-    for (int q = 0; q < (C + 1) / 2; ++q) {
-        h[q].x = (_Float16)x[2 * q];
-        h[q].y = (2 * q + 1 < C) ? (_Float16)x[2 * q + 1] : (_Float16)0.0f;
+    if constexpr (!U16) {
+        if constexpr (C == 1) {
+            h[0] = half2_t{(_Float16)(uint16_t)w, (_Float16)0.0f};
+        } else {
+            h[0] = bytes_to_half2((uint32_t)w, 0x04010400u);  // bytes 0, 1
+            if constexpr (C > 2) h[1] = bytes_to_half2((uint32_t)w, 0x04030402u);  // 2, 3
+        }
+    } else {
+        if constexpr (C == 1) {
+            h[0] = half2_t{(_Float16)(uint16_t)w, (_Float16)0.0f};
+        } else if constexpr (C == 2) {
+            const uint32_t u = (uint32_t)w;
+            h[0] = half2_t{(_Float16)(uint16_t)u, (_Float16)(uint16_t)(u >> 16)};
+        } else {
+            h[0] = half2_t{(_Float16)(uint16_t)w.x, (_Float16)(uint16_t)(w.x >> 16)};
+            h[1] = half2_t{(_Float16)(uint16_t)w.y, (_Float16)(uint16_t)(w.y >> 16)};
+        }
     }
 }
 
@@ -180,7 +201,30 @@ __device__ __forceinline__ half2_t lerp(half2_t a, half2_t b, half2_t f) {
 template <int C, bool U16, bool F16, typename T>
 __device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
     const float fx = t.fx, fy = t.fy, fz = t.fz;
-    if constexpr (!F16) {
+    if constexpr (!F16 && C >= 3) {
+        // Many channels: the eight trilinear weights once, then one 8-term
+        // weighted sum per channel.
+        const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+        const float w00 = gx * gy, w10 = fx * gy, w01 = gx * fy, w11 = fx * fy;
+        const float wt[8] = {w00 * gz, w10 * gz, w01 * gz, w11 * gz,
+                             w00 * fz, w10 * fz, w01 * fz, w11 * fz};
+        float v[8][C];
+        unpack_f32<C, U16>(t.w000, v[0]);
+        unpack_f32<C, U16>(t.w100, v[1]);
+        unpack_f32<C, U16>(t.w010, v[2]);
+        unpack_f32<C, U16>(t.w110, v[3]);
+        unpack_f32<C, U16>(t.w001, v[4]);
+        unpack_f32<C, U16>(t.w101, v[5]);
+        unpack_f32<C, U16>(t.w011, v[6]);
+        unpack_f32<C, U16>(t.w111, v[7]);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            float acc = wt[0] * v[0][c];
+#pragma unroll
+            for (int q = 1; q < 8; ++q) acc = fmaf(wt[q], v[q][c], acc);
+            x[c] = acc;
+        }
+    } else if constexpr (!F16) {
         float a000[C], a100[C], a010[C], a110[C], a001[C], a101[C], a011[C], a111[C];
         unpack_f32<C, U16>(t.w000, a000);
         unpack_f32<C, U16>(t.w100, a100);
@@ -211,9 +255,8 @@ __device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
         unpack_f16<C, U16>(t.w101, a101);
         unpack_f16<C, U16>(t.w011, a011);
         unpack_f16<C, U16>(t.w111, a111);
-        half2_t hx = {(_Float16)fx, (_Float16)fx};
-        half2_t hy = {(_Float16)fy, (_Float16)fy};
-        half2_t hz = {(_Float16)fz, (_Float16)fz};
+        const _Float16 ex = (_Float16)fx, ey = (_Float16)fy, ez = (_Float16)fz;
+        const half2_t hx = {ex, ex}, hy = {ey, ey}, hz = {ez, ez};
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
             half2_t c00 = lerp(a000[q], a100[q], hx);
