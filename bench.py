@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--tile", default="", help="wave_w,wave_h,waves_x,waves_y of vr_render")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-gb", type=float, default=150.0)
-    ap.add_argument("--serve-rates", default="25,50,100,200,400")
+    ap.add_argument("--serve-rates", default="25,100,400,1000,1600,2400")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "

@@ -341,7 +341,7 @@ vr_status vr_init(int32_t device, uint64_t mem_budget_bytes, vr_ctx** out) {
         mem_budget_bytes = free_b > reserve ? free_b - reserve : free_b / 2;
     }
     ctx->budget = mem_budget_bytes;
-    ctx->batch_grid = batch_grid_blocks(device);
+    batch_grid_blocks(device, ctx->batch_grid);
     *out = ctx;
     return ok();
 }

@@ -42,20 +42,21 @@ static void free_tables(BatchSlot* s) {
     s->capacity = 0;
 }
 
-static void drop_graph(BatchSlot* s) {
-    if (s->exec) (void)hipGraphExecDestroy(s->exec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
-    s->exec = nullptr;
-    s->graph = nullptr;
+static void drop_graphs(BatchSlot* s) {
+    for (auto& kv : s->graphs) {
+        if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
+        if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
+    }
+    s->graphs.clear();
 }
 
 void batch_slot_destroy(BatchSlot* s) {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
-    drop_graph(s);
+    drop_graphs(s);
     free_tables(s);
     if (s->d_work) (void)hipFree(s->d_work);
-    if (s->d_counter) (void)hipFree(s->d_counter);
+    if (s->d_counters) (void)hipFree(s->d_counters);
     if (s->h_work) (void)hipHostFree(s->h_work);
     if (s->staged) (void)hipEventDestroy(s->staged);
     if (s->capture) (void)hipStreamDestroy(s->capture);
@@ -66,7 +67,7 @@ static vr_status grow(BatchSlot* s, int cap) {
     // Earlier launches on this stream may still read the old tables.
     hipError_t e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    drop_graph(s);
+    drop_graphs(s);  // the captured launches hold the old table addresses
     free_tables(s);
     if ((e = hipMalloc(&s->d_reqs, sizeof(ReqParams) * (size_t)cap)) != hipSuccess ||
         (e = hipMalloc(&s->d_prefix, sizeof(int32_t) * (size_t)cap)) != hipSuccess ||
@@ -85,12 +86,11 @@ static vr_status grow(BatchSlot* s, int cap) {
 BatchSlot* batch_slot_create(vr_ctx* ctx, hipStream_t stream, vr_status* st) {
     BatchSlot* s = new BatchSlot();
     s->stream = stream;
-    s->grid = ctx->batch_grid;
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&s->staged, hipEventDisableTiming)) != hipSuccess ||
         (e = hipMalloc(&s->d_work, sizeof(BatchWork))) != hipSuccess ||
-        (e = hipMalloc(&s->d_counter, 256)) != hipSuccess ||
+        (e = hipMalloc(&s->d_counters, 256)) != hipSuccess ||
         (e = hipHostMalloc(&s->h_work, sizeof(BatchWork), hipHostMallocDefault)) != hipSuccess) {
         *st = hip_fail(e, "batch workspace");
         batch_slot_destroy(s);
@@ -116,19 +116,31 @@ BatchSlot* batch_slot_for(vr_ctx* ctx, hipStream_t stream, vr_status* st) {
     return s;
 }
 
-static vr_status capture(BatchSlot* s) {
-    drop_graph(s);
+static vr_status graph_for(vr_ctx* ctx, BatchSlot* s, uint32_t mask, hipGraphExec_t* out) {
+    auto it = s->graphs.find(mask);
+    if (it != s->graphs.end()) {
+        *out = it->second.second;
+        return VR_OK;
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
     hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le = launch_batch(s->d_work, s->d_counter, s->grid, s->capture);
-    e = hipStreamEndCapture(s->capture, &s->graph);
-    if (le != hipSuccess) return hip_fail(le, "batch launch capture");
+    hipError_t le = launch_batch(s->d_work, s->d_reqs, s->d_prefix, s->d_counters, mask,
+                                 ctx->batch_grid, s->capture);
+    e = hipStreamEndCapture(s->capture, &graph);
+    if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "batch launch capture");
+    }
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    e = hipGraphInstantiate(&s->exec, s->graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        drop_graph(s);
+        (void)hipGraphDestroy(graph);
         return hip_fail(e, "hipGraphInstantiate");
     }
+    s->graphs[mask] = {graph, exec};
+    *out = exec;
     return VR_OK;
 }
 
@@ -245,12 +257,16 @@ vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int 
 static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
                               const TileShape& ts) {
     hipError_t e;
-    // Most expensive first.
+    // Group by data variant (one persistent kernel each), most expensive
+    // request first within a group.
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::vector<double> cost(n);
     for (int q = 0; q < n; ++q) cost[q] = request_cost(params[q]);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (params[a].variant != params[b].variant) return params[a].variant < params[b].variant;
+        return cost[a] > cost[b];
+    });
 
     if (n > s->capacity) {
         int cap = s->capacity;
@@ -265,22 +281,28 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
         s->staged_pending = false;
     }
     const int bw = ts.wave_w * ts.waves_x, bh = ts.wave_h * ts.waves_y;
+    BatchWork* w = s->h_work;
+    std::memset(w->group, 0, sizeof w->group);
+    uint32_t mask = 0;
     int64_t items = 0;
     for (int q = 0; q < n; ++q) {
         const ReqParams& P = params[order[q]];
+        BatchGroup& g = w->group[P.variant];
+        if (g.n_req == 0) {
+            g.first = q;
+            items = 0;
+        }
         s->h_reqs[q] = P;
         s->h_prefix[q] = (int32_t)items;
         const int64_t tx = (P.width + bw - 1) / bw, ty = (P.height + bh - 1) / bh;
         items += tx * ty * P.eyes;
+        if (items > 0x7fffffff) return fail(VR_ERR_INVALID_ARG, "batch has too many tiles");
+        g.n_req += 1;
+        g.n_items = (int32_t)items;
+        if (items > 0) mask |= 1u << P.variant;
     }
-    if (items == 0) return VR_OK;
-    if (items > 0x7fffffff) return fail(VR_ERR_INVALID_ARG, "batch has too many tiles");
-    BatchWork* w = s->h_work;
-    w->reqs = s->d_reqs;
-    w->prefix = s->d_prefix;
-    w->counter = s->d_counter;
-    w->n_req = n;
-    w->n_items = (int32_t)items;
+    if (mask == 0) return VR_OK;
+    w->counters = s->d_counters;
     w->tile = ts;
     if ((e = hipMemcpyAsync(s->d_reqs, s->h_reqs, sizeof(ReqParams) * (size_t)n,
                             hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
@@ -293,15 +315,14 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
     s->staged_pending = true;
 
     if (ctx->use_graphs) {
-        if (!s->exec || s->grid != ctx->batch_grid) {
-            s->grid = ctx->batch_grid;
-            vr_status st = capture(s);
-            if (st != VR_OK) return st;
-        }
-        if ((e = hipGraphLaunch(s->exec, s->stream)) != hipSuccess)
+        hipGraphExec_t exec = nullptr;
+        vr_status st = graph_for(ctx, s, mask, &exec);
+        if (st != VR_OK) return st;
+        if ((e = hipGraphLaunch(exec, s->stream)) != hipSuccess)
             return hip_fail(e, "hipGraphLaunch");
     } else {
-        if ((e = launch_batch(s->d_work, s->d_counter, ctx->batch_grid, s->stream)) != hipSuccess)
+        if ((e = launch_batch(s->d_work, s->d_reqs, s->d_prefix, s->d_counters, mask,
+                              ctx->batch_grid, s->stream)) != hipSuccess)
             return hip_fail(e, "batch launch");
     }
     return VR_OK;

@@ -6,24 +6,38 @@
 
 namespace vr {
 
-// Device-resident description of one batched launch.  The host rewrites the
-// pointed-to arrays before each launch; the pointers themselves stay fixed so
-// a captured graph can be replayed.
-struct BatchWork {
-    const ReqParams* reqs;  // [n_req], most expensive request first
-    const int32_t* prefix;  // [n_req] first work item of each request
-    int32_t* counter;       // next unclaimed work item
+// Requests of one data variant within a batch: reqs[first .. first + n_req)
+// (most expensive first), their work items numbered from 0.
+struct BatchGroup {
+    int32_t first;
     int32_t n_req;
     int32_t n_items;
+    int32_t pad_;
+};
+
+// Device-resident description of one batched launch.  With it the kernels
+// take the request descriptors (grouped by variant) and each request's first
+// work item within its group.  The host rewrites all three before each
+// launch; their addresses stay fixed until the tables grow, so a captured
+// graph can be replayed.  One persistent kernel per data variant present
+// works through that variant's group, claiming items from its own counter.
+struct BatchWork {
+    int32_t* counters;      // [kVariants] next unclaimed item of each group
     TileShape tile;
+    BatchGroup group[kVariants];
 };
 
 hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
                            const void* src, uint8_t* dst, hipStream_t s);
 hipError_t launch_render(const ReqParams& P, const TileShape& ts, hipStream_t s);
-hipError_t launch_batch(const BatchWork* dev_work, int* dev_counter, int grid, hipStream_t s);
+// Launch the persistent kernels of the variants set in `mask` (after
+// zeroing the counters), `grid[v]` blocks for variant v.
+hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
+                        const int32_t* dev_prefix, int* dev_counters, uint32_t mask,
+                        const int* grid, hipStream_t s);
 hipError_t launch_debug_sample(const ReqParams& P, const float* pts, int n, float* out,
                                hipStream_t s);
-int batch_grid_blocks(int device);
+// Persistent blocks per variant: resident blocks per CU times the CUs.
+void batch_grid_blocks(int device, int* grid /* [kVariants] */);
 
 }  // namespace vr

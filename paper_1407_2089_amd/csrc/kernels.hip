@@ -115,34 +115,40 @@ __device__ __forceinline__ void batch_tile(const ReqParams& P, const TileShape& 
     render_pixel<V>(P, eye, valid ? px : 0, valid ? py : 0, valid);
 }
 
-__global__ __launch_bounds__(kBlockThreads) void batch_kernel(const BatchWork* __restrict__ work) {
+template <int V>
+__global__ __launch_bounds__(kBlockThreads) void batch_kernel(
+    const BatchWork* __restrict__ work, const ReqParams* __restrict__ reqs,
+    const int32_t* __restrict__ prefix) {
     __shared__ int s_item;
-    const int n_req = work->n_req;
-    const int n_items = work->n_items;
+    const BatchGroup grp = work->group[V];
     const TileShape ts = work->tile;
+    int32_t* counter = work->counters + V;
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(work->counter, 1);
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int item = s_item;
+        // The item is the same for the whole block: make that explicit so the
+        // request's descriptor (read-only, not aliased: restrict arguments) is
+        // read with scalar loads into scalar registers.
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
-        if (item >= n_items) break;
-        const int q = find_req(work->prefix, n_req, item);
-        const int local = item - work->prefix[q];
-        const ReqParams& P = work->reqs[q];
-        switch (P.variant) {
-#define VR_CASE(v) case v: batch_tile<v>(P, ts, local); break;
-            VR_CASE(0) VR_CASE(1) VR_CASE(2) VR_CASE(3) VR_CASE(4) VR_CASE(5) VR_CASE(6)
-            VR_CASE(7) VR_CASE(8) VR_CASE(9) VR_CASE(10) VR_CASE(11) VR_CASE(12)
-            VR_CASE(13) VR_CASE(14) VR_CASE(15)
-#undef VR_CASE
-            default: break;
-        }
+        if (item >= grp.n_items) break;
+        const int q = __builtin_amdgcn_readfirstlane(
+            grp.first + find_req(prefix + grp.first, grp.n_req, item));
+        const int local = __builtin_amdgcn_readfirstlane(item - prefix[q]);
+        batch_tile<V>(reqs[q], ts, local);
     }
 }
 
-__global__ void reset_counter_kernel(int* counter) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+__global__ void reset_counters_kernel(int* counters) {
+    if (blockIdx.x == 0 && threadIdx.x < kVariants) counters[threadIdx.x] = 0;
 }
+
+typedef void (*batch_fn)(const BatchWork*, const ReqParams*, const int32_t*);
+static const batch_fn kBatch[kVariants] = {
+    batch_kernel<0>, batch_kernel<1>, batch_kernel<2>, batch_kernel<3>,
+    batch_kernel<4>, batch_kernel<5>, batch_kernel<6>, batch_kernel<7>,
+    batch_kernel<8>, batch_kernel<9>, batch_kernel<10>, batch_kernel<11>,
+    batch_kernel<12>, batch_kernel<13>, batch_kernel<14>, batch_kernel<15>};
 
 // ------------------------------------------------------------ test hook
 template <int V>
@@ -201,12 +207,19 @@ hipError_t launch_render(const ReqParams& P, const TileShape& ts, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_batch(const BatchWork* dev_work, int* dev_counter, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, dev_counter);
+hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
+                        const int32_t* dev_prefix, int* dev_counters, uint32_t mask,
+                        const int* grid, hipStream_t s) {
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, dev_counters);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kBlockThreads), 0, s, dev_work);
-    return hipGetLastError();
+    for (int v = 0; v < kVariants; ++v) {
+        if (!(mask & (1u << v))) continue;
+        hipLaunchKernelGGL(kBatch[v], dim3(grid[v]), dim3(kBlockThreads), 0, s, dev_work,
+                           dev_reqs, dev_prefix);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 typedef void (*debug_fn)(ReqParams, const float*, int, float*);
@@ -227,17 +240,19 @@ hipError_t launch_debug_sample(const ReqParams& P, const float* pts, int n, floa
     return hipGetLastError();
 }
 
-int batch_grid_blocks(int device) {
+void batch_grid_blocks(int device, int* grid) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         cus <= 0)
         cus = 256;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel, kBlockThreads, 0) !=
-            hipSuccess ||
-        per_cu <= 0)
-        per_cu = 1;
-    return cus * per_cu;
+    for (int v = 0; v < kVariants; ++v) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kBatch[v], kBlockThreads, 0) !=
+                hipSuccess ||
+            per_cu <= 0)
+            per_cu = 1;
+        grid[v] = cus * per_cu;
+    }
 }
 
 }  // namespace vr

@@ -26,17 +26,16 @@ struct BatchSlot {
     int capacity = 0;               // requests the tables can hold
     ReqParams* d_reqs = nullptr;
     int32_t* d_prefix = nullptr;
-    int32_t* d_counter = nullptr;
+    int32_t* d_counters = nullptr;  // [kVariants]
     BatchWork* d_work = nullptr;
     ReqParams* h_reqs = nullptr;    // pinned
     int32_t* h_prefix = nullptr;    // pinned
     BatchWork* h_work = nullptr;    // pinned
     hipEvent_t staged = nullptr;    // staging copies of the last batch done
     bool staged_pending = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    int grid = 0;
-    TileShape tile{};
+    // Captured launches, one per set of variants present in a batch (they
+    // hold the table addresses: dropped when the tables grow).
+    std::map<uint32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
 // Sets the calling thread's error message and returns `st`.
@@ -62,7 +61,7 @@ struct vr_ctx {
     uint64_t budget = 0;
     std::atomic<uint64_t> used{0};
     std::atomic<int> volumes{0};
-    int batch_grid = 0;        // persistent blocks for a batched launch
+    int batch_grid[vr::kVariants] = {};  // persistent blocks per variant
     std::mutex mu;
     // Batched-launch workspaces keyed by stream (batch.cpp).
     std::map<hipStream_t, vr::BatchSlot*> batch_slots;

@@ -299,9 +299,10 @@ class Server {
             for (bool b : busy_) any_busy = any_busy || b;
             if (changed) continue;
             if (any_busy) {
-                // Poll device completions at a fine grain without holding the lock.
+                // Poll device completions at a fine grain without holding the
+                // lock (a timed sleep would round up to tens of microseconds).
                 lk.unlock();
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                std::this_thread::yield();
                 lk.lock();
             } else {
                 cv_.wait_for(lk, std::chrono::milliseconds(5));
