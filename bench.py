@@ -20,6 +20,41 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "render_2ch_u16_realistic_stereo_counters.txt")
+
+
+def render_kernel_hash():
+    """sha256 of the render kernel's source (march.h, params.h and the plain
+    render kernel's part of kernels.hip)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1407_2089_amd", "csrc")
+    for f in ("march.h", "params.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(csrc, "kernels.hip")) as fh:
+        k = fh.read()
+    a = k.index("// ------------------------------------------------------------ plain render")
+    b = k.index("// ------------------------------------------------------- persistent batch")
+    h.update(k[a:b].encode())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM-side bytes per launch of the headline kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain
+    copy's readings), or None once the kernel's source has changed since."""
+    try:
+        with open(COUNTERS) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    import re
+    t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    h = re.search(r"sha256 \(.*\):\s*([0-9a-f]{64})", text)
+    if not t or not h or h.group(1) != render_kernel_hash():
+        return None
+    return int(t.group(1))
 
 
 def log(msg):
@@ -68,7 +103,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--mode", choices=["render", "copy"], default="render",
                     help="copy: a plain 1 GiB device copy, to calibrate HBM byte counters")
-    ap.add_argument("--workload", choices=["realistic", "batch", "serve", "precision"],
+    ap.add_argument("--workload", choices=["realistic", "batch", "serve", "precision", "layout"],
                     default="realistic",
                     help="realistic (default): one stereo 1920x1080 frame per step; batch: 64 "
                          "mixed requests, batched vs plain launches; serve: Poisson arrivals "
@@ -109,6 +144,8 @@ def main():
             res = workloads.batching(ctx)
         elif args.workload == "precision":
             res = workloads.precision(ctx)
+        elif args.workload == "layout":
+            res = workloads.layout_sweep(ctx)
         else:
             rates = tuple(int(r) for r in args.serve_rates.split(","))
             res = workloads.serving(ctx, total_gb=args.serve_gb, seconds=args.serve_seconds,
@@ -166,6 +203,8 @@ def main():
 
     bytes_per_sample = 8 * c * 2
     alg_bytes = samples_per_step * bytes_per_sample
+    default_layout = args.precision == "fp32" and brick == (0, 0, 0) and not args.tile
+    traffic = measured_traffic() if default_layout else None
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     result = {
         "metric": "ray-samples/s",
@@ -187,9 +226,11 @@ def main():
                    "samples_per_step": samples_per_step},
         "stereo_fps": args.steps / wall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "render_kernel<2ch,u16,fp32>", "kernel_ms": kernel_ms,
-                     "bytes_per_launch": alg_bytes},
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes/launch (L2-to-fabric FETCH_SIZE + WRITE_SIZE, "
+                                     "copy-calibrated)",
+                     "kernel": f"render_kernel<2ch,u16,{args.precision}>",
+                     "kernel_ms": kernel_ms, "bytes_per_launch": alg_bytes},
     }
     vol.destroy()
     ctx.close()

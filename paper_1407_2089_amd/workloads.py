@@ -200,6 +200,47 @@ def precision(ctx, frames=48, seed=3, reps=2):
     return res
 
 
+# ------------------------------------------------------------------- layout
+
+def layout_sweep(ctx, reps=30):
+    """Render time of one stereo 1920x1080 pair of a 512x512x64 frame for
+    each brick shape and voxel-word size (1-channel u8: 1 B; 2-channel
+    u16-12 and 4-channel u8: 4 B; 4-channel u16: 8 B), for a view entering
+    through the top face and a grazing view entering through the sides."""
+    import torch
+    W, H = 1920, 1080
+    dims = (512, 512, 64)
+    views = {"top": synth.orbit_camera(dims, 30.0, 50.0, 45.0),
+             "side": synth.orbit_camera(dims, 75.0, 10.0, 45.0)}
+    bricks = [(4, 4, 4), (8, 8, 8), (16, 16, 16), (4, 8, 8), (8, 4, 8), (8, 8, 4), (8, 16, 8),
+              (16, 8, 8), (16, 16, 8), (32, 8, 8), (0, 0, 0)]
+    out = torch.empty((2, H, W, 4), dtype=torch.float32, device="cuda")
+    rows = []
+    for ch, bits in ((1, 8), (2, 12), (4, 8), (4, 16)):
+        frame = synth.DeviceSeries(dims, ch, bits, 77).frame(0)
+        for b in bricks:
+            vol = Volume(ctx, dims, ch, 1, VR_U8 if bits == 8 else VR_U16, bits, brick=b)
+            vol.upload(0, frame)
+            for c, tf in enumerate(default_tfs(ch)):
+                vol.set_transfer(c, tf)
+            for name, cam in views.items():
+                req = make_request(vol.ptr, 0, cam, W, H, True, 1.0, 0.99, out)
+                for _ in range(5):
+                    vr_render(ctx.ptr, req)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    vr_render(ctx.ptr, req)
+                e1.record()
+                torch.cuda.synchronize()
+                rows.append({"channels": ch, "bits": bits, "brick": list(b), "view": name,
+                             "ms": e0.elapsed_time(e1) / reps, "storage_bytes": vol.bytes})
+                log(f"  ch {ch} bits {bits} brick {b} {name}: {rows[-1]['ms']:.4f} ms")
+            vol.destroy()
+    return {"workload": "layout sweep: 512x512x64, stereo 1920x1080, step 1, alpha 0.99",
+            "rows": rows}
+
+
 # ------------------------------------------------------------------- serving
 
 class _Pool:
@@ -317,6 +358,9 @@ def serving(ctx, total_gb=150.0, seconds=10.0, warm=1.0,
                     lat.append((info.t_done_ns - sched) * 1e-9)
                 if idx in check_ids:
                     keep[idx] = out.clone()
+                    # the copy runs on torch's stream: let it finish before the
+                    # buffer can be handed to a later request on a serving stream
+                    torch.cuda.current_stream().synchronize()
                 pool.give(w, h, out)
                 vr_release(ctx.ptr, tk)
                 pending.pop(0)
