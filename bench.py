@@ -61,8 +61,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scene, target_s=12.0):
-    """Time the FP64 oracle on seeded random pixels of both eyes."""
+def cpu_baseline(scene, target_s=10.0):
+    """Time the FP64 oracle on the host: the whole stereo pair, repeated until
+    about target_s seconds have passed, on every host thread; plus one
+    thread on 2^16 seeded pixels per eye."""
     import numpy as np
 
     import oracle
@@ -72,26 +74,65 @@ def cpu_baseline(scene, target_s=12.0):
     c = scene.cam
     cam = oracle.Camera(c.projection, c.center, c.forward, c.up, c.fov_y, c.ortho_height,
                         c.eye_separation, c.convergence)
-    rng = np.random.default_rng(12345)
-    npx = scene.width * scene.height
 
-    def run(n):
-        pix = rng.choice(npx, size=min(n, npx), replace=False)
-        t0 = time.perf_counter()
+    def run(pixels, threads):
         s = 0
         for eye in (-1, 1):
             r = oracle.render(ov, tfs, cam, scene.width, scene.height, eye, scene.step,
-                              scene.term_alpha, pixels=pix, nthreads=cores)
+                              scene.term_alpha, pixels=pixels, nthreads=threads)
             s += int(r["samples"].sum())
-        return s, time.perf_counter() - t0, 2 * len(pix)
+        return s
 
-    s, dt, rays = run(20000)
-    n = int(20000 * max(1.0, target_s / max(dt, 1e-3)))
-    if n > 20000:
-        s, dt, rays = run(n)
-    return {"value": s / dt, "unit": "ray-samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"{rays} seeded random pixels of the same stereo pair "
-                      f"({rays // 2} per eye), FP64, {dt:.1f} s"}
+    t0 = time.perf_counter()
+    samples, reps = 0, 0
+    while reps == 0 or time.perf_counter() - t0 < target_s:
+        samples += run(None, cores)
+        reps += 1
+    dt = time.perf_counter() - t0
+    rng = np.random.default_rng(12345)
+    pix = rng.choice(scene.width * scene.height, size=1 << 16, replace=False)
+    t1 = time.perf_counter()
+    s1 = run(pix, 1)
+    dt1 = time.perf_counter() - t1
+    return {"value": samples / dt, "unit": "ray-samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole stereo pair ({2 * scene.width * scene.height} rays) x {reps}, "
+                      f"FP64, {dt:.1f} s on {cores} threads",
+            "value_1thread": s1 / dt1,
+            "sample_1thread": f"2 x 65536 seeded pixels, {dt1:.1f} s"}
+
+
+def tiny(args):
+    """Launch-bound small case: 1-channel u8 64x64x32, ortho mono 256x256."""
+    import numpy as np
+    import torch
+
+    import paper_1407_2089_amd as vr
+    from paper_1407_2089_amd import synth
+    sc = synth.tiny_scene()
+    ctx = vr.Context(0)
+    vol = vr.Volume(ctx, (64, 64, 32), 1, 1, vr.VR_U8, 8)
+    vol.upload(0, torch.from_numpy(sc.volume).cuda())
+    vol.set_transfer(0, sc.tfs[0])
+    out = torch.empty((1, 256, 256, 4), dtype=torch.float32, device="cuda")
+    smp = torch.empty((1, 256, 256), dtype=torch.int32, device="cuda")
+    req = vr.make_request(vol.ptr, 0, sc.cam, 256, 256, False, 0.5, 1.0, out, out_samples=smp)
+    vr.vr_render(ctx.ptr, req)
+    torch.cuda.synchronize()
+    samples = int(smp.sum().item())
+    ms = []
+    for _ in range(50 + 5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        vr.vr_render(ctx.ptr, req)
+        b.record()
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    med = float(np.median(ms[5:]))
+    vol.destroy()
+    ctx.close()
+    return {"workload": "tiny: 1ch u8 64x64x32 blobs, ortho mono 256x256, step 0.5",
+            "samples": samples, "median_ms": med, "samples_per_s": samples / (med * 1e-3),
+            "eff_GBps": samples * 8 / (med * 1e-3) / 1e9}
 
 
 def main():
@@ -103,7 +144,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--mode", choices=["render", "copy"], default="render",
                     help="copy: a plain 1 GiB device copy, to calibrate HBM byte counters")
-    ap.add_argument("--workload", choices=["realistic", "batch", "serve", "precision", "layout"],
+    ap.add_argument("--workload", choices=["realistic", "tiny", "batch", "serve", "precision",
+                                           "layout"],
                     default="realistic",
                     help="realistic (default): one stereo 1920x1080 frame per step; batch: 64 "
                          "mixed requests, batched vs plain launches; serve: Poisson arrivals "
@@ -140,6 +182,10 @@ def main():
     if args.workload != "realistic":
         from paper_1407_2089_amd import workloads
         ctx = vr.Context(0)
+        if args.workload == "tiny":
+            ctx.close()
+            print(json.dumps(dict(tiny(args), n_gpus=1, data="synthetic")), flush=True)
+            return
         if args.workload == "batch":
             res = workloads.batching(ctx)
         elif args.workload == "precision":

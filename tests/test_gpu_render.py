@@ -244,3 +244,78 @@ def test_brick_shape_does_not_change_the_image(ctx, realistic, brick):
     a, sa = gpu.render(ctx, sc, brick=(0, 0, 0))
     b, sb = gpu.render(ctx, sc, brick=brick)
     assert np.array_equal(a, b) and np.array_equal(sa, sb)
+
+
+# ------------------------------------------------ spacing, frames, clamping
+
+def test_anisotropic_spacing_and_origin(ctx):
+    # confocal stacks: 0.8 um pixels, 1 um z steps (Methods, acquisition)
+    nx, ny, nz = 48, 40, 20
+    vol = synth.cells_and_vessels((nx, ny, nz), 2, 12, 31, n_cells=5, n_tubes=2)
+    spacing, origin = (0.8, 0.8, 1.0), (-10.0, 5.0, 3.0)
+    ext = np.array([nx * 0.8, ny * 0.8, nz * 1.0])
+    centre = np.array(origin) + ext / 2
+    eye = centre + np.array([30.0, -55.0, 40.0])
+    fwd = centre - eye
+    dist = float(np.linalg.norm(fwd))
+    cam = Cam("perspective", tuple(eye), tuple(fwd / dist), (0, 0, 1), math.radians(35), 1.0,
+              dist / 30, dist)
+    tfs = [TF(0.05, 0.6, 0.2, 1.2, (0, 1, 0)), TF(0.08, 0.7, -0.3, 0.9, (1, 0, 0))]
+    sc = Scene("aniso", vol, 12, tfs, cam, 96, 72, True, 0.6, 0.99, spacing=spacing,
+               origin=origin)
+    rgba, smp = gpu.render(ctx, sc)
+    assert rgba[..., 3].max() > 0.2
+    gpu.compare(rgba, smp, orc.render_all(sc), TOL32)
+
+
+def test_time_series_frames_are_independent(ctx):
+    import torch
+    nx, ny, nz = 30, 26, 14
+    frames = [scenes.random_volume(40 + t, (2, nz, ny, nx), np.uint8) for t in range(3)]
+    cam = synth.orbit_camera((nx, ny, nz), 40.0, 30.0, 40.0)
+    tfs = [TF(0.2, 0.9, 0.0, 0.5, (0, 1, 0)), TF(0.3, 0.8, 0.5, 0.7, (1, 0, 1))]
+    v = vr.Volume(ctx, (nx, ny, nz), 2, 3, vr.VR_U8, 8)
+    try:
+        for t in (2, 0, 1):  # any upload order
+            v.upload(t, gpu.to_device(frames[t]))
+        for c, tf in enumerate(tfs):
+            v.set_transfer(c, tf)
+        for t in range(3):
+            sc = Scene("series", frames[t], 8, tfs, cam, 40, 30, True, 0.8, 0.98)
+            out, smp = gpu.alloc_out(sc)
+            vr.vr_render(ctx.ptr, gpu.request_for(v, sc, out, smp, frame=t),
+                         torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            gpu.compare(out.cpu().numpy(), smp.cpu().numpy(), orc.render_all(sc), TOL32)
+    finally:
+        v.destroy()
+
+
+def test_values_above_the_bit_depth_are_clamped(ctx):
+    nx, ny, nz = 24, 20, 12
+    raw = scenes.random_volume(50, (1, nz, ny, nx), np.uint16, 65536)  # up to 65535
+    clamped = np.minimum(raw, 4095).astype(np.uint16)
+    cam = synth.orbit_camera((nx, ny, nz), 10.0, 60.0, 40.0)
+    sc = Scene("clamp", raw, 12, [TF(0.3, 0.9)], cam, 32, 24, True, 0.7, 1.0)
+    rgba, smp = gpu.render(ctx, sc)
+    ref = orc.render_all(Scene("clamp", clamped, 12, [TF(0.3, 0.9)], cam, 32, 24, True, 0.7,
+                               1.0))
+    gpu.compare(rgba, smp, ref, TOL32)
+
+
+def test_invisible_channel_and_oblique_orthographic_view(ctx):
+    nx, ny, nz = 36, 28, 18
+    vol = scenes.random_volume(60, (3, nz, ny, nx), np.uint8)
+    tfs = [TF(0.1, 0.8, 0.0, 0.4, (1, 0, 0)), TF(0.0, 1.0, 0.0, 2.0, (0, 1, 0), visible=False),
+           TF(0.2, 0.9, 0.6, 0.6, (0, 0, 1))]
+    c = ((nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2)
+    cam = Cam("ortho", c, (0.4, -0.5, 0.77), (0, 0, 1), ortho_height=40.0)
+    sc = Scene("ortho", vol, 8, tfs, cam, 50, 40, False, 0.5, 0.995, (0.1, 0.1, 0.1, 1.0))
+    rgba, smp = gpu.render(ctx, sc)
+    gpu.compare(rgba, smp, orc.render_all(sc), TOL32)
+    # the invisible channel contributes nothing: zeroing it changes no pixel
+    vol2 = vol.copy()
+    vol2[1] = 0
+    rgba2, _ = gpu.render(ctx, Scene("ortho", vol2, 8, tfs, cam, 50, 40, False, 0.5, 0.995,
+                                     (0.1, 0.1, 0.1, 1.0)))
+    assert np.array_equal(rgba, rgba2)

@@ -361,3 +361,38 @@ def test_p12_perspective_stereo_projects_points_correctly():
         ei = (sx + 1) * W / 2 - 0.5
         ej = (1 - sy) * H / 2 - 0.5
         assert abs(ci - ei) < 0.3 and abs(cj - ej) < 0.3, (eye, ci, ei, cj, ej)
+
+
+# ------------------------------------------------------- P13 world scale
+
+def test_p13_uniform_world_scale_invariance():
+    # Scaling voxel spacing, origin, camera and step by one factor s leaves the
+    # image unchanged (pins the spacing and origin handling).
+    nx, ny, nz = 20, 16, 12
+    V = scenes.random_volume(13, (2, nz, ny, nx), np.uint8)
+    tfs = [TF(0.1, 0.9, 0.3, 0.8, (0.9, 0.2, 0.4)), TF(0.2, 0.7, -0.2, 1.1, (0.1, 0.8, 0.5))]
+    base_cam = scenes.mirror_camera(nx, ny, nz, sep=2.0)
+    o = (1.5, -2.0, 0.5)
+    a = orc.render(Scene("s1", V, 8, tfs, base_cam, 24, 18, True, 0.7, 0.97, origin=o), -1)
+    s = 2.5
+    # the map X -> s X sends voxel positions o + i to s o + i s and the camera
+    # to s c; directions, fov and the order of samples are unchanged
+    cam = Cam("perspective", tuple(s * np.array(base_cam.center)), base_cam.forward,
+              base_cam.up, base_cam.fov_y, 1.0, s * base_cam.eye_separation,
+              s * base_cam.convergence)
+    b = orc.render(Scene("s2", V, 8, tfs, cam, 24, 18, True, 0.7 * s, 0.97,
+                         spacing=(s, s, s), origin=tuple(s * np.array(o))), -1)
+    assert a["rgba"][..., 3].max() > 0.2
+    np.testing.assert_allclose(a["rgba"], b["rgba"], rtol=0, atol=1e-11)
+    assert np.array_equal(a["samples"], b["samples"])
+
+
+def test_p13_anisotropic_sample_count_closed_form():
+    # Ortho ray along z with z spacing 2.5 and step 1: the extended box spans
+    # (nz + 1) * 2.5 world units, so ceil((nz + 1) * 2.5 - 1/2) samples.
+    nz = 9
+    V = np.full((1, nz, 6, 6), 10, np.uint8)
+    cam = Cam("ortho", (2.5, 2.5, -3.0), (0, 0, 1), (0, -1, 0), ortho_height=2.0)
+    r = orc.render(Scene("az", V, 8, [TF(0.5, 1.0)], cam, 3, 3, False, 1.0, 1.0,
+                         spacing=(1.0, 1.0, 2.5)))
+    assert (r["nominal"] == math.ceil((nz + 1) * 2.5 - 0.5)).all()
