@@ -16,7 +16,7 @@
 
 namespace vr {
 
-class Server;
+class Scheduler;
 
 // Workspace of batched launches on one stream: device tables that a captured
 // graph reads, their pinned host staging copies, and the instantiated graph.
@@ -73,7 +73,7 @@ struct vr_ctx {
     vr::TileShape batch_tile{8, 8, 2, 2};
     vr::TileShape plain_tile{8, 8, 2, 2};  // tile of vr_render launches
     std::map<uint64_t, vr::TileShape> tuned;
-    vr::Server* server = nullptr;   // created by the first vr_submit (server.cpp)
+    vr::Scheduler* server = nullptr;  // created by the first vr_submit (server.cpp)
     std::mutex server_mu;
 };
 
