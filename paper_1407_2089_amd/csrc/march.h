@@ -382,42 +382,17 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         return fetch<Word>(P.g, S, fmaf(sj, d[0], pe[0]), fmaf(sj, d[1], pe[1]),
                            fmaf(sj, d[2], pe[2]));
     };
-#if VR_PIPELINE_DEPTH == 2
     if (n > 0) {
-        // Software pipeline, two samples deep: while sample j is interpolated
-        // and composited, the taps of samples j + 1 and j + 2 are in flight.
-        // Unrolled by three so the three tap sets rotate without copies.
-        // Every composite is predicated on the lane being live (a finished
-        // lane adds an exact zero), so the loop has a single exit, at the end
-        // of the three (a divergent loop: finished lanes are masked off and
-        // the wave leaves when none is live).  A live lane has taken every
-        // sample so far, so the wave-uniform iteration index j is its sample
-        // index.  At equal j a wave's sample points lie on a patch parallel to
-        // the face its rays entered through, which the brick layout serves
-        // with few cache lines.  A fetch past a lane's last sample reads a
-        // clamped, in-frame address and is unused.
-        bool live = true;
-        auto step_one = [&](const Taps<Word>& t) {
-            composite(t, live);
-            k += live ? 1 : 0;
-            live = live && k < n && A < tau;
-        };
-        int j = 0;
-        Taps<Word> a = fetch_at(0);
-        Taps<Word> b = fetch_at(1);
-        do {
-            const Taps<Word> c = fetch_at(j + 2);
-            step_one(a);
-            a = fetch_at(j + 3);
-            step_one(b);
-            b = fetch_at(j + 4);
-            step_one(c);
-            j += 3;
-        } while (live);
-    }
-
-#else
-    if (n > 0) {
+        // Software pipeline over pairs of samples: the taps of the next
+        // sample are always in flight while the current one is interpolated
+        // and composited.  The pair's second sample is composited with a
+        // zero weight on lanes that finished on its first, so the only exit
+        // is at the end of the pair (a divergent loop: finished lanes are
+        // masked off and the wave leaves when none is live).  At equal sample
+        // index a wave's sample points lie on a patch parallel to the face its
+        // rays entered through, which the brick layout serves with few cache
+        // lines.  A fetch past a lane's last sample reads a clamped, in-frame
+        // address and is unused.
         Taps<Word> a = fetch_at(k);
         bool live;
         do {
@@ -432,7 +407,6 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         } while (live);
     }
 
-#endif
     if (valid) {
         const float T = 1.0f - A;
         float4 o;
