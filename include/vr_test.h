@@ -33,6 +33,11 @@ vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h, int32_
 vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h, int32_t waves_x,
                              int32_t waves_y);
 
+/* Tile index that hardware block b of a plain vr_render launch of nblocks
+ * blocks renders, for b = 0 .. nblocks - 1, written to tiles[b] (host
+ * memory).  Pure host computation: a permutation of 0 .. nblocks - 1. */
+vr_status vr_test_block_map(int32_t nblocks, int32_t* tiles);
+
 #ifdef __cplusplus
 }
 #endif

@@ -102,6 +102,7 @@ def lib():
             "vr_test_fake_backend": [P, C.c_int32, C.c_double, C.c_int32, C.c_int32],
             "vr_test_batch_tile": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
             "vr_test_plain_tile": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
+            "vr_test_block_map": [C.c_int32, C.c_void_p],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -213,6 +214,14 @@ def vr_test_batch_tile(ctx, wave_w=0, wave_h=0, waves_x=0, waves_y=0):
 
 def vr_test_plain_tile(ctx, wave_w=0, wave_h=0, waves_x=0, waves_y=0):
     _check(lib().vr_test_plain_tile(ctx, wave_w, wave_h, waves_x, waves_y))
+
+
+def vr_test_block_map(nblocks: int):
+    """Tile rendered by each hardware block of a plain launch (host-only)."""
+    import numpy as np
+    out = np.zeros(max(nblocks, 1), np.int32)
+    _check(lib().vr_test_block_map(nblocks, out.ctypes.data))
+    return out[:nblocks]
 
 
 def vr_test_fake_backend(ctx, slots: int, ns_per_ray: float, fail_width: int = -1,

@@ -1,9 +1,10 @@
 // HIP kernels for gfx950: frame relayout into bricks, the plain per-request
 // render launch, the persistent batched render launch, and the sampling test
 // hook.  Host-side launchers at the bottom are the only entry points the
-// library's C++ code calls.
+// library's C++ code calls; the block-map test hook sits after them.
 #include <hip/hip_runtime.h>
 
+#include "../../include/vr_test.h"
 #include "kernels.h"
 #include "march.h"
 
@@ -256,3 +257,9 @@ void batch_grid_blocks(int device, int* grid) {
 }
 
 }  // namespace vr
+
+extern "C" vr_status vr_test_block_map(int32_t nblocks, int32_t* tiles) {
+    if (nblocks < 0 || (nblocks > 0 && !tiles)) return VR_ERR_INVALID_ARG;
+    for (int32_t b = 0; b < nblocks; ++b) tiles[b] = vr::xcd_remap(b, nblocks);
+    return VR_OK;
+}

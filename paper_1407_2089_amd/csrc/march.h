@@ -420,13 +420,20 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
     }
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs; remap so that each XCD
-// works on a contiguous run of tiles (neighbouring tiles share voxels in that
-// XCD's L2).  The tail beyond a multiple of 8 keeps its order.
-__device__ __forceinline__ int xcd_remap(int b, int nblocks) {
-    const int n8 = nblocks & ~7;
-    if (b >= n8) return b;
-    return (b & 7) * (n8 >> 3) + (b >> 3);
+// Blocks are dispatched round-robin over the 8 XCDs (block b to XCD b mod 8,
+// as its (b / 8)-th block).  Remap so that each XCD takes runs of kXcdRun
+// consecutive tiles (a 128-pixel-wide strip of one tile row at 16-pixel
+// tiles, whose rays share voxels in that XCD's L2), the runs dealt to the
+// XCDs in turn.  Handing each XCD one contiguous eighth of the image instead
+// leaves most XCDs idle: a volume seldom covers the whole image, so its
+// rays crowd into a few eighths.  The map is a bijection on [0, nblocks);
+// blocks past the last whole round of 8 runs keep their index.
+constexpr int kXcdRun = 8;
+__host__ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
+    const int whole = nblocks - nblocks % (8 * kXcdRun);
+    if (b >= whole) return b;
+    const int i = b >> 3;  // the block's rank on its XCD
+    return (((i / kXcdRun) << 3) + (b & 7)) * kXcdRun + i % kXcdRun;
 }
 
 }  // namespace vr

@@ -7,6 +7,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1407_2089_amd as vr
@@ -210,3 +211,25 @@ def test_null_arguments_do_not_crash():
     assert L.vr_poll(None, 0, None) == vr.VR_ERR_INVALID_ARG
     assert L.vr_release(None, 0) == vr.VR_ERR_INVALID_ARG
     assert vr.vr_last_error() != ""
+
+
+def test_block_map_is_a_permutation_that_deals_strips_to_xcds():
+    """Plain launches remap hardware block b (dispatched to XCD b mod 8) to a
+    tile: a bijection on every grid size, runs of 8 consecutive tiles per
+    XCD dealt in turn, and the tail past the last whole round unchanged."""
+    for n in list(range(0, 200)) + [16320, 16321, 16384 + 37, 65536 * 3 + 5]:
+        m = vr.vr_test_block_map(n)
+        assert np.array_equal(np.sort(m), np.arange(n)), n
+    m = vr.vr_test_block_map(130)
+    # Round 0: XCD x takes tiles 8x .. 8x + 7 as its blocks 0..7.
+    for xcd in range(8):
+        blocks = np.arange(xcd, 64 * 8, 8)[:8]
+        assert list(m[blocks]) == list(range(8 * xcd, 8 * xcd + 8))
+    assert list(m[128:]) == [128, 129]  # 130 = 2 * 64 + 2: tail keeps its order
+    # Work spread: every XCD holds tiles from every 64-tile round.
+    m = vr.vr_test_block_map(64 * 10)
+    for xcd in range(8):
+        rounds = set((m[np.arange(xcd, 640, 8)] // 64).tolist())
+        assert rounds == set(range(10))
+    with pytest.raises(vr.VrError):
+        vr.vr_test_block_map(-1)
