@@ -33,6 +33,12 @@ vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h, int32_
 vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h, int32_t waves_x,
                              int32_t waves_y);
 
+/* on = 0 makes vr_render composite transparent samples in full instead of
+ * leaving out their arithmetic (a sample whose taps are all below every
+ * channel's transfer-function floor has opacity exactly 0); the output bits
+ * are the same either way.  on = 1 (the default) restores the skip. */
+vr_status vr_test_clear_skip(vr_ctx* ctx, int32_t on);
+
 /* Tile index that hardware block b of a plain vr_render launch of nblocks
  * blocks renders, for b = 0 .. nblocks - 1, written to tiles[b] (host
  * memory).  Pure host computation: a permutation of 0 .. nblocks - 1. */

@@ -103,6 +103,7 @@ def lib():
             "vr_test_batch_tile": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
             "vr_test_plain_tile": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
             "vr_test_block_map": [C.c_int32, C.c_void_p],
+            "vr_test_clear_skip": [P, C.c_int32],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -214,6 +215,10 @@ def vr_test_batch_tile(ctx, wave_w=0, wave_h=0, waves_x=0, waves_y=0):
 
 def vr_test_plain_tile(ctx, wave_w=0, wave_h=0, waves_x=0, waves_y=0):
     _check(lib().vr_test_plain_tile(ctx, wave_w, wave_h, waves_x, waves_y))
+
+
+def vr_test_clear_skip(ctx, on: bool):
+    _check(lib().vr_test_clear_skip(ctx, int(bool(on))))
 
 
 def vr_test_block_map(nblocks: int):

@@ -202,6 +202,50 @@ static void normalise(double a[3]) {
     for (int q = 0; q < 3; ++q) a[q] /= n;
 }
 
+// Largest raw tap value t (0 .. full) such that every field value the kernel
+// can interpolate from taps that are all <= t gives u = 0 in its own FP32
+// arithmetic, or -1 if there is none.  The FP32 lerp tree and weighted sum
+// stay within a factor 1 + 2^-19 of the largest tap, the FP16 path (tap
+// rounding, then three half-precision lerps, each adding at most three
+// roundings of 2^-11 of the largest value) within 1 + 2^-7; the test allows
+// 1 + 2^-6.  u_pre(x) = fma(x, scale, bias) is monotone in x, so checking the
+// bound itself covers every smaller value.
+static int32_t transparent_max(float scale, float bias, uint32_t full) {
+    auto safe = [&](uint32_t t) {
+        const double hi = (double)t * (1.0 + 1.0 / 64.0);
+        float x = (float)hi;
+        if ((double)x < hi) x = std::nextafter(x, INFINITY);
+        return std::fma(x, scale, bias) <= 0.0f;
+    };
+    if (!safe(0)) return -1;
+    uint32_t lo = 0, hi = full;  // safe(lo) holds
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (safe(mid)) lo = mid; else hi = mid - 1;
+    }
+    return (int32_t)lo;
+}
+
+// Thresholds of the transparent-sample test: a channel whose alpha
+// multiplier is 0 (or that is hidden) never makes a sample opaque.
+static Transparent make_transparent(const ReqParams& P, uint32_t full) {
+    Transparent t{};
+    t.ok = 1;
+    for (int c = 0; c < kMaxChannels; ++c) {
+        int32_t m = 65535;
+        if (c < P.channels && P.tf[c].alpha_mul != 0.0f)
+            m = transparent_max(P.tf[c].scale, P.tf[c].bias, full);
+        if (m < 0) {
+            t.ok = 0;
+            m = 0;
+        }
+        t.tmax[c] = (uint32_t)m;
+    }
+    t.tmax2[0] = t.tmax[0] | t.tmax[1] << 16;
+    t.tmax2[1] = t.tmax[2] | t.tmax[3] << 16;
+    return t;
+}
+
 // Per-eye ray basis in double, rounded once to float.  Perspective: origin is
 // the eye e_s = center + s (sep / 2) r; the unnormalised direction to pixel
 // (sx, sy) is conv f - s (sep / 2) r + sx w r + sy h u.  Orthographic: the
@@ -227,6 +271,7 @@ void make_params(const vr_render_req& r, const vr_transfer* tf_in, ReqParams* P)
         o.alpha_mul = t.visible ? t.alpha_mul : 0.0f;
         for (int q = 0; q < 3; ++q) o.rgb[q] = t.visible ? t.rgb[q] : 0.0f;
     }
+    P->clear = make_transparent(*P, (uint32_t)full);
 
     double f[3] = {r.cam.forward[0], r.cam.forward[1], r.cam.forward[2]};
     const double up[3] = {r.cam.up[0], r.cam.up[1], r.cam.up[2]};
@@ -449,7 +494,7 @@ vr_status vr_render(vr_ctx* ctx, const vr_render_req* req, void* hip_stream) {
         std::lock_guard<std::mutex> lk(req->vol->tf_mu);
         make_params(*req, req->vol->tf, &P);
     }
-    hipError_t e = launch_render(P, ctx->plain_tile, (hipStream_t)hip_stream);
+    hipError_t e = launch_render(P, ctx->plain_tile, ctx->clear_skip, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return ok();
 }

@@ -361,6 +361,12 @@ extern "C" vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wav
     return ok();
 }
 
+extern "C" vr_status vr_test_clear_skip(vr_ctx* ctx, int32_t on) {
+    if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    ctx->clear_skip = on != 0;
+    return ok();
+}
+
 extern "C" vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
                                      void* hip_stream) {
     if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");

@@ -29,7 +29,10 @@ struct BatchWork {
 
 hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
                            const void* src, uint8_t* dst, hipStream_t s);
-hipError_t launch_render(const ReqParams& P, const TileShape& ts, hipStream_t s);
+// clear_skip = false selects the kernels that composite transparent samples
+// in full (same output bits).
+hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_skip,
+                         hipStream_t s);
 // Launch the persistent kernels of the variants set in `mask` (after
 // zeroing the counters), `grid[v]` blocks for variant v.
 hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,

@@ -67,8 +67,9 @@ __global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* 
 
 // ------------------------------------------------------------ plain render
 // Grid: one block per (eye, tile); block = 4 waves, each wave a wave_w x
-// wave_h pixel tile.
-template <int V>
+// wave_h pixel tile.  kClear = false composites transparent samples in full
+// (same output bits; kept to test and time the transparent-sample skip).
+template <int V, bool kClear>
 __global__ __launch_bounds__(kBlockThreads) void render_kernel(ReqParams P, TileShape ts,
                                                                int tiles_x, int tiles_y) {
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(kBlockThreads) void render_kernel(ReqParams P, Tile
     const int px = tx * ts.wave_w * ts.waves_x + wxi * ts.wave_w + lane % ts.wave_w;
     const int py = ty * ts.wave_h * ts.waves_y + wyi * ts.wave_h + lane / ts.wave_w;
     const bool valid = px < P.width && py < P.height;
-    render_pixel<V>(P, eye, valid ? px : 0, valid ? py : 0, valid);
+    render_pixel<V, kClear>(P, eye, valid ? px : 0, valid ? py : 0, valid);
 }
 
 // ------------------------------------------------------- persistent batch
@@ -188,13 +189,22 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
 }
 
 typedef void (*render_fn)(ReqParams, TileShape, int, int);
-static const render_fn kRender[kVariants] = {
-    render_kernel<0>, render_kernel<1>, render_kernel<2>, render_kernel<3>,
-    render_kernel<4>, render_kernel<5>, render_kernel<6>, render_kernel<7>,
-    render_kernel<8>, render_kernel<9>, render_kernel<10>, render_kernel<11>,
-    render_kernel<12>, render_kernel<13>, render_kernel<14>, render_kernel<15>};
+static const render_fn kRender[2][kVariants] = {
+    {render_kernel<0, false>, render_kernel<1, false>, render_kernel<2, false>,
+     render_kernel<3, false>, render_kernel<4, false>, render_kernel<5, false>,
+     render_kernel<6, false>, render_kernel<7, false>, render_kernel<8, false>,
+     render_kernel<9, false>, render_kernel<10, false>, render_kernel<11, false>,
+     render_kernel<12, false>, render_kernel<13, false>, render_kernel<14, false>,
+     render_kernel<15, false>},
+    {render_kernel<0, true>, render_kernel<1, true>, render_kernel<2, true>,
+     render_kernel<3, true>, render_kernel<4, true>, render_kernel<5, true>,
+     render_kernel<6, true>, render_kernel<7, true>, render_kernel<8, true>,
+     render_kernel<9, true>, render_kernel<10, true>, render_kernel<11, true>,
+     render_kernel<12, true>, render_kernel<13, true>, render_kernel<14, true>,
+     render_kernel<15, true>}};
 
-hipError_t launch_render(const ReqParams& P, const TileShape& ts, hipStream_t s) {
+hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_skip,
+                         hipStream_t s) {
     if (P.variant < 0 || P.variant >= kVariants) return hipErrorInvalidValue;
     if (ts.wave_w * ts.wave_h != kWave || ts.waves_x * ts.waves_y * kWave != kBlockThreads)
         return hipErrorInvalidValue;
@@ -203,8 +213,8 @@ hipError_t launch_render(const ReqParams& P, const TileShape& ts, hipStream_t s)
     const long long blocks = (long long)tiles_x * tiles_y * P.eyes;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kRender[P.variant], dim3((unsigned)blocks), dim3(kBlockThreads), 0, s, P,
-                       ts, tiles_x, tiles_y);
+    hipLaunchKernelGGL(kRender[clear_skip ? 1 : 0][P.variant], dim3((unsigned)blocks),
+                       dim3(kBlockThreads), 0, s, P, ts, tiles_x, tiles_y);
     return hipGetLastError();
 }
 

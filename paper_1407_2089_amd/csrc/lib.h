@@ -72,6 +72,7 @@ struct vr_ctx {
     bool tuning_cache_loaded = false;
     vr::TileShape batch_tile{8, 8, 2, 2};
     vr::TileShape plain_tile{8, 8, 2, 2};  // tile of vr_render launches
+    bool clear_skip = true;  // vr_render leaves out transparent samples' arithmetic
     std::map<uint64_t, vr::TileShape> tuned;
     vr::Scheduler* server = nullptr;  // created by the first vr_submit (server.cpp)
     std::mutex server_mu;

@@ -64,6 +64,18 @@ __device__ __forceinline__ half2_t bytes_to_half2(uint32_t w, uint32_t sel) {
     return __builtin_bit_cast(half2_t, v) - bias;
 }
 
+typedef uint16_t u16x2_t __attribute__((ext_vector_type(2)));
+
+// 16-bit values at or above 65520 would round to +inf in FP16; they are
+// clamped to 65504, the largest finite half (a change of at most 31 raw
+// units, within FP16's own rounding step of 32 at that magnitude).
+constexpr uint16_t kHalfMax = 65504;
+__device__ __forceinline__ half2_t u16x2_to_half2(uint32_t w) {
+    const u16x2_t v = __builtin_elementwise_min(__builtin_bit_cast(u16x2_t, w),
+                                                u16x2_t{kHalfMax, kHalfMax});
+    return half2_t{(_Float16)v.x, (_Float16)v.y};
+}
+
 template <int C, bool U16, typename T>
 __device__ __forceinline__ void unpack_f16(T w, half2_t (&h)[(C + 1) / 2]) {
     if constexpr (!U16) {
@@ -75,13 +87,13 @@ __device__ __forceinline__ void unpack_f16(T w, half2_t (&h)[(C + 1) / 2]) {
         }
     } else {
         if constexpr (C == 1) {
-            h[0] = half2_t{(_Float16)(uint16_t)w, (_Float16)0.0f};
+            const uint16_t v = (uint16_t)w < kHalfMax ? (uint16_t)w : kHalfMax;
+            h[0] = half2_t{(_Float16)v, (_Float16)0.0f};
         } else if constexpr (C == 2) {
-            const uint32_t u = (uint32_t)w;
-            h[0] = half2_t{(_Float16)(uint16_t)u, (_Float16)(uint16_t)(u >> 16)};
+            h[0] = u16x2_to_half2((uint32_t)w);
         } else {
-            h[0] = half2_t{(_Float16)(uint16_t)w.x, (_Float16)(uint16_t)(w.x >> 16)};
-            h[1] = half2_t{(_Float16)(uint16_t)w.y, (_Float16)(uint16_t)(w.y >> 16)};
+            h[0] = u16x2_to_half2(w.x);
+            h[1] = u16x2_to_half2(w.y);
         }
     }
 }
@@ -272,6 +284,48 @@ __device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
     }
 }
 
+// Channel pair q of a stored word as two 16-bit lanes (channel 2q, 2q + 1).
+template <int C, bool U16, typename T>
+__device__ __forceinline__ u16x2_t pair16(T w, int q) {
+    if constexpr (U16) {
+        if constexpr (C == 2) return __builtin_bit_cast(u16x2_t, (uint32_t)w);
+        else return __builtin_bit_cast(u16x2_t, q == 0 ? w.x : w.y);
+    } else {
+        const uint32_t sel = q == 0 ? 0x0c010c00u : 0x0c030c02u;  // zero-extend 2 bytes
+        return __builtin_bit_cast(u16x2_t, __builtin_amdgcn_perm(0u, (uint32_t)w, sel));
+    }
+}
+
+// True when every tap of every channel c is at most tmax[c]: the sample's
+// opacity is then exactly 0 (see Transparent), so its compositing can be left
+// out without changing any output bit.  Costs a packed 16-bit max per word
+// pair and one saturating compare per channel pair.
+template <int C, bool U16, typename T>
+__device__ __forceinline__ bool transparent(const Taps<T>& t, const Transparent& z) {
+    if constexpr (C == 1) {
+        const uint32_t m =
+            max(max(max((uint32_t)t.w000, (uint32_t)t.w100), max((uint32_t)t.w010, (uint32_t)t.w110)),
+                max(max((uint32_t)t.w001, (uint32_t)t.w101), max((uint32_t)t.w011, (uint32_t)t.w111)));
+        return m <= z.tmax[0];
+    } else {
+        bool clear = true;
+#pragma unroll
+        for (int q = 0; q < (C + 1) / 2; ++q) {
+            const u16x2_t m = __builtin_elementwise_max(
+                __builtin_elementwise_max(
+                    __builtin_elementwise_max(pair16<C, U16>(t.w000, q), pair16<C, U16>(t.w100, q)),
+                    __builtin_elementwise_max(pair16<C, U16>(t.w010, q), pair16<C, U16>(t.w110, q))),
+                __builtin_elementwise_max(
+                    __builtin_elementwise_max(pair16<C, U16>(t.w001, q), pair16<C, U16>(t.w101, q)),
+                    __builtin_elementwise_max(pair16<C, U16>(t.w011, q), pair16<C, U16>(t.w111, q))));
+            const u16x2_t over =
+                __builtin_elementwise_sub_sat(m, __builtin_bit_cast(u16x2_t, z.tmax2[q]));
+            clear = clear && __builtin_bit_cast(uint32_t, over) == 0u;
+        }
+        return clear;
+    }
+}
+
 // Trilinear field (raw units) of every channel at index-space point p.
 template <int C, bool U16, bool F16>
 __device__ __forceinline__ void sample(const BrickGeom& g, const Sampler& S, float px, float py,
@@ -288,7 +342,7 @@ template <int V> struct Variant {
 
 // One pixel of one eye: returns nothing, writes RGBA (and the sample count).
 // `valid` false lanes take part in the wave's loop structure but do no work.
-template <int V>
+template <int V, bool kClear = true>
 __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px, int py,
                                              bool valid) {
     constexpr int C = Variant<V>::C;
@@ -354,9 +408,14 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
     // accumulating, and the wave leaves when the mask is empty (the wave-wide
     // ballot of the lanes' live flags).
     using Word = typename WordT<C, U16>::T;
-    // Composite one sample from landed taps.  `on` false leaves the lane's
-    // state bitwise unchanged (its weight is 0), without a branch.
+    // Composite one sample from landed taps.  A lane leaves its state as it
+    // is when `on` is false (past its last sample) or when the taps show the
+    // sample to be transparent (its weight would be exactly 0); a wave skips
+    // the arithmetic when that holds for all of its lanes, the common case in
+    // the empty, below-floor space around stained structures.
+    const bool clear_ok = kClear && P.clear.ok != 0;
     auto composite = [&](const Taps<Word>& t, bool on) {
+        if (!on || (clear_ok && transparent<C, U16>(t, P.clear))) return;
         float x[C];
         interpolate<C, U16, F16>(t, x);
         float amax = 0.0f, r = 0.0f, gg = 0.0f, bb = 0.0f;
@@ -371,7 +430,7 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
             bb = fmaf(g, tf[c].rgb[2], bb);
         }
         const float a_s = fminf(amax, 1.0f);
-        const float wgt = on ? (1.0f - A) * a_s : 0.0f;
+        const float wgt = (1.0f - A) * a_s;
         Cr = fmaf(wgt, fminf(r, 1.0f), Cr);
         Cg = fmaf(wgt, fminf(gg, 1.0f), Cg);
         Cb = fmaf(wgt, fminf(bb, 1.0f), Cb);
@@ -385,9 +444,8 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
     if (n > 0) {
         // Software pipeline over pairs of samples: the taps of the next
         // sample are always in flight while the current one is interpolated
-        // and composited.  The pair's second sample is composited with a
-        // zero weight on lanes that finished on its first, so the only exit
-        // is at the end of the pair (a divergent loop: finished lanes are
+        // and composited.  The pair's second sample is left out on lanes that
+        // finished on its first, so the only exit is at the end of the pair (a divergent loop: finished lanes are
         // masked off and the wave leaves when none is live).  At equal sample
         // index a wave's sample points lie on a patch parallel to the face its
         // rays entered through, which the brick layout serves with few cache

@@ -53,12 +53,25 @@ struct ChanTF {
     float rgb[3];        // 0 for an invisible channel
 };
 
+// Transparency thresholds of a request.  A sample whose eight taps of every
+// channel c are at most tmax[c] (raw units) has opacity exactly 0 in the
+// kernel's own arithmetic (FP32 or FP16 interpolation), so compositing it
+// leaves the pixel bitwise unchanged.  ok = 0 when some channel can never be
+// shown transparent that way (then no sample is).
+struct Transparent {
+    uint32_t tmax2[2];   // (tmax[2q] | tmax[2q + 1] << 16), 16-bit lanes
+    uint32_t tmax[4];    // per channel, 0 .. 65535
+    int32_t ok;
+    int32_t pad_;
+};
+
 struct ReqParams {
     const uint8_t* vox;     // this frame's storage
     BrickGeom g;
     int32_t channels;
     int32_t variant;
     ChanTF tf[kMaxChannels];
+    Transparent clear;      // transparent-sample test of this request's TFs
     // Rays.  Index-space origin p0 = o0[eye] + sx * ou + sy * ov; world
     // direction w = base[eye] + sx * du + sy * dv, unit-normalised, then
     // index-space direction d = w * inv_sp.
