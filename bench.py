@@ -151,7 +151,7 @@ def main():
                          "mixed requests, batched vs plain launches; serve: Poisson arrivals "
                          "on resident datasets, p50/p99; precision: 48-frame series FP32/FP16")
     ap.add_argument("--brick", default="0,0,0", help="brick edge per axis (0,0,0 = default)")
-    ap.add_argument("--tile", default="", help="wave_w,wave_h,waves_x,waves_y of vr_render")
+    ap.add_argument("--tile", default="", help="wave_w,wave_h (pixels per wave) of vr_render")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-gb", type=float, default=150.0)
     ap.add_argument("--serve-rates", default="25,100,400,1000,1600,2400")
@@ -268,7 +268,7 @@ def main():
         "config": {"workload": "realistic frame: 2ch u16-12 512x512x64 cells+vessels, "
                                "perspective stereo 1920x1080 per eye, step 1, alpha 0.99",
                    "eyes": 2, "width": sc.width, "height": sc.height, "brick": list(brick),
-                   "tile": args.tile or "8,8,2,2",
+                   "tile": args.tile or "8,8",
                    "samples_per_step": samples_per_step},
         "stereo_fps": args.steps / wall,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,

@@ -21,17 +21,14 @@ extern "C" {
 vr_status vr_test_fake_backend(vr_ctx* ctx, int32_t slots, double ns_per_ray,
                                int32_t fail_width, int32_t max_batch);
 
-/* Fix the tile shape of batched launches (wave_w x wave_h pixels per wave,
- * waves_x x waves_y waves per 256-thread block; wave_w * wave_h = 64 and
- * waves_x * waves_y = 4), bypassing the autotuner; all zeros hands the
- * choice back to the autotuner. */
-vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h, int32_t waves_x,
-                             int32_t waves_y);
+/* Fix the wave tile of batched launches (wave_w x wave_h pixels per wave,
+ * wave_w * wave_h = 64), bypassing the autotuner; 0, 0 hands the choice back
+ * to the autotuner. */
+vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h);
 
-/* The same for plain vr_render launches (default 8 x 8 pixels per wave, 2 x 2
- * waves); all zeros restores the default. */
-vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h, int32_t waves_x,
-                             int32_t waves_y);
+/* The same for plain vr_render launches (default 8 x 8 pixels per wave, one
+ * wave per block); 0, 0 restores the default. */
+vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h);
 
 /* on = 0 makes vr_render composite transparent samples in full instead of
  * leaving out their arithmetic (a sample whose taps are all below every

@@ -100,8 +100,8 @@ def lib():
             "vr_release": [P, C.c_uint64],
             "vr_debug_sample": [P, C.c_int32, P, C.c_int32, P, P],
             "vr_test_fake_backend": [P, C.c_int32, C.c_double, C.c_int32, C.c_int32],
-            "vr_test_batch_tile": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
-            "vr_test_plain_tile": [P, C.c_int32, C.c_int32, C.c_int32, C.c_int32],
+            "vr_test_batch_tile": [P, C.c_int32, C.c_int32],
+            "vr_test_plain_tile": [P, C.c_int32, C.c_int32],
             "vr_test_block_map": [C.c_int32, C.c_void_p],
             "vr_test_clear_skip": [P, C.c_int32],
         }
@@ -209,12 +209,12 @@ def vr_debug_sample(vol, frame: int, pts, n: int, out, stream=None):
     _check(lib().vr_debug_sample(vol, frame, _ptr(pts), n, _ptr(out), _stream(stream)))
 
 
-def vr_test_batch_tile(ctx, wave_w=0, wave_h=0, waves_x=0, waves_y=0):
-    _check(lib().vr_test_batch_tile(ctx, wave_w, wave_h, waves_x, waves_y))
+def vr_test_batch_tile(ctx, wave_w=0, wave_h=0):
+    _check(lib().vr_test_batch_tile(ctx, wave_w, wave_h))
 
 
-def vr_test_plain_tile(ctx, wave_w=0, wave_h=0, waves_x=0, waves_y=0):
-    _check(lib().vr_test_plain_tile(ctx, wave_w, wave_h, waves_x, waves_y))
+def vr_test_plain_tile(ctx, wave_w=0, wave_h=0):
+    _check(lib().vr_test_plain_tile(ctx, wave_w, wave_h))
 
 
 def vr_test_clear_skip(ctx, on: bool):

@@ -189,7 +189,7 @@ static vr_status check_transfer(const vr_transfer* t) {
     return VR_OK;
 }
 
-TileShape default_tile() { return TileShape{8, 8, 2, 2}; }
+TileShape default_tile() { return TileShape{8, 8}; }
 
 static void cross(const double a[3], const double b[3], double o[3]) {
     o[0] = a[1] * b[2] - a[2] * b[1];
@@ -386,7 +386,6 @@ vr_status vr_init(int32_t device, uint64_t mem_budget_bytes, vr_ctx** out) {
         mem_budget_bytes = free_b > reserve ? free_b - reserve : free_b / 2;
     }
     ctx->budget = mem_budget_bytes;
-    batch_grid_blocks(device, ctx->batch_grid);
     *out = ctx;
     return ok();
 }

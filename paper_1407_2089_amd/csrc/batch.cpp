@@ -56,7 +56,6 @@ void batch_slot_destroy(BatchSlot* s) {
     drop_graphs(s);
     free_tables(s);
     if (s->d_work) (void)hipFree(s->d_work);
-    if (s->d_counters) (void)hipFree(s->d_counters);
     if (s->h_work) (void)hipHostFree(s->h_work);
     if (s->staged) (void)hipEventDestroy(s->staged);
     if (s->capture) (void)hipStreamDestroy(s->capture);
@@ -90,7 +89,6 @@ BatchSlot* batch_slot_create(vr_ctx* ctx, hipStream_t stream, vr_status* st) {
     if ((e = hipStreamCreateWithFlags(&s->capture, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&s->staged, hipEventDisableTiming)) != hipSuccess ||
         (e = hipMalloc(&s->d_work, sizeof(BatchWork))) != hipSuccess ||
-        (e = hipMalloc(&s->d_counters, 256)) != hipSuccess ||
         (e = hipHostMalloc(&s->h_work, sizeof(BatchWork), hipHostMallocDefault)) != hipSuccess) {
         *st = hip_fail(e, "batch workspace");
         batch_slot_destroy(s);
@@ -116,8 +114,9 @@ BatchSlot* batch_slot_for(vr_ctx* ctx, hipStream_t stream, vr_status* st) {
     return s;
 }
 
-static vr_status graph_for(vr_ctx* ctx, BatchSlot* s, uint32_t mask, hipGraphExec_t* out) {
-    auto it = s->graphs.find(mask);
+static vr_status graph_for(BatchSlot* s, uint32_t mask, int blocks, hipGraphExec_t* out) {
+    const uint64_t key = (uint64_t)mask << 32 | (uint32_t)blocks;
+    auto it = s->graphs.find(key);
     if (it != s->graphs.end()) {
         *out = it->second.second;
         return VR_OK;
@@ -126,8 +125,7 @@ static vr_status graph_for(vr_ctx* ctx, BatchSlot* s, uint32_t mask, hipGraphExe
     hipGraphExec_t exec = nullptr;
     hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le = launch_batch(s->d_work, s->d_reqs, s->d_prefix, s->d_counters, mask,
-                                 ctx->batch_grid, s->capture);
+    hipError_t le = launch_batch(s->d_work, s->d_reqs, s->d_prefix, mask, blocks, s->capture);
     e = hipStreamEndCapture(s->capture, &graph);
     if (le != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -139,19 +137,19 @@ static vr_status graph_for(vr_ctx* ctx, BatchSlot* s, uint32_t mask, hipGraphExe
         (void)hipGraphDestroy(graph);
         return hip_fail(e, "hipGraphInstantiate");
     }
-    s->graphs[mask] = {graph, exec};
+    s->graphs[key] = {graph, exec};
     *out = exec;
     return VR_OK;
 }
 
+// Largest grid of a batch kernel, in single-wave blocks.
+constexpr int kBatchBlocksMax = 1 << 17;
+
 // ----------------------------------------------------------------- tuning
-// Candidate tile shapes of a 256-thread block (pixels per wave x waves).
-// Per-ray arithmetic does not depend on the tiling, so every candidate gives
-// the same image bit for bit; only the speed differs.
-static const TileShape kCandidates[] = {
-    {8, 8, 2, 2}, {8, 8, 4, 1}, {8, 8, 1, 4}, {16, 4, 1, 4},
-    {16, 4, 2, 2}, {4, 16, 4, 1}, {32, 2, 1, 4}, {64, 1, 1, 4},
-};
+// Candidate wave tiles (pixels per wave, width x height).  Per-ray
+// arithmetic does not depend on the tiling, so every candidate gives the
+// same image bit for bit; only the speed differs.
+static const TileShape kCandidates[] = {{8, 8}, {16, 4}, {4, 16}, {32, 2}, {64, 1}};
 
 // Shape class: the set of data variants in the batch and the order of
 // magnitude of its ray count.
@@ -172,9 +170,9 @@ static void load_tuning_cache(vr_ctx* ctx) {
     FILE* f = std::fopen(path, "r");
     if (!f) return;
     unsigned long long key;
-    int a, b, c, d;
-    while (std::fscanf(f, "%llx %d %d %d %d", &key, &a, &b, &c, &d) == 5)
-        if (a * b == kWave && c * d * kWave == kBlockThreads) ctx->tuned[key] = TileShape{a, b, c, d};
+    int a, b;
+    while (std::fscanf(f, "%llx %d %d", &key, &a, &b) == 3)
+        if (a > 0 && b > 0 && a * b == kWave) ctx->tuned[key] = TileShape{a, b};
     std::fclose(f);
 }
 
@@ -183,8 +181,7 @@ static void save_tuning(uint64_t key, const TileShape& t) {
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%llx %d %d %d %d\n", (unsigned long long)key, t.wave_w, t.wave_h, t.waves_x,
-                 t.waves_y);
+    std::fprintf(f, "%llx %d %d\n", (unsigned long long)key, t.wave_w, t.wave_h);
     std::fclose(f);
 }
 
@@ -280,7 +277,7 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
         if ((e = hipEventSynchronize(s->staged)) != hipSuccess) return hip_fail(e, "staging wait");
         s->staged_pending = false;
     }
-    const int bw = ts.wave_w * ts.waves_x, bh = ts.wave_h * ts.waves_y;
+    const int bw = ts.wave_w, bh = ts.wave_h;
     BatchWork* w = s->h_work;
     std::memset(w->group, 0, sizeof w->group);
     uint32_t mask = 0;
@@ -296,14 +293,20 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
         s->h_prefix[q] = (int32_t)items;
         const int64_t tx = (P.width + bw - 1) / bw, ty = (P.height + bh - 1) / bh;
         items += tx * ty * P.eyes;
-        if (items > 0x7fffffff) return fail(VR_ERR_INVALID_ARG, "batch has too many tiles");
+        if (items > (1 << 30)) return fail(VR_ERR_INVALID_ARG, "batch has too many tiles");
         g.n_req += 1;
         g.n_items = (int32_t)items;
         if (items > 0) mask |= 1u << P.variant;
     }
     if (mask == 0) return VR_OK;
-    w->counters = s->d_counters;
     w->tile = ts;
+    // Grid of every variant's kernel: the largest group's item count rounded
+    // up to a power of two (a few captured graphs cover all batch sizes),
+    // capped so that a block takes a handful of items of a large batch.
+    int64_t most = 0;
+    for (int v = 0; v < kVariants; ++v) most = std::max<int64_t>(most, w->group[v].n_items);
+    int blocks = kWave;
+    while (blocks < most && blocks < kBatchBlocksMax) blocks *= 2;
     if ((e = hipMemcpyAsync(s->d_reqs, s->h_reqs, sizeof(ReqParams) * (size_t)n,
                             hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
         (e = hipMemcpyAsync(s->d_prefix, s->h_prefix, sizeof(int32_t) * (size_t)n,
@@ -316,13 +319,13 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
 
     if (ctx->use_graphs) {
         hipGraphExec_t exec = nullptr;
-        vr_status st = graph_for(ctx, s, mask, &exec);
+        vr_status st = graph_for(s, mask, blocks, &exec);
         if (st != VR_OK) return st;
         if ((e = hipGraphLaunch(exec, s->stream)) != hipSuccess)
             return hip_fail(e, "hipGraphLaunch");
     } else {
-        if ((e = launch_batch(s->d_work, s->d_reqs, s->d_prefix, s->d_counters, mask,
-                              ctx->batch_grid, s->stream)) != hipSuccess)
+        if ((e = launch_batch(s->d_work, s->d_reqs, s->d_prefix, mask, blocks, s->stream)) !=
+            hipSuccess)
             return hip_fail(e, "batch launch");
     }
     return VR_OK;
@@ -332,32 +335,28 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
 
 using namespace vr;
 
-extern "C" vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h,
-                                        int32_t waves_x, int32_t waves_y) {
+extern "C" vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h) {
     if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
-    if (wave_w == 0 && wave_h == 0 && waves_x == 0 && waves_y == 0) {
+    if (wave_w == 0 && wave_h == 0) {
         ctx->forced_tile = false;
         return ok();
     }
-    if (wave_w <= 0 || wave_h <= 0 || waves_x <= 0 || waves_y <= 0 || wave_w * wave_h != kWave ||
-        waves_x * waves_y * kWave != kBlockThreads)
-        return fail(VR_ERR_INVALID_ARG, "a tile is 64 pixels per wave and 4 waves per block");
-    ctx->batch_tile = TileShape{wave_w, wave_h, waves_x, waves_y};
+    if (wave_w <= 0 || wave_h <= 0 || wave_w * wave_h != kWave)
+        return fail(VR_ERR_INVALID_ARG, "a wave tile is 64 pixels");
+    ctx->batch_tile = TileShape{wave_w, wave_h};
     ctx->forced_tile = true;
     return ok();
 }
 
-extern "C" vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h,
-                                        int32_t waves_x, int32_t waves_y) {
+extern "C" vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h) {
     if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
-    if (wave_w == 0 && wave_h == 0 && waves_x == 0 && waves_y == 0) {
+    if (wave_w == 0 && wave_h == 0) {
         ctx->plain_tile = default_tile();
         return ok();
     }
-    if (wave_w <= 0 || wave_h <= 0 || waves_x <= 0 || waves_y <= 0 || wave_w * wave_h != kWave ||
-        waves_x * waves_y * kWave != kBlockThreads)
-        return fail(VR_ERR_INVALID_ARG, "a tile is 64 pixels per wave and 4 waves per block");
-    ctx->plain_tile = TileShape{wave_w, wave_h, waves_x, waves_y};
+    if (wave_w <= 0 || wave_h <= 0 || wave_w * wave_h != kWave)
+        return fail(VR_ERR_INVALID_ARG, "a wave tile is 64 pixels");
+    ctx->plain_tile = TileShape{wave_w, wave_h};
     return ok();
 }
 

@@ -19,10 +19,11 @@ struct BatchGroup {
 // take the request descriptors (grouped by variant) and each request's first
 // work item within its group.  The host rewrites all three before each
 // launch; their addresses stay fixed until the tables grow, so a captured
-// graph can be replayed.  One persistent kernel per data variant present
-// works through that variant's group, claiming items from its own counter.
+// graph can be replayed.  One kernel per data variant present works through
+// that variant's group: a fixed grid of single-wave blocks, block b taking
+// items b, b + grid, b + 2 grid, ... (after the XCD remap), so the hardware
+// dispatcher balances the load as blocks finish, with no shared counter.
 struct BatchWork {
-    int32_t* counters;      // [kVariants] next unclaimed item of each group
     TileShape tile;
     BatchGroup group[kVariants];
 };
@@ -33,14 +34,11 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
 // in full (same output bits).
 hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_skip,
                          hipStream_t s);
-// Launch the persistent kernels of the variants set in `mask` (after
-// zeroing the counters), `grid[v]` blocks for variant v.
+// Launch the batch kernels of the variants set in `mask`, `blocks`
+// single-wave blocks each.
 hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
-                        const int32_t* dev_prefix, int* dev_counters, uint32_t mask,
-                        const int* grid, hipStream_t s);
+                        const int32_t* dev_prefix, uint32_t mask, int blocks, hipStream_t s);
 hipError_t launch_debug_sample(const ReqParams& P, const float* pts, int n, float* out,
                                hipStream_t s);
-// Persistent blocks per variant: resident blocks per CU times the CUs.
-void batch_grid_blocks(int device, int* grid /* [kVariants] */);
 
 }  // namespace vr

@@ -26,16 +26,15 @@ struct BatchSlot {
     int capacity = 0;               // requests the tables can hold
     ReqParams* d_reqs = nullptr;
     int32_t* d_prefix = nullptr;
-    int32_t* d_counters = nullptr;  // [kVariants]
     BatchWork* d_work = nullptr;
     ReqParams* h_reqs = nullptr;    // pinned
     int32_t* h_prefix = nullptr;    // pinned
     BatchWork* h_work = nullptr;    // pinned
     hipEvent_t staged = nullptr;    // staging copies of the last batch done
     bool staged_pending = false;
-    // Captured launches, one per set of variants present in a batch (they
-    // hold the table addresses: dropped when the tables grow).
-    std::map<uint32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // Captured launches, one per (set of variants present, grid size) of a
+    // batch (they hold the table addresses: dropped when the tables grow).
+    std::map<uint64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
 // Sets the calling thread's error message and returns `st`.
@@ -61,7 +60,6 @@ struct vr_ctx {
     uint64_t budget = 0;
     std::atomic<uint64_t> used{0};
     std::atomic<int> volumes{0};
-    int batch_grid[vr::kVariants] = {};  // persistent blocks per variant
     std::mutex mu;
     // Batched-launch workspaces keyed by stream (batch.cpp).
     std::map<hipStream_t, vr::BatchSlot*> batch_slots;
@@ -70,8 +68,8 @@ struct vr_ctx {
     bool autotune = true;
     bool forced_tile = false;          // a test fixed the tile shape
     bool tuning_cache_loaded = false;
-    vr::TileShape batch_tile{8, 8, 2, 2};
-    vr::TileShape plain_tile{8, 8, 2, 2};  // tile of vr_render launches
+    vr::TileShape batch_tile{8, 8};
+    vr::TileShape plain_tile{8, 8};  // wave tile of vr_render launches
     bool clear_skip = true;  // vr_render leaves out transparent samples' arithmetic
     std::map<uint64_t, vr::TileShape> tuned;
     vr::Scheduler* server = nullptr;  // created by the first vr_submit (server.cpp)

@@ -480,9 +480,9 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b to XCD b mod 8,
 // as its (b / 8)-th block).  Remap so that each XCD takes runs of kXcdRun
-// consecutive tiles (a 128-pixel-wide strip of one tile row at 16-pixel
-// tiles, whose rays share voxels in that XCD's L2), the runs dealt to the
-// XCDs in turn.  Handing each XCD one contiguous eighth of the image instead
+// consecutive tiles (a 64-pixel-wide strip of one row of 8 x 8 wave tiles,
+// whose rays share voxels in that XCD's L2), the runs dealt to the XCDs in
+// turn.  Handing each XCD one contiguous eighth of the image instead
 // leaves most XCDs idle: a volume seldom covers the whole image, so its
 // rays crowd into a few eighths.  The map is a bijection on [0, nblocks);
 // blocks past the last whole round of 8 runs keep their index.

@@ -90,10 +90,11 @@ struct ReqParams {
     int32_t* samples;       // [eyes][H][W] or null
 };
 
-// Work decomposition: one item = one pixel tile of one eye of one request.
+// Work decomposition: one item = one wave's pixel tile of one eye of one
+// request.  Waves take items independently (a wave whose rays end early
+// does not wait for the others of its block).
 struct TileShape {
     int32_t wave_w, wave_h;   // pixels per wave (wave_w * wave_h = 64)
-    int32_t waves_x, waves_y; // waves per block
 };
 
 }  // namespace vr

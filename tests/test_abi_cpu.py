@@ -233,3 +233,13 @@ def test_block_map_is_a_permutation_that_deals_strips_to_xcds():
         assert rounds == set(range(10))
     with pytest.raises(vr.VrError):
         vr.vr_test_block_map(-1)
+
+
+def test_tile_hooks_validate_wave_tiles(vctx):
+    for hook in (vr.vr_test_plain_tile, vr.vr_test_batch_tile):
+        hook(vctx, 16, 4)
+        hook(vctx, 1, 64)
+        hook(vctx)  # back to the default / the autotuner
+        for bad in ((8, 4), (0, 64), (-8, -8), (65, 1), (128, 0)):
+            with pytest.raises(vr.VrError):
+                hook(vctx, *bad)
