@@ -36,9 +36,10 @@ vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h);
  * are the same either way.  on = 1 (the default) restores the skip. */
 vr_status vr_test_clear_skip(vr_ctx* ctx, int32_t on);
 
-/* Tile index that hardware block b of a plain vr_render launch of nblocks
- * blocks renders, for b = 0 .. nblocks - 1, written to tiles[b] (host
- * memory).  Pure host computation: a permutation of 0 .. nblocks - 1. */
+/* Position in a launch's tile order (super-tile by super-tile) that
+ * hardware block b of a launch of nblocks single-wave blocks takes, for
+ * b = 0 .. nblocks - 1, written to tiles[b] (host memory).  Pure host
+ * computation: a permutation of 0 .. nblocks - 1. */
 vr_status vr_test_block_map(int32_t nblocks, int32_t* tiles);
 
 #ifdef __cplusplus

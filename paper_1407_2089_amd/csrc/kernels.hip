@@ -71,15 +71,19 @@ __global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* 
 // end (measured: 4-wave blocks were 6 % slower on the top view and up to
 // 24 % on grazing views).  kClear = false composites transparent samples in
 // full (same output bits; kept to test and time the transparent-sample skip).
+// Tiles of an eye run super-tile by super-tile (row-major over super-tiles of
+// kSuperW x kSuperH tiles, row-major inside each); the grid covers whole
+// super-tiles, and lanes past the image edge are invalid.
 template <int V, bool kClear>
-__global__ __launch_bounds__(kWave) void render_kernel(ReqParams P, TileShape ts, int tiles_x,
-                                                       int tiles_y) {
+__global__ __launch_bounds__(kWave) void render_kernel(ReqParams P, TileShape ts, int supers_x,
+                                                       int per_eye) {
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int per_eye = tiles_x * tiles_y;
     const int eye = b / per_eye;
     const int t = b - eye * per_eye;
-    const int ty = t / tiles_x;
-    const int tx = t - ty * tiles_x;
+    const int st = t / kXcdRun, j = t - st * kXcdRun;
+    const int sy = st / supers_x, sx = st - sy * supers_x;
+    const int tx = sx * kSuperW + j % kSuperW;
+    const int ty = sy * kSuperH + j / kSuperW;
     const int lane = threadIdx.x;
     const int px = tx * ts.wave_w + lane % ts.wave_w;
     const int py = ty * ts.wave_h + lane / ts.wave_w;
@@ -201,11 +205,14 @@ hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_ski
         return hipErrorInvalidValue;
     const int tiles_x = (P.width + ts.wave_w - 1) / ts.wave_w;
     const int tiles_y = (P.height + ts.wave_h - 1) / ts.wave_h;
-    const long long blocks = (long long)tiles_x * tiles_y * P.eyes;
+    const long long supers_x = (tiles_x + kSuperW - 1) / kSuperW;
+    const long long supers_y = (tiles_y + kSuperH - 1) / kSuperH;
+    const long long per_eye = supers_x * supers_y * kXcdRun;
+    const long long blocks = per_eye * P.eyes;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(kRender[clear_skip ? 1 : 0][P.variant], dim3((unsigned)blocks),
-                       dim3(kWave), 0, s, P, ts, tiles_x, tiles_y);
+                       dim3(kWave), 0, s, P, ts, (int)supers_x, (int)per_eye);
     return hipGetLastError();
 }
 

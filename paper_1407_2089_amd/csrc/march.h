@@ -479,14 +479,18 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b to XCD b mod 8,
-// as its (b / 8)-th block).  Remap so that each XCD takes runs of kXcdRun
-// consecutive tiles (a 64-pixel-wide strip of one row of 8 x 8 wave tiles,
-// whose rays share voxels in that XCD's L2), the runs dealt to the XCDs in
-// turn.  Handing each XCD one contiguous eighth of the image instead
-// leaves most XCDs idle: a volume seldom covers the whole image, so its
-// rays crowd into a few eighths.  The map is a bijection on [0, nblocks);
-// blocks past the last whole round of 8 runs keep their index.
-constexpr int kXcdRun = 8;
+// as its (b / 8)-th block).  A launch orders its wave tiles by super-tiles of
+// kSuperW x kSuperH tiles (32 x 32 pixels at 8 x 8 wave tiles), and the remap
+// deals whole super-tiles to the XCDs in turn: an XCD's consecutive blocks
+// render one compact patch whose rays share voxels in that XCD's L2.  Handing
+// each XCD one contiguous eighth of the image instead leaves most XCDs idle
+// (a volume seldom covers the whole image, so its rays crowd into a few
+// eighths); larger super-tiles unbalance the XCDs again (measured, and
+// simulated from per-pixel sample counts: 4 x 4 stays within 1-7 %).  The map
+// is a bijection on [0, nblocks); blocks past the last whole round of 8 runs
+// keep their index.
+constexpr int kSuperW = 4, kSuperH = 4;
+constexpr int kXcdRun = kSuperW * kSuperH;
 __host__ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
     const int whole = nblocks - nblocks % (8 * kXcdRun);
     if (b >= whole) return b;

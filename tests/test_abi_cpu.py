@@ -213,23 +213,26 @@ def test_null_arguments_do_not_crash():
     assert vr.vr_last_error() != ""
 
 
-def test_block_map_is_a_permutation_that_deals_strips_to_xcds():
-    """Plain launches remap hardware block b (dispatched to XCD b mod 8) to a
-    tile: a bijection on every grid size, runs of 8 consecutive tiles per
-    XCD dealt in turn, and the tail past the last whole round unchanged."""
-    for n in list(range(0, 200)) + [16320, 16321, 16384 + 37, 65536 * 3 + 5]:
+def test_block_map_is_a_permutation_that_deals_super_tiles_to_xcds():
+    """Launches remap hardware block b (dispatched to XCD b mod 8) to a
+    position in their tile order: a bijection on every grid size, runs of 16
+    consecutive positions (one 4 x 4 super-tile) per XCD dealt in turn, and
+    the tail past the last whole round of 8 runs unchanged."""
+    R = 16
+    for n in list(range(0, 300)) + [16320, 16321, 16384 + 37, 65536 * 3 + 5]:
         m = vr.vr_test_block_map(n)
         assert np.array_equal(np.sort(m), np.arange(n)), n
-    m = vr.vr_test_block_map(130)
-    # Round 0: XCD x takes tiles 8x .. 8x + 7 as its blocks 0..7.
+    n = 8 * R * 2 + 5
+    m = vr.vr_test_block_map(n)
+    # Round 0: XCD x takes positions R x .. R x + R - 1 as its blocks 0..R-1.
     for xcd in range(8):
-        blocks = np.arange(xcd, 64 * 8, 8)[:8]
-        assert list(m[blocks]) == list(range(8 * xcd, 8 * xcd + 8))
-    assert list(m[128:]) == [128, 129]  # 130 = 2 * 64 + 2: tail keeps its order
-    # Work spread: every XCD holds tiles from every 64-tile round.
-    m = vr.vr_test_block_map(64 * 10)
+        blocks = np.arange(xcd, 8 * R * 8, 8)[:R]
+        assert list(m[blocks]) == list(range(R * xcd, R * xcd + R))
+    assert list(m[8 * R * 2:]) == list(range(8 * R * 2, n))  # the tail keeps its order
+    # Work spread: every XCD holds positions from every round of 8 runs.
+    m = vr.vr_test_block_map(8 * R * 10)
     for xcd in range(8):
-        rounds = set((m[np.arange(xcd, 640, 8)] // 64).tolist())
+        rounds = set((m[np.arange(xcd, 8 * R * 10, 8)] // (8 * R)).tolist())
         assert rounds == set(range(10))
     with pytest.raises(vr.VrError):
         vr.vr_test_block_map(-1)
