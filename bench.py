@@ -152,6 +152,10 @@ def main():
                          "on resident datasets, p50/p99; precision: 48-frame series FP32/FP16")
     ap.add_argument("--brick", default="0,0,0", help="brick edge per axis (0,0,0 = default)")
     ap.add_argument("--tile", default="", help="wave_w,wave_h (pixels per wave) of vr_render")
+    ap.add_argument("--layout", choices=["bricks", "pairs"], default="pairs",
+                    help="voxel layout of the realistic frame: bricks with row pairs "
+                         "(default; two 16-byte loads per sample, 2.2x the storage) or plain "
+                         "bricks (the library's default layout)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-gb", type=float, default=150.0)
     ap.add_argument("--serve-rates", default="25,100,400,1000,1600,2400")
@@ -207,7 +211,8 @@ def main():
     ctx = vr.Context(0)
     c, nz, ny, nx = sc.volume.shape
     brick = tuple(int(b) for b in args.brick.split(","))
-    vol = vr.Volume(ctx, (nx, ny, nz), c, 1, vr.VR_U16, sc.bits, brick=brick)
+    pairs = args.layout == "pairs"
+    vol = vr.Volume(ctx, (nx, ny, nz), c, 1, vr.VR_U16, sc.bits, brick=brick, row_pairs=pairs)
     if args.tile:
         vr.vr_test_plain_tile(ctx.ptr, *[int(t) for t in args.tile.split(",")])
     stream = torch.cuda.current_stream()
@@ -249,8 +254,9 @@ def main():
 
     bytes_per_sample = 8 * c * 2
     alg_bytes = samples_per_step * bytes_per_sample
-    default_layout = args.precision == "fp32" and brick == (0, 0, 0) and not args.tile
-    traffic = measured_traffic() if default_layout else None
+    headline_layout = (args.precision == "fp32" and brick == (0, 0, 0) and not args.tile
+                       and pairs)
+    traffic = measured_traffic() if headline_layout else None
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     result = {
         "metric": "ray-samples/s",
@@ -268,6 +274,7 @@ def main():
         "config": {"workload": "realistic frame: 2ch u16-12 512x512x64 cells+vessels, "
                                "perspective stereo 1920x1080 per eye, step 1, alpha 0.99",
                    "eyes": 2, "width": sc.width, "height": sc.height, "brick": list(brick),
+                   "layout": args.layout, "storage_bytes": vol.bytes,
                    "tile": args.tile or "8,8",
                    "samples_per_step": samples_per_step},
         "stereo_fps": args.steps / wall,
@@ -275,7 +282,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "traffic_unit": "bytes/launch (L2-to-fabric FETCH_SIZE + WRITE_SIZE, "
                                      "copy-calibrated)",
-                     "kernel": f"render_kernel<2ch,u16,{args.precision}>",
+                     "kernel": f"render_kernel<2ch,u16,{args.precision},{args.layout}>",
                      "kernel_ms": kernel_ms, "bytes_per_launch": alg_bytes},
     }
     vol.destroy()

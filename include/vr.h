@@ -75,7 +75,17 @@ typedef struct {
                            (all channels of a voxel, 1, 2, 4 or 8 bytes):
                            16 x 16 x 8 for 1-byte, 8 x 16 x 8 for 2- and
                            4-byte, 8 x 8 x 8 for 8-byte words.  Fixed at
-                           creation.                                          */
+                           creation.  With row_pairs the default is
+                           4 x 16 x 16.                                       */
+    int32_t row_pairs;  /* 0: default layout.  1: store each brick row next to
+                           the row after it (4-byte words only: 2 channels of
+                           uint16, 3 or 4 of uint8), so a sample's eight taps
+                           take two 16-byte loads instead of four 8-byte
+                           ones.  Storage: 2 (Bx + 1) By (Bz + 1) words per
+                           brick, 2.7x the raw voxels for 4 x 16 x 16 bricks
+                           against 1.3x for the default layout, before
+                           padding (see vr_volume_storage_bytes).  Images are
+                           the same bit for bit either way.                   */
 } vr_volume_desc;
 
 /* One channel's transfer function (User Interface, transfer-function

@@ -44,7 +44,7 @@ class vr_volume_desc(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("channels", C.c_int32), ("frames", C.c_int32), ("dtype", C.c_int32),
                 ("bits", C.c_int32), ("spacing", C.c_float * 3), ("origin", C.c_float * 3),
-                ("brick", C.c_int32 * 3)]
+                ("brick", C.c_int32 * 3), ("row_pairs", C.c_int32)]
 
 
 class vr_transfer(C.Structure):
@@ -274,13 +274,14 @@ class Volume:
     """A resident series in torch-allocated device storage."""
 
     def __init__(self, ctx: Context, dims, channels, frames=1, dtype=VR_U8, bits=None,
-                 spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), brick=(0, 0, 0)):
+                 spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), brick=(0, 0, 0),
+                 row_pairs=False):
         import torch
         nx, ny, nz = dims
         bits = bits if bits is not None else (8 if dtype == VR_U8 else 16)
         self.desc = vr_volume_desc(nx, ny, nz, channels, frames, dtype, bits,
                                    (C.c_float * 3)(*spacing), (C.c_float * 3)(*origin),
-                                   (C.c_int32 * 3)(*brick))
+                                   (C.c_int32 * 3)(*brick), int(bool(row_pairs)))
         self.bytes = vr_volume_storage_bytes(self.desc)
         self.storage = torch.empty(self.bytes + 256, dtype=torch.uint8,
                                    device=f"cuda:{ctx.device}")

@@ -58,6 +58,12 @@ static void brick_edges(const vr_volume_desc& d, int b[3]) {
         return;
     }
     const int w = word_bytes(d.channels, d.dtype == VR_U16);
+    if (d.row_pairs) {  // measured: narrow pair rows, deep bricks
+        b[0] = 4;
+        b[1] = 16;
+        b[2] = 16;
+        return;
+    }
     b[0] = w == 1 ? 16 : 8;
     b[1] = w == 8 ? 8 : 16;
     b[2] = 8;
@@ -74,8 +80,9 @@ BrickGeom make_geom(const vr_volume_desc& d) {
         g.nb[a] = (n[a] + 1 + b[a] - 1) / b[a];
         g.clamp_hi[a] = std::nextafter((float)(n[a] + 1), 0.0f);
     }
-    g.row = b[0] + 1;
-    g.plane = (b[0] + 1) * (b[1] + 1);
+    g.pairs = d.row_pairs ? 1 : 0;
+    g.row = g.pairs ? 2 * (b[0] + 1) : b[0] + 1;
+    g.plane = g.pairs ? b[1] * g.row : (b[1] + 1) * g.row;
     g.brick = g.plane * (b[2] + 1);
     g.word = word_bytes(d.channels, d.dtype == VR_U16);
     const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
@@ -103,6 +110,11 @@ vr_status check_desc(const vr_volume_desc* d) {
         if (!(d->spacing[a] > 0.0f) || !std::isfinite(d->spacing[a]))
             return fail(VR_ERR_INVALID_ARG, "spacing[%d] must be finite and > 0", a);
     if (!finite3(d->origin)) return fail(VR_ERR_INVALID_ARG, "origin must be finite");
+    if (d->row_pairs != 0 && d->row_pairs != 1)
+        return fail(VR_ERR_INVALID_ARG, "row_pairs = %d is neither 0 nor 1", d->row_pairs);
+    if (d->row_pairs && word_bytes(d->channels, d->dtype == VR_U16) != 4)
+        return fail(VR_ERR_INVALID_ARG,
+                    "row pairs need 4-byte voxel words (2 channels of uint16, 3 or 4 of uint8)");
     const bool dflt = d->brick[0] == 0 && d->brick[1] == 0 && d->brick[2] == 0;
     if (!dflt)
         for (int a = 0; a < 3; ++a)
@@ -257,7 +269,8 @@ void make_params(const vr_render_req& r, const vr_transfer* tf_in, ReqParams* P)
     P->g = v.geom;
     P->vox = v.storage + (uint64_t)r.frame * v.geom.frame_bytes;
     P->channels = d.channels;
-    P->variant = variant_index(d.channels, d.dtype == VR_U16, r.precision == VR_FP16);
+    P->variant = variant_index(d.channels, d.dtype == VR_U16, r.precision == VR_FP16,
+                               v.geom.pairs != 0);
 
     const double full = std::ldexp(1.0, d.bits) - 1.0;
     for (int c = 0; c < d.channels; ++c) {
@@ -511,7 +524,8 @@ vr_status vr_debug_sample(vr_volume* vol, int32_t frame, const float* pts, int32
     P.g = vol->geom;
     P.vox = vol->storage + (uint64_t)frame * vol->geom.frame_bytes;
     P.channels = vol->desc.channels;
-    P.variant = variant_index(vol->desc.channels, vol->desc.dtype == VR_U16, false);
+    P.variant = variant_index(vol->desc.channels, vol->desc.dtype == VR_U16, false,
+                              vol->geom.pairs != 0);
     hipError_t e = launch_debug_sample(P, pts, n, out, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "debug sample launch");
     return ok();

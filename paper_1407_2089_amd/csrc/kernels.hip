@@ -4,6 +4,9 @@
 // library's C++ code calls; the block-map test hook sits after them.
 #include <hip/hip_runtime.h>
 
+#include <array>
+#include <utility>
+
 #include "../../include/vr_test.h"
 #include "kernels.h"
 #include "march.h"
@@ -13,7 +16,8 @@ namespace vr {
 // ------------------------------------------------------------- relayout
 // One thread per stored word of the frame: gathers the word's channels from
 // the linear [C][Z][Y][X] source (zero outside the grid), clamps them to the
-// declared bit depth and packs them side by side.
+// declared bit depth and packs them side by side.  In the row-pair layout a
+// word's brick-local row is its pair's row plus the word's parity.
 template <int C, bool U16>
 __global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* __restrict__ src,
                                                         uint8_t* __restrict__ dst, uint32_t maxval,
@@ -23,15 +27,15 @@ __global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* 
     const S* in = reinterpret_cast<const S*>(src);
     T* out = reinterpret_cast<T*>(dst);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint32_t bx_mask = (1u << g.shift[0]) - 1u;
-    (void)bx_mask;
     for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total_words; w += stride) {
         const uint32_t brick = (uint32_t)(w / (uint32_t)g.brick);
         const uint32_t rem = (uint32_t)(w - (uint64_t)brick * (uint32_t)g.brick);
         const uint32_t lz = rem / (uint32_t)g.plane;
         const uint32_t r2 = rem - lz * (uint32_t)g.plane;
-        const uint32_t ly = r2 / (uint32_t)g.row;
-        const uint32_t lx = r2 - ly * (uint32_t)g.row;
+        const uint32_t lr = r2 / (uint32_t)g.row;
+        const uint32_t e = r2 - lr * (uint32_t)g.row;
+        const uint32_t ly = g.pairs ? lr + (e & 1u) : lr;
+        const uint32_t lx = g.pairs ? e >> 1 : e;
         const uint32_t bx = brick % (uint32_t)g.nb[0];
         const uint32_t byz = brick / (uint32_t)g.nb[0];
         const uint32_t by = byz % (uint32_t)g.nb[1];
@@ -141,11 +145,18 @@ __global__ __launch_bounds__(kWave) void batch_kernel(const BatchWork* __restric
 }
 
 typedef void (*batch_fn)(const BatchWork*, const ReqParams*, const int32_t*);
-static const batch_fn kBatch[kVariants] = {
-    batch_kernel<0>, batch_kernel<1>, batch_kernel<2>, batch_kernel<3>,
-    batch_kernel<4>, batch_kernel<5>, batch_kernel<6>, batch_kernel<7>,
-    batch_kernel<8>, batch_kernel<9>, batch_kernel<10>, batch_kernel<11>,
-    batch_kernel<12>, batch_kernel<13>, batch_kernel<14>, batch_kernel<15>};
+
+// Kernel tables indexed by variant, null where the variant does not exist.
+template <int V> constexpr batch_fn batch_entry() {
+    if constexpr (variant_exists(V)) return batch_kernel<V>;
+    else return nullptr;
+}
+template <int... V>
+constexpr std::array<batch_fn, kVariants> batch_table(std::integer_sequence<int, V...>) {
+    return {{batch_entry<V>()...}};
+}
+static const std::array<batch_fn, kVariants> kBatch =
+    batch_table(std::make_integer_sequence<int, kVariants>{});
 
 // ------------------------------------------------------------ test hook
 template <int V>
@@ -156,8 +167,9 @@ __global__ __launch_bounds__(256) void debug_sample_kernel(ReqParams P, const fl
     if (i >= n) return;
     float x[C];
     const Sampler S = make_sampler(P.vox, P.g);
-    sample<C, Variant<V>::U16, Variant<V>::F16>(P.g, S, pts[3 * i], pts[3 * i + 1],
-                                                pts[3 * i + 2], x);
+    sample<C, Variant<V>::U16, Variant<V>::F16, Variant<V>::PAIRS>(P.g, S, pts[3 * i],
+                                                                    pts[3 * i + 1],
+                                                                    pts[3 * i + 2], x);
 #pragma unroll
     for (int c = 0; c < C; ++c) out[(size_t)i * C + c] = x[c];
 }
@@ -184,23 +196,22 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
 }
 
 typedef void (*render_fn)(ReqParams, TileShape, int, int);
-static const render_fn kRender[2][kVariants] = {
-    {render_kernel<0, false>, render_kernel<1, false>, render_kernel<2, false>,
-     render_kernel<3, false>, render_kernel<4, false>, render_kernel<5, false>,
-     render_kernel<6, false>, render_kernel<7, false>, render_kernel<8, false>,
-     render_kernel<9, false>, render_kernel<10, false>, render_kernel<11, false>,
-     render_kernel<12, false>, render_kernel<13, false>, render_kernel<14, false>,
-     render_kernel<15, false>},
-    {render_kernel<0, true>, render_kernel<1, true>, render_kernel<2, true>,
-     render_kernel<3, true>, render_kernel<4, true>, render_kernel<5, true>,
-     render_kernel<6, true>, render_kernel<7, true>, render_kernel<8, true>,
-     render_kernel<9, true>, render_kernel<10, true>, render_kernel<11, true>,
-     render_kernel<12, true>, render_kernel<13, true>, render_kernel<14, true>,
-     render_kernel<15, true>}};
+template <int V, bool kClear> constexpr render_fn render_entry() {
+    if constexpr (variant_exists(V)) return render_kernel<V, kClear>;
+    else return nullptr;
+}
+template <bool kClear, int... V>
+constexpr std::array<render_fn, kVariants> render_table(std::integer_sequence<int, V...>) {
+    return {{render_entry<V, kClear>()...}};
+}
+static const std::array<render_fn, kVariants> kRender[2] = {
+    render_table<false>(std::make_integer_sequence<int, kVariants>{}),
+    render_table<true>(std::make_integer_sequence<int, kVariants>{})};
 
 hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_skip,
                          hipStream_t s) {
-    if (P.variant < 0 || P.variant >= kVariants) return hipErrorInvalidValue;
+    if (P.variant < 0 || P.variant >= kVariants || !kRender[0][P.variant])
+        return hipErrorInvalidValue;
     if (ts.wave_w <= 0 || ts.wave_h <= 0 || ts.wave_w * ts.wave_h != kWave)
         return hipErrorInvalidValue;
     const int tiles_x = (P.width + ts.wave_w - 1) / ts.wave_w;
@@ -221,6 +232,7 @@ hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
     if (blocks <= 0) return hipErrorInvalidValue;
     for (int v = 0; v < kVariants; ++v) {
         if (!(mask & (1u << v))) continue;
+        if (!kBatch[v]) return hipErrorInvalidValue;
         hipLaunchKernelGGL(kBatch[v], dim3(blocks), dim3(kWave), 0, s, dev_work, dev_reqs,
                            dev_prefix);
         const hipError_t e = hipGetLastError();
@@ -230,17 +242,21 @@ hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
 }
 
 typedef void (*debug_fn)(ReqParams, const float*, int, float*);
-static const debug_fn kDebug[kVariants] = {
-    debug_sample_kernel<0>, debug_sample_kernel<1>, debug_sample_kernel<2>,
-    debug_sample_kernel<3>, debug_sample_kernel<4>, debug_sample_kernel<5>,
-    debug_sample_kernel<6>, debug_sample_kernel<7>, debug_sample_kernel<8>,
-    debug_sample_kernel<9>, debug_sample_kernel<10>, debug_sample_kernel<11>,
-    debug_sample_kernel<12>, debug_sample_kernel<13>, debug_sample_kernel<14>,
-    debug_sample_kernel<15>};
+template <int V> constexpr debug_fn debug_entry() {
+    if constexpr (variant_exists(V)) return debug_sample_kernel<V>;
+    else return nullptr;
+}
+template <int... V>
+constexpr std::array<debug_fn, kVariants> debug_table(std::integer_sequence<int, V...>) {
+    return {{debug_entry<V>()...}};
+}
+static const std::array<debug_fn, kVariants> kDebug =
+    debug_table(std::make_integer_sequence<int, kVariants>{});
 
 hipError_t launch_debug_sample(const ReqParams& P, const float* pts, int n, float* out,
                                hipStream_t s) {
-    if (P.variant < 0 || P.variant >= kVariants) return hipErrorInvalidValue;
+    if (P.variant < 0 || P.variant >= kVariants || !kDebug[P.variant])
+        return hipErrorInvalidValue;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(kDebug[P.variant], dim3((n + 255) / 256), dim3(256), 0, s, P, pts, n,
                        out);

@@ -126,6 +126,17 @@ template <> __device__ __forceinline__ uint2 load_word<uint2>(__amdgpu_buffer_rs
     return make_uint2(w.x, w.y);
 }
 
+// Four consecutive 4-byte words (the row-pair layout's taps of one plane):
+// one 16-byte load.
+template <typename T> struct Quad { T w[4]; };
+template <typename T>
+__device__ __forceinline__ Quad<T> load_quad(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ Quad<uint32_t> load_quad<uint32_t>(__amdgpu_buffer_rsrc_t r,
+                                                                          uint32_t v, uint32_t s) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)v, (int)s, 0);
+    return Quad<uint32_t>{{a.x, a.y, a.z, a.w}};
+}
 // floor(x) converted to int in one instruction (register-only).
 __device__ __forceinline__ int cvt_floor(float x) {
     int r;
@@ -160,7 +171,8 @@ template <typename T> struct Taps {
 };
 
 // Locate the taps around a point given in stored coordinates (index-space
-// position + 1) and issue their loads.  The point is clamped into [0, n + 1)
+// position + 1) and issue their loads (PAIRS: the row-pair layout, two quad
+// loads; otherwise four x-pair loads, one per row).  The point is clamped into [0, n + 1)
 // per axis (it lies in the box [0, n + 1] up to rounding; a point on the
 // upper face is evaluated at the largest float below n + 1: one float step,
 // about (n + 1) * 6e-8 voxels, inside the face where the field is zero).  The low corner floor(q) then
@@ -168,7 +180,7 @@ template <typename T> struct Taps {
 // from the same value, so they always agree.  Every factor and partial sum of
 // the word index is below 2^24 (a frame holds < 2^31 words and a brick >= 125
 // of them), so 24-bit multiply-adds are exact.
-template <typename T>
+template <typename T, bool PAIRS>
 __device__ __forceinline__ Taps<T> fetch(const BrickGeom& g, const Sampler& S, float qx,
                                          float qy, float qz) {
     Taps<T> t;
@@ -189,10 +201,24 @@ __device__ __forceinline__ Taps<T> fetch(const BrickGeom& g, const Sampler& S, f
     const uint32_t bz = s[2] >> g.shift[2], lz = s[2] & ((1u << g.shift[2]) - 1u);
     uint32_t brick = __umul24(bz, (uint32_t)g.nb[1]) + by;
     brick = __umul24(brick, (uint32_t)g.nb[0]) + bx;
-    uint32_t local = __umul24(lz, (uint32_t)g.plane) + lx;
+    uint32_t local = __umul24(lz, (uint32_t)g.plane) + (PAIRS ? lx << 1 : lx);
     local = __umul24(ly, (uint32_t)g.row) + local;
     constexpr uint32_t W = sizeof(T);
     const uint32_t o = (__umul24(brick, (uint32_t)g.brick) + local) * W;
+    if constexpr (PAIRS) {
+        // Words (x, y), (x, y + 1), (x + 1, y), (x + 1, y + 1) of each plane.
+        const Quad<T> a = load_quad<T>(S.rsrc, o, 0);
+        const Quad<T> b = load_quad<T>(S.rsrc, o, S.plane_b);
+        t.w000 = a.w[0];
+        t.w010 = a.w[1];
+        t.w100 = a.w[2];
+        t.w110 = a.w[3];
+        t.w001 = b.w[0];
+        t.w011 = b.w[1];
+        t.w101 = b.w[2];
+        t.w111 = b.w[3];
+        return t;
+    }
     t.w000 = load_word<T>(S.rsrc, o, 0);
     t.w100 = load_word<T>(S.rsrc, o + W, 0);
     t.w010 = load_word<T>(S.rsrc, o, S.row_b);
@@ -327,17 +353,18 @@ __device__ __forceinline__ bool transparent(const Taps<T>& t, const Transparent&
 }
 
 // Trilinear field (raw units) of every channel at index-space point p.
-template <int C, bool U16, bool F16>
+template <int C, bool U16, bool F16, bool PAIRS>
 __device__ __forceinline__ void sample(const BrickGeom& g, const Sampler& S, float px, float py,
                                        float pz, float (&x)[C]) {
     using T = typename WordT<C, U16>::T;
-    interpolate<C, U16, F16>(fetch<T>(g, S, px + 1.0f, py + 1.0f, pz + 1.0f), x);
+    interpolate<C, U16, F16>(fetch<T, PAIRS>(g, S, px + 1.0f, py + 1.0f, pz + 1.0f), x);
 }
 
 template <int V> struct Variant {
     static constexpr int C = (V & 3) + 1;
     static constexpr bool U16 = (V & 4) != 0;
     static constexpr bool F16 = (V & 8) != 0;
+    static constexpr bool PAIRS = (V & 16) != 0;
 };
 
 // One pixel of one eye: returns nothing, writes RGBA (and the sample count).
@@ -348,6 +375,7 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
     constexpr int C = Variant<V>::C;
     constexpr bool U16 = Variant<V>::U16;
     constexpr bool F16 = Variant<V>::F16;
+    constexpr bool PAIRS = Variant<V>::PAIRS;
 
     const float sx = fmaf((float)px + 0.5f, P.sx_scale, -1.0f);
     const float sy = fmaf(-((float)py + 0.5f), P.sy_scale, 1.0f);
@@ -438,8 +466,8 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
     };
     auto fetch_at = [&](int j) -> Taps<Word> {
         const float sj = fmaf((float)j, P.step, half_step);
-        return fetch<Word>(P.g, S, fmaf(sj, d[0], pe[0]), fmaf(sj, d[1], pe[1]),
-                           fmaf(sj, d[2], pe[2]));
+        return fetch<Word, PAIRS>(P.g, S, fmaf(sj, d[0], pe[0]), fmaf(sj, d[1], pe[1]),
+                                  fmaf(sj, d[2], pe[2]));
     };
     if (n > 0) {
         // Software pipeline over pairs of samples: the taps of the next

@@ -14,11 +14,11 @@ constexpr int kMaxChannels = 4;
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kBlockThreads = 256;
 
-// Data variant of a request: channels (1..4), voxel width and sample precision.
-// Index = (channels - 1) + 4 * u16 + 8 * fp16.
-constexpr int kVariants = 16;
-inline constexpr int variant_index(int channels, bool u16, bool fp16) {
-    return (channels - 1) + (u16 ? 4 : 0) + (fp16 ? 8 : 0);
+// Data variant of a request: channels (1..4), voxel width, sample precision
+// and storage layout.  Index = (channels - 1) + 4 u16 + 8 fp16 + 16 pairs.
+constexpr int kVariants = 32;
+inline constexpr int variant_index(int channels, bool u16, bool fp16, bool pairs) {
+    return (channels - 1) + (u16 ? 4 : 0) + (fp16 ? 8 : 0) + (pairs ? 16 : 0);
 }
 
 // Bytes of one stored voxel word: all channels of a voxel side by side, the
@@ -27,19 +27,33 @@ inline constexpr int word_bytes(int channels, bool u16) {
     return (channels == 1 ? 1 : channels == 2 ? 2 : 4) * (u16 ? 2 : 1);
 }
 
+// The row-pair layout exists for 4-byte words only: four of them make one
+// 16-byte load.  (Narrower words would need unaligned loads; for 8-byte words
+// a plane's four taps already take two 16-byte loads without pairs.)
+inline constexpr bool variant_exists(int v) {
+    return !(v & 16) || word_bytes((v & 3) + 1, (v & 4) != 0) == 4;
+}
+
 // Brick-major layout of one frame.  Stored coordinates s = i + 1 run over
 // [0, n + 1] per axis (voxel -1 and voxel n are zero padding).  A trilinear
 // sample at index-space p reads the 2x2x2 words starting at s0 = floor(p + 1)
 // in [0, n]; bricks tile those origins B at a time and store B + 1 words per
 // axis (one-word halo on the high side) so all eight taps sit in one brick.
+//
+// Row pairs (optional): a brick plane stores, for each local row ly in
+// [0, By), rows ly and ly + 1 interleaved word by word, (x, ly), (x, ly + 1)
+// for x = 0 .. Bx.  The four taps of a sample in one plane are then four
+// consecutive words (one or two wide loads per plane instead of two narrow
+// ones per row), at the price of storing every inner row twice.
 struct BrickGeom {
     int32_t n[3];       // voxels per axis
     int32_t shift[3];   // log2 of the brick edge per axis
     int32_t nb[3];      // bricks per axis = ceil((n + 1) / B)
-    int32_t row;        // words per brick row   = Bx + 1
-    int32_t plane;      // words per brick plane = (Bx + 1)(By + 1)
-    int32_t brick;      // words per brick       = (Bx + 1)(By + 1)(Bz + 1)
+    int32_t row;        // words per brick row = Bx + 1 (pairs: 2 (Bx + 1))
+    int32_t plane;      // words per brick plane = (By + 1) row (pairs: By row)
+    int32_t brick;      // words per brick = (Bz + 1) plane
     int32_t word;       // bytes per word
+    int32_t pairs;      // 1: row-pair layout
     float clamp_hi[3];  // largest float below n + 1 per axis
     uint64_t frame_bytes; // bytes per frame, multiple of 256
 };

@@ -13,12 +13,12 @@ def to_device(vol_np):
     return torch.from_numpy(arr).cuda()
 
 
-def make_volume(ctx, scene, brick=(0, 0, 0), data=None, frames=1):
+def make_volume(ctx, scene, brick=(0, 0, 0), data=None, frames=1, row_pairs=False):
     data = scene.volume if data is None else data
     c, nz, ny, nx = data.shape
     dtype = vr.VR_U8 if data.dtype == np.uint8 else vr.VR_U16
     v = vr.Volume(ctx, (nx, ny, nz), c, frames, dtype, scene.bits, scene.spacing, scene.origin,
-                  brick)
+                  brick, row_pairs)
     v.upload(0, to_device(data))
     for ch, tf in enumerate(scene.tfs):
         v.set_transfer(ch, tf)
@@ -42,13 +42,13 @@ def alloc_out(scene):
     return out, smp
 
 
-def render(ctx, scene, precision=vr.VR_FP32, brick=(0, 0, 0), vol=None):
+def render(ctx, scene, precision=vr.VR_FP32, brick=(0, 0, 0), vol=None, row_pairs=False):
     """Render a scene through vr_render; returns (rgba [eyes][H][W][4],
     samples [eyes][H][W]) as numpy."""
     import torch
     own = vol is None
     if own:
-        vol = make_volume(ctx, scene, brick)
+        vol = make_volume(ctx, scene, brick, row_pairs=row_pairs)
     try:
         out, smp = alloc_out(scene)
         req = request_for(vol, scene, out, smp, precision)

@@ -31,9 +31,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def desc(nx=64, ny=48, nz=20, ch=2, frames=3, dtype=vr.VR_U16, bits=12, brick=(0, 0, 0),
-         spacing=(1.0, 1.0, 1.0)):
+         spacing=(1.0, 1.0, 1.0), row_pairs=0):
     return vr.vr_volume_desc(nx, ny, nz, ch, frames, dtype, bits, (C.c_float * 3)(*spacing),
-                             (C.c_float * 3)(0, 0, 0), (C.c_int32 * 3)(*brick))
+                             (C.c_float * 3)(0, 0, 0), (C.c_int32 * 3)(*brick), row_pairs)
 
 
 @pytest.mark.parametrize("dims,ch,dtype,brick", [
@@ -51,6 +51,33 @@ def test_storage_bytes_follow_brick_layout(dims, ch, dtype, brick):
     frame = nb[0] * nb[1] * nb[2] * per_brick * word
     frame = (frame + 255) // 256 * 256
     assert vr.vr_volume_storage_bytes(d) == 3 * frame
+
+
+@pytest.mark.parametrize("dims,ch,dtype,brick", [
+    ((64, 48, 20), 2, vr.VR_U16, (16, 16, 16)),
+    ((100, 37, 9), 3, vr.VR_U8, (8, 16, 4)),
+    ((512, 512, 64), 2, vr.VR_U16, (0, 0, 0)),
+    ((7, 5, 3), 4, vr.VR_U8, (4, 4, 4)),
+])
+def test_storage_bytes_of_the_row_pair_layout(dims, ch, dtype, brick):
+    """Row pairs: a brick plane holds By pairs of rows, 2 (Bx + 1) words each."""
+    d = desc(*dims, ch=ch, frames=2, dtype=dtype, bits=8 if dtype == vr.VR_U8 else 16,
+             brick=brick, row_pairs=1)
+    word = 4
+    brick = brick if brick != (0, 0, 0) else (4, 16, 16)
+    nb = [math.ceil((n + 1) / b) for n, b in zip(dims, brick)]
+    per_brick = brick[1] * 2 * (brick[0] + 1) * (brick[2] + 1)
+    frame = nb[0] * nb[1] * nb[2] * per_brick * word
+    frame = (frame + 255) // 256 * 256
+    assert vr.vr_volume_storage_bytes(d) == 2 * frame
+
+
+@pytest.mark.parametrize("ch,dtype,bits,row_pairs", [
+    (1, vr.VR_U8, 8, 1), (2, vr.VR_U8, 8, 1), (1, vr.VR_U16, 12, 1), (2, vr.VR_U16, 12, 2),
+    (4, vr.VR_U8, 8, -1), (3, vr.VR_U16, 16, 1), (4, vr.VR_U16, 12, 1)])
+def test_row_pairs_need_wide_words_and_a_flag(ch, dtype, bits, row_pairs):
+    with pytest.raises(vr.VrError):
+        vr.vr_volume_storage_bytes(desc(ch=ch, dtype=dtype, bits=bits, row_pairs=row_pairs))
 
 
 @pytest.mark.parametrize("ch,dtype,bits,brick", [

@@ -68,19 +68,23 @@ def test_linear_field_and_voxel_centres(ctx, brick):
     v.destroy()
 
 
-@pytest.mark.parametrize("ch,dtype,bits", [(1, np.uint8, 8), (2, np.uint8, 8), (3, np.uint8, 8),
-                                           (4, np.uint8, 8), (1, np.uint16, 16),
-                                           (2, np.uint16, 12), (3, np.uint16, 12),
-                                           (4, np.uint16, 16)])
-def test_sampler_matches_oracle_everywhere_in_box(ctx, ch, dtype, bits):
+SAMPLER_CASES = [(1, np.uint8, 8, False), (2, np.uint8, 8, False), (3, np.uint8, 8, False),
+                 (4, np.uint8, 8, False), (1, np.uint16, 16, False), (2, np.uint16, 12, False),
+                 (3, np.uint16, 12, False), (4, np.uint16, 16, False),
+                 (3, np.uint8, 8, True), (4, np.uint8, 8, True), (2, np.uint16, 12, True),
+                 (2, np.uint16, 16, True)]
+
+
+@pytest.mark.parametrize("ch,dtype,bits,row_pairs", SAMPLER_CASES)
+def test_sampler_matches_oracle_everywhere_in_box(ctx, ch, dtype, bits, row_pairs):
     import oracle
     import torch
-    log(f"sampler ch={ch} {dtype.__name__}")
+    log(f"sampler ch={ch} {dtype.__name__} row_pairs={row_pairs}")
     nx, ny, nz = 19, 13, 11
     data = scenes.random_volume(ch, (ch, nz, ny, nx), dtype, 1 << bits)
     sc = Scene("rnd", data, bits, [TF()] * ch, scenes.ortho_down_z(nx, ny, 8, 8, 8.0), 8, 8,
                False, 1.0, 1.0)
-    v = gpu.make_volume(ctx, sc, (8, 4, 8))
+    v = gpu.make_volume(ctx, sc, (8, 4, 8), row_pairs=row_pairs)
     rng = np.random.default_rng(ch)
     pts = rng.uniform([-1, -1, -1], [nx, ny, nz], size=(8192, 3)).astype(np.float32)
     # faces and corners of the extended box
@@ -236,6 +240,26 @@ def test_p7_channel_permutation_on_gpu(ctx):
 
 
 # --------------------------------------------------------- layouts
+
+@pytest.mark.parametrize("ch,dtype,bits", [(3, np.uint8, 8), (4, np.uint8, 8), (2, np.uint16, 12),
+                                           (2, np.uint16, 16)])
+@pytest.mark.parametrize("brick", [(0, 0, 0), (4, 8, 16), (16, 4, 8), (32, 32, 4)])
+def test_row_pair_layout_gives_the_same_images(ctx, ch, dtype, bits, brick):
+    """Row pairs change where the taps are stored, not their values: images
+    and sample counts are bitwise those of the default layout, FP32 and FP16."""
+    nx, ny, nz = 45, 38, 27
+    vol = np.zeros((ch, nz, ny, nx), dtype)
+    for c in range(ch):
+        vol[c] = synth.cells_and_vessels((nx, ny, nz), 1, bits, 30 + c, n_cells=6, n_tubes=2)[0]
+    tfs = [TF(0.08 + 0.03 * c, 0.8, 0.1 * c, 1.0, (1.0 - 0.2 * c, 0.3 * c, 0.5)) for c in range(ch)]
+    cam = synth.orbit_camera((nx, ny, nz), 35.0 + 20 * ch, 25.0, 45.0)
+    sc = Scene("pairs", vol, bits, tfs, cam, 70, 52, True, 0.9, 0.99)
+    for precision in (vr.VR_FP32, vr.VR_FP16):
+        a = gpu.render(ctx, sc, precision, brick)
+        b = gpu.render(ctx, sc, precision, brick, row_pairs=True)
+        assert np.array_equal(a[1], b[1])
+        assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
+
 
 @pytest.mark.parametrize("brick", [(4, 4, 4), (16, 16, 16), (32, 32, 32), (16, 16, 4)])
 def test_brick_shape_does_not_change_the_image(ctx, realistic, brick):
