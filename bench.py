@@ -158,7 +158,7 @@ def main():
                          "bricks (the library's default layout)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-gb", type=float, default=150.0)
-    ap.add_argument("--serve-rates", default="25,100,400,1000,1600,2400")
+    ap.add_argument("--serve-rates", default="25,100,400,1000,1600,2400,3200,4000")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "

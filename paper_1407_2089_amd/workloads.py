@@ -214,12 +214,17 @@ def layout_sweep(ctx, reps=30):
              "side": synth.orbit_camera(dims, 75.0, 10.0, 45.0)}
     bricks = [(4, 4, 4), (8, 8, 8), (16, 16, 16), (4, 8, 8), (8, 4, 8), (8, 8, 4), (8, 16, 8),
               (16, 8, 8), (16, 16, 8), (32, 8, 8), (0, 0, 0)]
+    # row pairs exist for 4-byte words (2-channel u16, 4-channel u8)
+    pair_bricks = [(0, 0, 0), (4, 16, 8), (4, 8, 8), (8, 16, 8), (4, 32, 8), (8, 8, 8)]
     out = torch.empty((2, H, W, 4), dtype=torch.float32, device="cuda")
     rows = []
     for ch, bits in ((1, 8), (2, 12), (4, 8), (4, 16)):
         frame = synth.DeviceSeries(dims, ch, bits, 77).frame(0)
-        for b in bricks:
-            vol = Volume(ctx, dims, ch, 1, VR_U8 if bits == 8 else VR_U16, bits, brick=b)
+        wide = (ch == 2 and bits > 8) or (ch == 4 and bits == 8)
+        cases = [(b, False) for b in bricks] + ([(b, True) for b in pair_bricks] if wide else [])
+        for b, pairs in cases:
+            vol = Volume(ctx, dims, ch, 1, VR_U8 if bits == 8 else VR_U16, bits, brick=b,
+                         row_pairs=pairs)
             vol.upload(0, frame)
             for c, tf in enumerate(default_tfs(ch)):
                 vol.set_transfer(c, tf)
@@ -233,9 +238,11 @@ def layout_sweep(ctx, reps=30):
                     vr_render(ctx.ptr, req)
                 e1.record()
                 torch.cuda.synchronize()
-                rows.append({"channels": ch, "bits": bits, "brick": list(b), "view": name,
-                             "ms": e0.elapsed_time(e1) / reps, "storage_bytes": vol.bytes})
-                log(f"  ch {ch} bits {bits} brick {b} {name}: {rows[-1]['ms']:.4f} ms")
+                rows.append({"channels": ch, "bits": bits, "brick": list(b), "row_pairs": pairs,
+                             "view": name, "ms": e0.elapsed_time(e1) / reps,
+                             "storage_bytes": vol.bytes})
+                log(f"  ch {ch} bits {bits} brick {b} pairs {pairs} {name}: "
+                    f"{rows[-1]['ms']:.4f} ms")
             vol.destroy()
     return {"workload": "layout sweep: 512x512x64, stereo 1920x1080, step 1, alpha 0.99",
             "rows": rows}
@@ -262,7 +269,7 @@ class _Pool:
 
 
 def serving(ctx, total_gb=150.0, seconds=10.0, warm=1.0,
-            rates=(25, 100, 400, 1000, 1600, 2400), seed=5, n_datasets=16, check=32,
+            rates=(25, 100, 400, 1000, 1600, 2400, 3200, 4000), seed=5, n_datasets=16, check=32,
             max_inflight=128):
     """16 resident datasets (2-4 channels, 24-96 frames of up to
     1024x1024x64 uint16-12, frame counts scaled to `total_gb` resident);
