@@ -35,7 +35,7 @@ def render_kernel_hash():
     with open(os.path.join(csrc, "kernels.hip")) as fh:
         k = fh.read()
     a = k.index("// ------------------------------------------------------------ plain render")
-    b = k.index("// ------------------------------------------------------- persistent batch")
+    b = k.index("// -------------------------------------------------------- batched render")
     h.update(k[a:b].encode())
     return h.hexdigest()
 

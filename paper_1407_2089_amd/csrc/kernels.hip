@@ -1,7 +1,7 @@
 // HIP kernels for gfx950: frame relayout into bricks, the plain per-request
-// render launch, the persistent batched render launch, and the sampling test
-// hook.  Host-side launchers at the bottom are the only entry points the
-// library's C++ code calls; the block-map test hook sits after them.
+// render launch, the batched render launch, and the sampling test hook.
+// Host-side launchers at the bottom are the only entry points the library's
+// C++ code calls; the block-map test hook sits after them.
 #include <hip/hip_runtime.h>
 
 #include <array>
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kWave) void render_kernel(ReqParams P, TileShape ts
     render_pixel<V, kClear>(P, eye, valid ? px : 0, valid ? py : 0, valid);
 }
 
-// ------------------------------------------------------- persistent batch
+// -------------------------------------------------------- batched render
 // Work items are (request, eye, wave tile) triples numbered request by
 // request in the order the host laid the requests out (most expensive
 // first); prefix[q] is the first item of request q.  Each wave pulls items

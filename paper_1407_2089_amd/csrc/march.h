@@ -2,9 +2,9 @@
 // brick-major layout, per-channel transfer functions, front-to-back
 // compositing with early termination.  One lane owns one pixel of one eye.
 //
-// Every kernel that renders (the plain per-request launch and the persistent
-// batched launch) calls render_pixel<V>() below, so a pixel's arithmetic is
-// the same instruction sequence whichever way it was scheduled.
+// Every kernel that renders (the plain per-request launch and the batched
+// launch) calls render_pixel<V>() below, so a pixel's arithmetic is the same
+// instruction sequence whichever way it was scheduled.
 #pragma once
 #include <hip/hip_runtime.h>
 

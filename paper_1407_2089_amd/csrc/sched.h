@@ -218,14 +218,17 @@ class Scheduler {
 
     void loop() {
         std::unique_lock<std::mutex> lk(mu_);
+        uint64_t last_activity = now_ns();
         while (!stop_) {
             const bool changed = step();
             bool any_busy = false;
             for (bool b : busy_) any_busy = any_busy || b;
+            if (changed || any_busy) last_activity = now_ns();
             if (changed) continue;
-            if (any_busy) {
-                // Poll completions at a fine grain without holding the lock
-                // (a timed sleep would round up to tens of microseconds).
+            if (any_busy || now_ns() - last_activity < kSpinNs) {
+                // Poll completions and arrivals at a fine grain without
+                // holding the lock (a timed sleep, or a wake-up through the
+                // condition variable, costs tens of microseconds).
                 lk.unlock();
                 std::this_thread::yield();
                 lk.lock();
@@ -234,6 +237,10 @@ class Scheduler {
             }
         }
     }
+
+    // The loop keeps polling this long after its last activity before it
+    // sleeps on the condition variable.
+    static constexpr uint64_t kSpinNs = 2000000;
 
     Backend* backend_;
     int max_batch_;

@@ -48,14 +48,24 @@ class HipBackend : public Backend {
     }
     int slots() const override { return (int)slots_.size(); }
     vr_status launch(int slot, const std::vector<Job*>& jobs) override {
-        params_.resize(jobs.size());
-        for (size_t q = 0; q < jobs.size(); ++q) params_[q] = jobs[q]->params;
-        // The loop never stops to tune: a shape class tuned by vr_render_batch
-        // (or loaded from the cache file) is used, else the default tile.
-        vr_status st = batch_enqueue(ctx_, slots_[slot], params_.data(), (int)jobs.size(),
-                                     /*allow_tuning=*/false);
-        if (st != VR_OK) return st;
-        hipError_t e = hipEventRecord(events_[slot], streams_[slot]);
+        hipError_t e;
+        if (jobs.size() == 1) {
+            // A lone request takes the plain launch: its parameters travel as
+            // kernel arguments, with no table upload and no graph.
+            e = launch_render(jobs[0]->params, ctx_->plain_tile, ctx_->clear_skip,
+                              streams_[slot]);
+            if (e != hipSuccess) return hip_fail(e, "render launch");
+        } else {
+            params_.resize(jobs.size());
+            for (size_t q = 0; q < jobs.size(); ++q) params_[q] = jobs[q]->params;
+            // The loop never stops to tune: a shape class tuned by
+            // vr_render_batch (or loaded from the cache file) is used, else the
+            // default tile.
+            vr_status st = batch_enqueue(ctx_, slots_[slot], params_.data(), (int)jobs.size(),
+                                         /*allow_tuning=*/false);
+            if (st != VR_OK) return st;
+        }
+        e = hipEventRecord(events_[slot], streams_[slot]);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
         return VR_OK;
     }

@@ -1,4 +1,4 @@
-"""GPU: batched persistent launches and the serving loop give, for every
+"""GPU: batched launches and the serving loop give, for every
 request, exactly the image vr_render gives for it alone (bitwise), across
 graph replays, capacity growth and mixed volumes / channel counts / voxel
 types / precisions / sizes; FP16 sampling stays within 4e-3 of the oracle."""
@@ -35,18 +35,20 @@ def log(msg):
 
 
 def mixed_scenes(seed=21):
-    """Volumes of every channel count and voxel type, different shapes."""
+    """Volumes of every channel count and voxel type, different shapes, two
+    of them in the row-pair layout."""
     rng = np.random.default_rng(seed)
     out = []
-    specs = [(1, np.uint8, 8), (2, np.uint16, 12), (3, np.uint8, 8), (4, np.uint16, 16),
-             (2, np.uint8, 8), (1, np.uint16, 12)]
-    for q, (ch, dt, bits) in enumerate(specs):
+    specs = [(1, np.uint8, 8, False), (2, np.uint16, 12, False), (3, np.uint8, 8, False),
+             (4, np.uint16, 16, False), (2, np.uint8, 8, False), (1, np.uint16, 12, False),
+             (2, np.uint16, 12, True), (4, np.uint8, 8, True)]
+    for q, (ch, dt, bits, pairs) in enumerate(specs):
         dims = (int(rng.integers(20, 70)), int(rng.integers(20, 70)), int(rng.integers(8, 40)))
         vol = synth.cells_and_vessels(dims, ch, bits, seed + q, n_cells=6, n_tubes=2)
         tfs = [TF(float(rng.uniform(0.02, 0.1)), float(rng.uniform(0.3, 0.9)),
                   float(rng.uniform(-0.5, 0.5)), float(rng.uniform(0.5, 2.0)),
                   tuple(rng.uniform(0, 1, 3))) for _ in range(ch)]
-        out.append((vol, bits, tfs, dims))
+        out.append((vol, bits, tfs, dims, pairs))
     return out
 
 
@@ -54,9 +56,9 @@ def make_requests(ctx, n, seed=5):
     import torch
     rng = np.random.default_rng(seed)
     vols = []
-    for vol, bits, tfs, dims in mixed_scenes():
+    for vol, bits, tfs, dims, pairs in mixed_scenes():
         sc = Scene("m", vol, bits, tfs, None, 1, 1, False, 1.0, 1.0)
-        vols.append((gpu.make_volume(ctx, sc), dims))
+        vols.append((gpu.make_volume(ctx, sc, row_pairs=pairs), dims))
     reqs, outs = [], []
     for q in range(n):
         v, dims = vols[q % len(vols)]
@@ -173,7 +175,7 @@ def test_batch_matches_oracle(ctx):
     specs = mixed_scenes()
     rng = np.random.default_rng(9)
     for q, (r, (o, s)) in enumerate(zip(reqs, outs)):
-        vol, bits, tfs, dims = specs[q % len(specs)]
+        vol, bits, tfs, dims, _ = specs[q % len(specs)]
         cam = gpu_cam(r.cam)
         sc = Scene("b", vol, bits, tfs, cam, r.width, r.height, bool(r.stereo), r.step,
                    r.term_alpha, tuple(r.background))
