@@ -239,20 +239,28 @@ static int32_t transparent_max(float scale, float bias, uint32_t full) {
 }
 
 // Thresholds of the transparent-sample test: a channel whose alpha
-// multiplier is 0 (or that is hidden) never makes a sample opaque.
+// multiplier is 0 (or that is hidden) never makes a sample opaque.  The test
+// is switched off when the opaque-capable channels all have thresholds below
+// 1 (floors at zero): then only all-zero taps could pass it, too rarely to
+// pay for it.
 static Transparent make_transparent(const ReqParams& P, uint32_t full) {
     Transparent t{};
     t.ok = 1;
+    bool any = false, useful = false;
     for (int c = 0; c < kMaxChannels; ++c) {
         int32_t m = 65535;
-        if (c < P.channels && P.tf[c].alpha_mul != 0.0f)
+        if (c < P.channels && P.tf[c].alpha_mul != 0.0f) {
             m = transparent_max(P.tf[c].scale, P.tf[c].bias, full);
+            any = true;
+            useful = useful || m >= 1;
+        }
         if (m < 0) {
             t.ok = 0;
             m = 0;
         }
         t.tmax[c] = (uint32_t)m;
     }
+    if (any && !useful) t.ok = 0;
     t.tmax2[0] = t.tmax[0] | t.tmax[1] << 16;
     t.tmax2[1] = t.tmax[2] | t.tmax[3] << 16;
     return t;
