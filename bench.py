@@ -283,7 +283,11 @@ def main():
                      "traffic_unit": "bytes/launch (L2-to-fabric FETCH_SIZE + WRITE_SIZE, "
                                      "copy-calibrated)",
                      "kernel": f"render_kernel<2ch,u16,{args.precision},{args.layout}>",
-                     "kernel_ms": kernel_ms, "bytes_per_launch": alg_bytes},
+                     "kernel_ms": kernel_ms, "bytes_per_launch": alg_bytes,
+                     # effective bytes price every tap as an HBM byte; the measured
+                     # fabric-side rate of the same launches, for comparison:
+                     "traffic_GBps": (traffic / (kernel_ms * 1e-3) / 1e9
+                                      if traffic is not None else None)},
     }
     vol.destroy()
     ctx.close()

@@ -36,6 +36,14 @@ vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h);
  * are the same either way.  on = 1 (the default) restores the skip. */
 vr_status vr_test_clear_skip(vr_ctx* ctx, int32_t on);
 
+/* Transparent-sample threshold of one channel with floor lo and ceiling hi
+ * on bits-bit data: the folded transfer-function constants the kernels use
+ * (u = clamp(raw * scale + bias, 0, 1)) and the largest raw tap value tmax
+ * for which every field value interpolated from taps <= tmax gives u = 0 in
+ * the kernels' FP32 arithmetic (-1 if none).  Pure host computation. */
+vr_status vr_test_transparent_max(float lo, float hi, int32_t bits, float* scale, float* bias,
+                                  int32_t* tmax);
+
 /* Position in a launch's tile order (super-tile by super-tile) that
  * hardware block b of a launch of nblocks single-wave blocks takes, for
  * b = 0 .. nblocks - 1, written to tiles[b] (host memory).  Pure host

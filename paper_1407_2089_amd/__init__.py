@@ -104,6 +104,8 @@ def lib():
             "vr_test_plain_tile": [P, C.c_int32, C.c_int32],
             "vr_test_block_map": [C.c_int32, C.c_void_p],
             "vr_test_clear_skip": [P, C.c_int32],
+            "vr_test_transparent_max": [C.c_float, C.c_float, C.c_int32, C.POINTER(C.c_float),
+                                        C.POINTER(C.c_float), C.POINTER(C.c_int32)],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -219,6 +221,14 @@ def vr_test_plain_tile(ctx, wave_w=0, wave_h=0):
 
 def vr_test_clear_skip(ctx, on: bool):
     _check(lib().vr_test_clear_skip(ctx, int(bool(on))))
+
+
+def vr_test_transparent_max(lo: float, hi: float, bits: int):
+    """(scale, bias, tmax) of the transparent-sample test (host-only)."""
+    scale, bias, tmax = C.c_float(), C.c_float(), C.c_int32()
+    _check(lib().vr_test_transparent_max(lo, hi, bits, C.byref(scale), C.byref(bias),
+                                         C.byref(tmax)))
+    return scale.value, bias.value, tmax.value
 
 
 def vr_test_block_map(nblocks: int):

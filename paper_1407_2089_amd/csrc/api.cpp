@@ -266,6 +266,20 @@ static Transparent make_transparent(const ReqParams& P, uint32_t full) {
     return t;
 }
 
+extern "C" vr_status vr_test_transparent_max(float lo, float hi, int32_t bits, float* scale,
+                                             float* bias, int32_t* tmax) {
+    if (!(lo >= 0.0f) || !(hi <= 1.0f) || !(lo < hi) || bits < 8 || bits > 16 || !scale ||
+        !bias || !tmax)
+        return fail(VR_ERR_INVALID_ARG, "need 0 <= lo < hi <= 1, bits 8..16, outputs");
+    // The same folding as make_params.
+    const double full = std::ldexp(1.0, bits) - 1.0;
+    const double range = (double)hi - (double)lo;
+    *scale = (float)(1.0 / (full * range));
+    *bias = (float)(-(double)lo / range);
+    *tmax = transparent_max(*scale, *bias, (uint32_t)full);
+    return ok();
+}
+
 // Per-eye ray basis in double, rounded once to float.  Perspective: origin is
 // the eye e_s = center + s (sep / 2) r; the unnormalised direction to pixel
 // (sx, sy) is conv f - s (sep / 2) r + sx w r + sy h u.  Orthographic: the

@@ -273,3 +273,36 @@ def test_tile_hooks_validate_wave_tiles(vctx):
         for bad in ((8, 4), (0, 64), (-8, -8), (65, 1), (128, 0)):
             with pytest.raises(vr.VrError):
                 hook(vctx, *bad)
+
+
+def _f32_up(x):
+    """Smallest float32 >= x (x a Fraction or float)."""
+    from fractions import Fraction
+    f = np.float32(float(x))
+    if Fraction(float(f)) < Fraction(x):
+        f = np.nextafter(f, np.float32(np.inf))
+    return f
+
+
+@pytest.mark.parametrize("lo,hi,bits", [(0.0, 1.0, 8), (300 / 4095, 3000 / 4095, 12),
+                                        (24 / 255, 220 / 255, 8), (0.5, 0.6, 16),
+                                        (0.013, 0.9, 12), (0.999, 1.0, 16), (0.2, 0.21, 8)])
+def test_transparent_threshold_is_safe_and_tight(lo, hi, bits):
+    """The largest tap value T whose samples are skipped: every value up to
+    T (1 + 2^-6) (the interpolation error margin) gives u <= 0 in exact
+    arithmetic with the kernels' folded constants; T + 1 does not pass the
+    same test; and T sits just below the floor lo (2^bits - 1) of the
+    transfer-function definition."""
+    from fractions import Fraction as F
+    scale, bias, t = vr.vr_test_transparent_max(lo, hi, bits)
+    full = (1 << bits) - 1
+    s, b = F(float(np.float32(scale))), F(float(np.float32(bias)))
+    assert t >= 0
+    margin = F(1) + F(1, 64)
+    assert F(t) * margin * s + b <= 0
+    if t < full:
+        x = _f32_up(F(t + 1) * margin)
+        assert F(float(x)) * s + b > 0
+    floor_raw = F(float(np.float32(lo))) * full
+    assert t <= floor_raw
+    assert t >= floor_raw / margin - 2
