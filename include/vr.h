@@ -28,7 +28,9 @@
  *
  * Threads: calls on distinct volumes may run concurrently; vr_submit and
  * vr_poll are thread-safe; calls on one volume must not race with
- * vr_destroy_volume of that volume.
+ * vr_destroy_volume of that volume.  Every call that enqueues GPU work does so
+ * on the context's device, whatever device is current in the calling thread,
+ * and restores the caller's current device before it returns.
  */
 #ifndef VR_H
 #define VR_H

@@ -407,10 +407,7 @@ vr_status vr_init(int32_t device, uint64_t mem_budget_bytes, vr_ctx** out) {
         return fail(VR_ERR_UNSUPPORTED, "device %d is %s; this library is built for gfx950",
                     device, prop.gcnArchName);
     }
-    if ((e = hipSetDevice(device)) != hipSuccess) {
-        delete ctx;
-        return hip_fail(e, "hipSetDevice");
-    }
+    DeviceGuard dg(device);
     if (mem_budget_bytes == 0) {
         size_t free_b = 0, total_b = 0;
         if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) {
@@ -431,7 +428,7 @@ vr_status vr_shutdown(vr_ctx* ctx) {
     if (st != VR_OK) return st;
     if (ctx->volumes.load() != 0)
         return fail(VR_ERR_BUSY, "%d volumes are still alive", ctx->volumes.load());
-    if (ctx->device >= 0) (void)hipSetDevice(ctx->device);
+    DeviceGuard dg(ctx->device);
     for (auto& kv : ctx->batch_slots) batch_slot_destroy(kv.second);
     ctx->batch_slots.clear();
     delete ctx;
@@ -487,6 +484,7 @@ vr_status vr_upload_frame(vr_volume* vol, int32_t frame, const void* dev_src, vo
         return fail(VR_ERR_INVALID_ARG, "frame %d outside 0..%d", frame, vol->desc.frames - 1);
     if (!dev_src) return fail(VR_ERR_INVALID_ARG, "source is NULL");
     if (vol->ctx->device < 0) return fail(VR_ERR_UNSUPPORTED, "validation-only context");
+    DeviceGuard dg(vol->ctx->device);
     hipError_t e = launch_relayout(vol->geom, vol->desc.channels, vol->desc.dtype == VR_U16,
                                    vol->desc.bits, dev_src,
                                    vol->storage + (uint64_t)frame * vol->geom.frame_bytes,
@@ -528,6 +526,7 @@ vr_status vr_render(vr_ctx* ctx, const vr_render_req* req, void* hip_stream) {
         std::lock_guard<std::mutex> lk(req->vol->tf_mu);
         make_params(*req, req->vol->tf, &P);
     }
+    DeviceGuard dg(ctx->device);
     hipError_t e = launch_render(P, ctx->plain_tile, ctx->clear_skip, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return ok();
@@ -548,6 +547,7 @@ vr_status vr_debug_sample(vr_volume* vol, int32_t frame, const float* pts, int32
     P.channels = vol->desc.channels;
     P.variant = variant_index(vol->desc.channels, vol->desc.dtype == VR_U16, false,
                               vol->geom.pairs != 0);
+    DeviceGuard dg(vol->ctx->device);
     hipError_t e = launch_debug_sample(P, pts, n, out, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "debug sample launch");
     return ok();

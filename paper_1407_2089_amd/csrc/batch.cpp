@@ -1,8 +1,9 @@
 // Batched rendering: many requests (of different sizes, volumes, channel
-// counts and precisions) in one persistent launch.  Each (request, eye,
-// tile) is one work item; blocks claim items from a device counter, most
-// expensive request first, so one large view does not become the tail.  The
-// launch (counter reset + persistent kernel) is captured once per stream
+// counts and precisions) in one launch.  Each (request, eye, wave tile) is
+// one work item; the items of one data variant go to one kernel whose fixed
+// grid of single-wave blocks takes them cyclically, most expensive request
+// first, so one large view does not become the tail.  The launch (one kernel
+// per variant present) is captured per stream, variant set and grid size
 // into a HIP graph whose arguments point at fixed device tables; each batch
 // only rewrites the tables.
 #include <hip/hip_runtime.h>
@@ -385,6 +386,7 @@ extern "C" vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int
         std::lock_guard<std::mutex> lk(reqs[q].vol->tf_mu);
         make_params(reqs[q], reqs[q].vol->tf, &P[q]);
     }
+    DeviceGuard dg(ctx->device);
     vr_status st;
     BatchSlot* s = batch_slot_for(ctx, (hipStream_t)hip_stream, &st);
     if (!s) return st;

@@ -16,6 +16,24 @@
 
 namespace vr {
 
+// Makes the context's device current for the calling thread for the length
+// of one entry point, and restores the caller's device afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int device) {
+        if (device < 0 || hipGetDevice(&prev) != hipSuccess) {
+            prev = -1;
+            return;
+        }
+        if (prev == device || hipSetDevice(device) != hipSuccess) prev = -1;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    DeviceGuard(const DeviceGuard&) = delete;
+    DeviceGuard& operator=(const DeviceGuard&) = delete;
+};
+
 class Scheduler;
 
 // Workspace of batched launches on one stream: device tables that a captured
