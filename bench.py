@@ -40,21 +40,37 @@ def render_kernel_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM-side bytes per launch of the headline kernel from the committed
-    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain
-    copy's readings), or None once the kernel's source has changed since."""
+def measured_counters():
+    """From the committed rocprofv3 counter summary of the headline kernel:
+    HBM-side bytes per launch (FETCH_SIZE and WRITE_SIZE, scaled by a plain
+    copy's readings), VALU busy and TA busy fractions; an empty dict once the
+    kernel's source has changed since the counters were taken."""
     try:
         with open(COUNTERS) as fh:
             text = fh.read()
     except OSError:
-        return None
+        return {}
     import re
-    t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
     h = re.search(r"sha256 \(.*\):\s*([0-9a-f]{64})", text)
-    if not t or not h or h.group(1) != render_kernel_hash():
-        return None
-    return int(t.group(1))
+    if not h or h.group(1) != render_kernel_hash():
+        return {}
+    out = {}
+    t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    if t:
+        out["traffic"] = int(t.group(1))
+    v = re.search(r"VALUBusy ([0-9.]+) %", text)
+    if v:
+        out["valu_busy"] = float(v.group(1)) / 100.0
+    a = re.search(r"TA busy ([0-9.]+) %", text)
+    if a:
+        out["ta_busy"] = float(a.group(1)) / 100.0
+    return out
+
+
+def measured_traffic():
+    """HBM-side bytes per launch of the headline kernel (see
+    measured_counters), or None."""
+    return measured_counters().get("traffic")
 
 
 def log(msg):
@@ -256,7 +272,8 @@ def main():
     alg_bytes = samples_per_step * bytes_per_sample
     headline_layout = (args.precision == "fp32" and brick == (0, 0, 0) and not args.tile
                        and pairs)
-    traffic = measured_traffic() if headline_layout else None
+    counters = measured_counters() if headline_layout else {}
+    traffic = counters.get("traffic")
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     result = {
         "metric": "ray-samples/s",
@@ -287,7 +304,10 @@ def main():
                      # effective bytes price every tap as an HBM byte; the measured
                      # fabric-side rate of the same launches, for comparison:
                      "traffic_GBps": (traffic / (kernel_ms * 1e-3) / 1e9
-                                      if traffic is not None else None)},
+                                      if traffic is not None else None),
+                     # what does limit the kernel (rocprofv3 counters of the same launch)
+                     "valu_busy": counters.get("valu_busy"),
+                     "ta_busy": counters.get("ta_busy")},
     }
     vol.destroy()
     ctx.close()
