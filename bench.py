@@ -126,7 +126,7 @@ def tiny(args):
     from paper_1407_2089_amd import synth
     sc = synth.tiny_scene()
     ctx = vr.Context(0)
-    vol = vr.Volume(ctx, (64, 64, 32), 1, 1, vr.VR_U8, 8)
+    vol = vr.Volume(ctx, (64, 64, 32), 1, 1, vr.VR_U8, 8, row_pairs=args.layout == "pairs")
     vol.upload(0, torch.from_numpy(sc.volume).cuda())
     vol.set_transfer(0, sc.tfs[0])
     out = torch.empty((1, 256, 256, 4), dtype=torch.float32, device="cuda")
@@ -147,6 +147,7 @@ def tiny(args):
     vol.destroy()
     ctx.close()
     return {"workload": "tiny: 1ch u8 64x64x32 blobs, ortho mono 256x256, step 0.5",
+            "layout": args.layout,
             "samples": samples, "median_ms": med, "samples_per_s": samples / (med * 1e-3),
             "eff_GBps": samples * 8 / (med * 1e-3) / 1e9}
 
@@ -169,9 +170,10 @@ def main():
     ap.add_argument("--brick", default="0,0,0", help="brick edge per axis (0,0,0 = default)")
     ap.add_argument("--tile", default="", help="wave_w,wave_h (pixels per wave) of vr_render")
     ap.add_argument("--layout", choices=["bricks", "pairs"], default="pairs",
-                    help="voxel layout of the realistic frame: bricks with row pairs "
-                         "(default; two 16-byte loads per sample, 2.2x the storage) or plain "
-                         "bricks (the library's default layout)")
+                    help="voxel layout of the realistic and tiny frames: bricks with row "
+                         "pairs (default; two 16-byte loads per sample for the realistic "
+                         "frame, 2.2x the storage) or plain bricks (the library's default "
+                         "layout)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-gb", type=float, default=150.0)
     ap.add_argument("--serve-rates", default="25,100,400,1000,1600,2400,3200,4000")

@@ -77,17 +77,22 @@ typedef struct {
                            (all channels of a voxel, 1, 2, 4 or 8 bytes):
                            16 x 16 x 8 for 1-byte, 8 x 16 x 8 for 2- and
                            4-byte, 8 x 8 x 8 for 8-byte words.  Fixed at
-                           creation.  With row_pairs the default is
-                           4 x 16 x 16.                                       */
+                           creation.  With row_pairs the defaults are
+                           16 x 16 x 16, 8 x 32 x 8 and 4 x 16 x 16 for 1-, 2-
+                           and 4-byte words.                                  */
     int32_t row_pairs;  /* 0: default layout.  1: store each brick row next to
-                           the row after it (4-byte words only: 2 channels of
-                           uint16, 3 or 4 of uint8), so a sample's eight taps
-                           take two 16-byte loads instead of four 8-byte
-                           ones.  Storage: 2 (Bx + 1) By (Bz + 1) words per
-                           brick, 2.7x the raw voxels for 4 x 16 x 16 bricks
-                           against 1.3x for the default layout, before
-                           padding (see vr_volume_storage_bytes).  Images are
-                           the same bit for bit either way.                   */
+                           the row after it (voxel words of 1, 2 or 4 bytes:
+                           not 3 or 4 channels of uint16), so the four taps of
+                           a sample in one brick plane are consecutive words:
+                           a sample takes two 16-byte loads instead of four
+                           8-byte ones (4-byte words), two 8-byte loads instead
+                           of eight 2-byte ones (2-byte words) or four 2-byte
+                           loads instead of eight 1-byte ones (1-byte words).
+                           Storage: 2 (Bx + 1) By (Bz + 1) words per brick,
+                           2.7x the raw voxels for 4 x 16 x 16 bricks against
+                           1.3x for the default layout, before padding (see
+                           vr_volume_storage_bytes).  Images are the same bit
+                           for bit either way.                                */
 } vr_volume_desc;
 
 /* One channel's transfer function (User Interface, transfer-function

@@ -58,10 +58,10 @@ static void brick_edges(const vr_volume_desc& d, int b[3]) {
         return;
     }
     const int w = word_bytes(d.channels, d.dtype == VR_U16);
-    if (d.row_pairs) {  // measured: narrow pair rows, deep bricks
-        b[0] = 4;
-        b[1] = 16;
-        b[2] = 16;
+    if (d.row_pairs) {  // measured per word size (layout sweep)
+        b[0] = w == 1 ? 16 : w == 2 ? 8 : 4;
+        b[1] = w == 2 ? 32 : 16;
+        b[2] = w == 2 ? 8 : 16;
         return;
     }
     b[0] = w == 1 ? 16 : 8;
@@ -112,9 +112,9 @@ vr_status check_desc(const vr_volume_desc* d) {
     if (!finite3(d->origin)) return fail(VR_ERR_INVALID_ARG, "origin must be finite");
     if (d->row_pairs != 0 && d->row_pairs != 1)
         return fail(VR_ERR_INVALID_ARG, "row_pairs = %d is neither 0 nor 1", d->row_pairs);
-    if (d->row_pairs && word_bytes(d->channels, d->dtype == VR_U16) != 4)
+    if (d->row_pairs && word_bytes(d->channels, d->dtype == VR_U16) > 4)
         return fail(VR_ERR_INVALID_ARG,
-                    "row pairs need 4-byte voxel words (2 channels of uint16, 3 or 4 of uint8)");
+                    "row pairs need voxel words of at most 4 bytes (not 3 or 4 uint16 channels)");
     const bool dflt = d->brick[0] == 0 && d->brick[1] == 0 && d->brick[2] == 0;
     if (!dflt)
         for (int a = 0; a < 3; ++a)

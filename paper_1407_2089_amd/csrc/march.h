@@ -126,8 +126,10 @@ template <> __device__ __forceinline__ uint2 load_word<uint2>(__amdgpu_buffer_rs
     return make_uint2(w.x, w.y);
 }
 
-// Four consecutive 4-byte words (the row-pair layout's taps of one plane):
-// one 16-byte load.
+// Four consecutive words (the row-pair layout's taps of one plane, which
+// starts at an even word, so 4 W bytes from a 2 W-aligned byte offset): one
+// 16-byte load for 4-byte words, one 8-byte load (dword-aligned) for 2-byte
+// words, two 2-byte loads for 1-byte words.
 template <typename T> struct Quad { T w[4]; };
 template <typename T>
 __device__ __forceinline__ Quad<T> load_quad(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
@@ -136,6 +138,19 @@ template <> __device__ __forceinline__ Quad<uint32_t> load_quad<uint32_t>(__amdg
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const u32x4 a = __builtin_amdgcn_raw_buffer_load_b128(r, (int)v, (int)s, 0);
     return Quad<uint32_t>{{a.x, a.y, a.z, a.w}};
+}
+template <> __device__ __forceinline__ Quad<uint16_t> load_quad<uint16_t>(__amdgpu_buffer_rsrc_t r,
+                                                                          uint32_t v, uint32_t s) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, 0);
+    return Quad<uint16_t>{{(uint16_t)a.x, (uint16_t)(a.x >> 16), (uint16_t)a.y,
+                           (uint16_t)(a.y >> 16)}};
+}
+template <> __device__ __forceinline__ Quad<uint8_t> load_quad<uint8_t>(__amdgpu_buffer_rsrc_t r,
+                                                                        uint32_t v, uint32_t s) {
+    const uint16_t a = __builtin_amdgcn_raw_buffer_load_b16(r, (int)v, (int)s, 0);
+    const uint16_t b = __builtin_amdgcn_raw_buffer_load_b16(r, (int)(v + 2u), (int)s, 0);
+    return Quad<uint8_t>{{(uint8_t)a, (uint8_t)(a >> 8), (uint8_t)b, (uint8_t)(b >> 8)}};
 }
 // floor(x) converted to int in one instruction (register-only).
 __device__ __forceinline__ int cvt_floor(float x) {

@@ -27,11 +27,11 @@ inline constexpr int word_bytes(int channels, bool u16) {
     return (channels == 1 ? 1 : channels == 2 ? 2 : 4) * (u16 ? 2 : 1);
 }
 
-// The row-pair layout exists for 4-byte words only: four of them make one
-// 16-byte load.  (Narrower words would need unaligned loads; for 8-byte words
-// a plane's four taps already take two 16-byte loads without pairs.)
+// The row-pair layout exists for 1-, 2- and 4-byte words: a plane's four
+// taps are then two aligned 2-byte loads, one 8-byte or one 16-byte load.
+// (For 8-byte words they already take two 16-byte loads without pairs.)
 inline constexpr bool variant_exists(int v) {
-    return !(v & 16) || word_bytes((v & 3) + 1, (v & 4) != 0) == 4;
+    return !(v & 16) || word_bytes((v & 3) + 1, (v & 4) != 0) <= 4;
 }
 
 // Brick-major layout of one frame.  Stored coordinates s = i + 1 run over

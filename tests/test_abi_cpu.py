@@ -58,13 +58,17 @@ def test_storage_bytes_follow_brick_layout(dims, ch, dtype, brick):
     ((100, 37, 9), 3, vr.VR_U8, (8, 16, 4)),
     ((512, 512, 64), 2, vr.VR_U16, (0, 0, 0)),
     ((7, 5, 3), 4, vr.VR_U8, (4, 4, 4)),
+    ((33, 20, 11), 1, vr.VR_U8, (0, 0, 0)),
+    ((33, 20, 11), 2, vr.VR_U8, (8, 4, 16)),
+    ((9, 70, 5), 1, vr.VR_U16, (32, 4, 4)),
 ])
 def test_storage_bytes_of_the_row_pair_layout(dims, ch, dtype, brick):
     """Row pairs: a brick plane holds By pairs of rows, 2 (Bx + 1) words each."""
     d = desc(*dims, ch=ch, frames=2, dtype=dtype, bits=8 if dtype == vr.VR_U8 else 16,
              brick=brick, row_pairs=1)
-    word = 4
-    brick = brick if brick != (0, 0, 0) else (4, 16, 16)
+    word = {1: 1, 2: 2, 3: 4, 4: 4}[ch] * (1 if dtype == vr.VR_U8 else 2)
+    if brick == (0, 0, 0):
+        brick = {1: (16, 16, 16), 2: (8, 32, 8), 4: (4, 16, 16)}[word]
     nb = [math.ceil((n + 1) / b) for n, b in zip(dims, brick)]
     per_brick = brick[1] * 2 * (brick[0] + 1) * (brick[2] + 1)
     frame = nb[0] * nb[1] * nb[2] * per_brick * word
@@ -73,9 +77,8 @@ def test_storage_bytes_of_the_row_pair_layout(dims, ch, dtype, brick):
 
 
 @pytest.mark.parametrize("ch,dtype,bits,row_pairs", [
-    (1, vr.VR_U8, 8, 1), (2, vr.VR_U8, 8, 1), (1, vr.VR_U16, 12, 1), (2, vr.VR_U16, 12, 2),
-    (4, vr.VR_U8, 8, -1), (3, vr.VR_U16, 16, 1), (4, vr.VR_U16, 12, 1)])
-def test_row_pairs_need_wide_words_and_a_flag(ch, dtype, bits, row_pairs):
+    (2, vr.VR_U16, 12, 2), (4, vr.VR_U8, 8, -1), (3, vr.VR_U16, 16, 1), (4, vr.VR_U16, 12, 1)])
+def test_row_pairs_need_words_of_at_most_4_bytes_and_a_flag(ch, dtype, bits, row_pairs):
     with pytest.raises(vr.VrError):
         vr.vr_volume_storage_bytes(desc(ch=ch, dtype=dtype, bits=bits, row_pairs=row_pairs))
 

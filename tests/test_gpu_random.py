@@ -52,7 +52,7 @@ def random_case(seed):
         vol[c] += rng.uniform(0, 0.08 * full, size=(nz, ny, nx))
     vol = np.clip(np.rint(vol), 0, full).astype(dtype)
     word = {1: 1, 2: 2, 3: 4, 4: 4}[ch] * (2 if u16 else 1)
-    pairs = word == 4 and bool(rng.integers(0, 2))
+    pairs = word <= 4 and bool(rng.integers(0, 2))
     brick = (0, 0, 0) if rng.integers(0, 3) == 0 else tuple(int(rng.choice(EDGES)) for _ in range(3))
     spacing = tuple(float(x) for x in rng.uniform(0.5, 2.0, 3))
     origin = tuple(float(x) for x in rng.uniform(-5, 5, 3))

@@ -72,7 +72,8 @@ SAMPLER_CASES = [(1, np.uint8, 8, False), (2, np.uint8, 8, False), (3, np.uint8,
                  (4, np.uint8, 8, False), (1, np.uint16, 16, False), (2, np.uint16, 12, False),
                  (3, np.uint16, 12, False), (4, np.uint16, 16, False),
                  (3, np.uint8, 8, True), (4, np.uint8, 8, True), (2, np.uint16, 12, True),
-                 (2, np.uint16, 16, True)]
+                 (2, np.uint16, 16, True), (1, np.uint8, 8, True), (2, np.uint8, 8, True),
+                 (1, np.uint16, 16, True)]
 
 
 @pytest.mark.parametrize("ch,dtype,bits,row_pairs", SAMPLER_CASES)
@@ -242,7 +243,8 @@ def test_p7_channel_permutation_on_gpu(ctx):
 # --------------------------------------------------------- layouts
 
 @pytest.mark.parametrize("ch,dtype,bits", [(3, np.uint8, 8), (4, np.uint8, 8), (2, np.uint16, 12),
-                                           (2, np.uint16, 16)])
+                                           (2, np.uint16, 16), (1, np.uint8, 8), (2, np.uint8, 8),
+                                           (1, np.uint16, 12)])
 @pytest.mark.parametrize("brick", [(0, 0, 0), (4, 8, 16), (16, 4, 8), (32, 32, 4)])
 def test_row_pair_layout_gives_the_same_images(ctx, ch, dtype, bits, brick):
     """Row pairs change where the taps are stored, not their values: images
