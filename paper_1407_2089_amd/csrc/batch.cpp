@@ -278,7 +278,6 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
         if ((e = hipEventSynchronize(s->staged)) != hipSuccess) return hip_fail(e, "staging wait");
         s->staged_pending = false;
     }
-    const int bw = ts.wave_w, bh = ts.wave_h;
     BatchWork* w = s->h_work;
     std::memset(w->group, 0, sizeof w->group);
     uint32_t mask = 0;
@@ -292,8 +291,7 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
         }
         s->h_reqs[q] = P;
         s->h_prefix[q] = (int32_t)items;
-        const int64_t tx = (P.width + bw - 1) / bw, ty = (P.height + bh - 1) / bh;
-        items += tx * ty * P.eyes;
+        items += tiles_per_eye(P.width, P.height, ts) * P.eyes;
         if (items > (1 << 30)) return fail(VR_ERR_INVALID_ARG, "batch has too many tiles");
         g.n_req += 1;
         g.n_items = (int32_t)items;

@@ -83,11 +83,8 @@ __global__ __launch_bounds__(kWave) void render_kernel(ReqParams P, TileShape ts
                                                        int per_eye) {
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
     const int eye = b / per_eye;
-    const int t = b - eye * per_eye;
-    const int st = t / kXcdRun, j = t - st * kXcdRun;
-    const int sy = st / supers_x, sx = st - sy * supers_x;
-    const int tx = sx * kSuperW + j % kSuperW;
-    const int ty = sy * kSuperH + j / kSuperW;
+    int tx, ty;
+    tile_at(b - eye * per_eye, supers_x, tx, ty);
     const int lane = threadIdx.x;
     const int px = tx * ts.wave_w + lane % ts.wave_w;
     const int py = ty * ts.wave_h + lane / ts.wave_w;
@@ -112,13 +109,12 @@ __device__ __forceinline__ int find_req(const int32_t* __restrict__ prefix, int 
 
 template <int V>
 __device__ __forceinline__ void batch_tile(const ReqParams& P, const TileShape& ts, int local) {
-    const int tiles_x = (P.width + ts.wave_w - 1) / ts.wave_w;
-    const int tiles_y = (P.height + ts.wave_h - 1) / ts.wave_h;
-    const int per_eye = tiles_x * tiles_y;
+    // A request's items are its eyes' tiles in super-tile order.
+    const int supers_x = (int)supers_across(P.width, ts);
+    const int per_eye = (int)tiles_per_eye(P.width, P.height, ts);
     const int eye = local / per_eye;
-    const int t = local - eye * per_eye;
-    const int ty = t / tiles_x;
-    const int tx = t - ty * tiles_x;
+    int tx, ty;
+    tile_at(local - eye * per_eye, supers_x, tx, ty);
     const int lane = threadIdx.x & (kWave - 1);
     const int px = tx * ts.wave_w + lane % ts.wave_w;
     const int py = ty * ts.wave_h + lane / ts.wave_w;
@@ -214,11 +210,8 @@ hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_ski
         return hipErrorInvalidValue;
     if (ts.wave_w <= 0 || ts.wave_h <= 0 || ts.wave_w * ts.wave_h != kWave)
         return hipErrorInvalidValue;
-    const int tiles_x = (P.width + ts.wave_w - 1) / ts.wave_w;
-    const int tiles_y = (P.height + ts.wave_h - 1) / ts.wave_h;
-    const long long supers_x = (tiles_x + kSuperW - 1) / kSuperW;
-    const long long supers_y = (tiles_y + kSuperH - 1) / kSuperH;
-    const long long per_eye = supers_x * supers_y * kXcdRun;
+    const long long supers_x = supers_across(P.width, ts);
+    const long long per_eye = tiles_per_eye(P.width, P.height, ts);
     const long long blocks = per_eye * P.eyes;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;

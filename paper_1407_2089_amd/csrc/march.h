@@ -532,13 +532,20 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
 // simulated from per-pixel sample counts: 4 x 4 stays within 1-7 %).  The map
 // is a bijection on [0, nblocks); blocks past the last whole round of 8 runs
 // keep their index.
-constexpr int kSuperW = 4, kSuperH = 4;
-constexpr int kXcdRun = kSuperW * kSuperH;
+constexpr int kXcdRun = kSuperTiles;
 __host__ __device__ __forceinline__ int xcd_remap(int b, int nblocks) {
     const int whole = nblocks - nblocks % (8 * kXcdRun);
     if (b >= whole) return b;
     const int i = b >> 3;  // the block's rank on its XCD
     return (((i / kXcdRun) << 3) + (b & 7)) * kXcdRun + i % kXcdRun;
+}
+
+// Tile (tx, ty) at position t of an eye's super-tile order.
+__device__ __forceinline__ void tile_at(int t, int supers_x, int& tx, int& ty) {
+    const int st = t / kSuperTiles, j = t - st * kSuperTiles;
+    const int sy = st / supers_x, sx = st - sy * supers_x;
+    tx = sx * kSuperW + j % kSuperW;
+    ty = sy * kSuperH + j / kSuperW;
 }
 
 }  // namespace vr

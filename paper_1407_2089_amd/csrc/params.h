@@ -111,4 +111,18 @@ struct TileShape {
     int32_t wave_w, wave_h;   // pixels per wave (wave_w * wave_h = 64)
 };
 
+// The tiles of an eye are ordered super-tile by super-tile (row-major over
+// super-tiles of kSuperW x kSuperH tiles, row-major inside each), padded to
+// whole super-tiles; tiles of the padding lie past the image edge.
+constexpr int kSuperW = 4, kSuperH = 4;
+constexpr int kSuperTiles = kSuperW * kSuperH;
+inline constexpr int64_t supers_across(int32_t width, const TileShape& ts) {
+    const int64_t tx = ((int64_t)width + ts.wave_w - 1) / ts.wave_w;
+    return (tx + kSuperW - 1) / kSuperW;
+}
+inline constexpr int64_t tiles_per_eye(int32_t width, int32_t height, const TileShape& ts) {
+    const int64_t ty = ((int64_t)height + ts.wave_h - 1) / ts.wave_h;
+    return supers_across(width, ts) * ((ty + kSuperH - 1) / kSuperH) * kSuperTiles;
+}
+
 }  // namespace vr
