@@ -3,6 +3,7 @@
 // batch.cpp, the serving loop in server.cpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -263,6 +264,9 @@ static Transparent make_transparent(const ReqParams& P, uint32_t full) {
     if (any && !useful) t.ok = 0;
     t.tmax2[0] = t.tmax[0] | t.tmax[1] << 16;
     t.tmax2[1] = t.tmax[2] | t.tmax[3] << 16;
+    auto lane = [&](int c) { return (std::min(t.tmax[c], 255u) << 8) | 255u; };
+    t.byte_hi = lane(1) | lane(3) << 16;
+    t.byte_lo = lane(0) | lane(2) << 16;
     return t;
 }
 

@@ -348,6 +348,29 @@ __device__ __forceinline__ bool transparent(const Taps<T>& t, const Transparent&
             max(max(max((uint32_t)t.w000, (uint32_t)t.w100), max((uint32_t)t.w010, (uint32_t)t.w110)),
                 max(max((uint32_t)t.w001, (uint32_t)t.w101), max((uint32_t)t.w011, (uint32_t)t.w111)));
         return m <= z.tmax[0];
+    } else if constexpr (!U16 && C >= 3) {
+        // Four uint8 channels: the odd channels are the high bytes of the
+        // word's 16-bit lanes, the even ones become so after a shift by 8 in
+        // each lane; a lane max compared with (t << 8 | 255) tests the high
+        // byte (no byte unpacking).
+        const u16x2_t eight = {8, 8};
+        const auto hi_lo = [&](uint32_t a, uint32_t b, u16x2_t& hi, u16x2_t& lo) {
+            const u16x2_t x = __builtin_bit_cast(u16x2_t, a), y = __builtin_bit_cast(u16x2_t, b);
+            hi = __builtin_elementwise_max(x, y);
+            lo = __builtin_elementwise_max(x << eight, y << eight);
+        };
+        u16x2_t h0, l0, h1, l1, h2, l2, h3, l3;
+        hi_lo((uint32_t)t.w000, (uint32_t)t.w100, h0, l0);
+        hi_lo((uint32_t)t.w010, (uint32_t)t.w110, h1, l1);
+        hi_lo((uint32_t)t.w001, (uint32_t)t.w101, h2, l2);
+        hi_lo((uint32_t)t.w011, (uint32_t)t.w111, h3, l3);
+        const u16x2_t hi = __builtin_elementwise_max(__builtin_elementwise_max(h0, h1),
+                                                     __builtin_elementwise_max(h2, h3));
+        const u16x2_t lo = __builtin_elementwise_max(__builtin_elementwise_max(l0, l1),
+                                                     __builtin_elementwise_max(l2, l3));
+        const u16x2_t over_hi = __builtin_elementwise_sub_sat(hi, __builtin_bit_cast(u16x2_t, z.byte_hi));
+        const u16x2_t over_lo = __builtin_elementwise_sub_sat(lo, __builtin_bit_cast(u16x2_t, z.byte_lo));
+        return (__builtin_bit_cast(uint32_t, over_hi) | __builtin_bit_cast(uint32_t, over_lo)) == 0u;
     } else {
         bool clear = true;
 #pragma unroll

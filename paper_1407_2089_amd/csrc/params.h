@@ -75,6 +75,11 @@ struct ChanTF {
 struct Transparent {
     uint32_t tmax2[2];   // (tmax[2q] | tmax[2q + 1] << 16), 16-bit lanes
     uint32_t tmax[4];    // per channel, 0 .. 65535
+    // 4 uint8 channels (c0 | c1 << 8 | c2 << 16 | c3 << 24) read as 16-bit
+    // lanes: a lane (hi << 8 | lo) is at most (t << 8 | 255) exactly when its
+    // high byte is at most t.  byte_hi tests c1, c3 on the words themselves,
+    // byte_lo tests c0, c2 on the words shifted left by 8 in each lane.
+    uint32_t byte_hi, byte_lo;
     int32_t ok;
     int32_t pad_;
 };
