@@ -12,7 +12,8 @@ import numpy as np
 
 from .build import LIB, build
 
-__all__ = ["Volume", "Transfer", "Camera", "sample", "render", "load"]
+__all__ = ["Volume", "Transfer", "Camera", "Light", "sample", "gradient", "shade",
+           "render", "load"]
 
 _lib = None
 
@@ -40,7 +41,18 @@ class _Camera(C.Structure):
 class _View(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("eye", C.c_int32),
                 ("step", C.c_double), ("term_alpha", C.c_double),
-                ("band_eps", C.c_double), ("background", C.c_double * 4)]
+                ("band_eps", C.c_double), ("background", C.c_double * 4),
+                ("lit", C.c_int32), ("light_dir", C.c_double * 3),
+                ("ambient", C.c_double), ("diffuse", C.c_double)]
+
+
+class Light:
+    """Global directional light: ``direction`` points towards the light
+    (world space); shade = ambient + diffuse * max(0, n . l)."""
+
+    def __init__(self, direction=(0.0, 0.0, -1.0), ambient=0.3, diffuse=0.7):
+        self.direction = tuple(float(x) for x in direction)
+        self.ambient, self.diffuse = float(ambient), float(diffuse)
 
 
 def load():
@@ -57,9 +69,15 @@ def load():
                                           C.c_void_p]
         lib.orc_sample_points.restype = C.c_int
         P = C.c_void_p
+        lib.orc_gradient_points.argtypes = [C.POINTER(_Volume), C.c_void_p, C.c_int64,
+                                            C.c_void_p]
+        lib.orc_gradient_points.restype = C.c_int
+        lib.orc_shade.argtypes = [C.POINTER(_Volume), C.POINTER(_View), C.c_void_p,
+                                  C.c_void_p, C.c_void_p]
+        lib.orc_shade.restype = C.c_int
         lib.orc_render.argtypes = [C.POINTER(_Volume), C.POINTER(_Transfer),
                                    C.POINTER(_Camera), C.POINTER(_View), P,
-                                   C.c_int64, P, P, P, P, P, P, P, C.c_int]
+                                   C.c_int64, P, P, P, P, P, P, P, P, C.c_int]
         lib.orc_render.restype = C.c_int
         _lib = lib
     return _lib
@@ -128,19 +146,51 @@ def sample(vol: Volume, points):
     return out
 
 
+def _view(width, height, eye, step, term_alpha, band_eps, background, light):
+    lit = light is not None
+    d = light.direction if lit else (0.0, 0.0, 0.0)
+    return _View(int(width), int(height), int(eye), float(step), float(term_alpha),
+                 float(band_eps), (C.c_double * 4)(*[float(b) for b in background]),
+                 int(lit), (C.c_double * 3)(*d), light.ambient if lit else 0.0,
+                 light.diffuse if lit else 0.0)
+
+
+def gradient(vol: Volume, points):
+    """Central-difference gradient (raw intensity per world unit) of every
+    channel at index-space points [n][3].  Returns float64 [n][C][3]."""
+    lib = load()
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    cv = vol._c()
+    out = np.zeros((pts.shape[0], vol.data.shape[0], 3), dtype=np.float64)
+    lib.orc_gradient_points(C.byref(cv), pts.ctypes.data, pts.shape[0], out.ctypes.data)
+    return out
+
+
+def shade(vol: Volume, light, point):
+    """Per-channel shade and shade margin at one index-space point."""
+    lib = load()
+    p = np.ascontiguousarray(point, dtype=np.float64).reshape(3)
+    nc = vol.data.shape[0]
+    s, m = np.zeros(nc), np.zeros(nc)
+    cv = vol._c()
+    view = _view(1, 1, 0, 1.0, 1.0, 0.0, (0, 0, 0, 0), light)
+    lib.orc_shade(C.byref(cv), C.byref(view), p.ctypes.data, s.ctypes.data, m.ctypes.data)
+    return s, m
+
+
 def render(vol: Volume, transfers, cam: Camera, width, height, eye=0, step=1.0,
            term_alpha=1.0, band_eps=1e-3, background=(0, 0, 0, 0), pixels=None,
-           nthreads=None):
-    """Render one eye (-1 left, 0 mono, +1 right).  ``pixels`` is an optional
-    int64 array of linear pixel indices j * width + i.  Returns a dict of
-    float64 / int32 numpy arrays keyed rgba, samples, nominal, count_margin,
-    band_lo, band_hi, band_k."""
+           nthreads=None, light=None):
+    """Render one eye (-1 left, 0 mono, +1 right), lit by ``light`` (a
+    Light, or None for no lighting).  ``pixels`` is an optional int64 array of
+    linear pixel indices j * width + i.  Returns a dict of float64 / int32
+    numpy arrays keyed rgba, samples, nominal, count_margin, band_lo,
+    band_hi, band_k, lit_margin."""
     lib = load()
     if len(transfers) != vol.data.shape[0]:
         raise ValueError("one transfer function per channel is required")
     tfs = (_Transfer * len(transfers))(*[t._c() for t in transfers])
-    view = _View(int(width), int(height), int(eye), float(step), float(term_alpha),
-                 float(band_eps), (C.c_double * 4)(*[float(b) for b in background]))
+    view = _view(width, height, eye, step, term_alpha, band_eps, background, light)
     if pixels is None:
         npix = int(width) * int(height)
         pix_ptr = None
@@ -156,6 +206,7 @@ def render(vol: Volume, transfers, cam: Camera, width, height, eye=0, step=1.0,
         "band_lo": np.zeros((npix, 4), np.float64),
         "band_hi": np.zeros((npix, 4), np.float64),
         "band_k": np.zeros((npix, 2), np.int32),
+        "lit_margin": np.zeros(npix, np.float64),
     }
     if nthreads is None:
         nthreads = os.cpu_count() or 1
@@ -164,7 +215,8 @@ def render(vol: Volume, transfers, cam: Camera, width, height, eye=0, step=1.0,
                         res["rgba"].ctypes.data, res["samples"].ctypes.data,
                         res["nominal"].ctypes.data, res["count_margin"].ctypes.data,
                         res["band_lo"].ctypes.data, res["band_hi"].ctypes.data,
-                        res["band_k"].ctypes.data, int(nthreads))
+                        res["band_k"].ctypes.data, res["lit_margin"].ctypes.data,
+                        int(nthreads))
     if rc != 0:
         raise ValueError("orc_render rejected its arguments")
     if pixels is None:

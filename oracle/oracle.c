@@ -16,6 +16,10 @@
  * trilinear interpolation with zero outside the grid, front-to-back
  * compositing with an early-termination threshold, an off-axis parallel-eye
  * stereo pair) are listed with every other reading in the design notes.
+ * The optional lighting (one global directional light, normals from the
+ * gradient over the 3 x 3 x 3 neighbourhood, same section) is read as
+ * central differences of the trilinear field and Lambert shading of each
+ * channel's colour; it leaves opacity untouched.
  *
  * Everything is IEEE double, written as the plain definition, one pixel at a
  * time.  Threads only split the pixel list; they do not change arithmetic.
@@ -58,6 +62,10 @@ typedef struct {
     double term_alpha;    /* stop once accumulated opacity reaches this       */
     double band_eps;      /* width of the termination band (acceptance rule)  */
     double background[4];
+    /* Global directional light (the viewer's lighting check box). */
+    int32_t lit;          /* 0 off, 1 on                                      */
+    double light_dir[3];  /* world space, pointing towards the light          */
+    double ambient, diffuse;
 } orc_view;
 
 /* Per-pixel results. */
@@ -73,6 +81,9 @@ typedef struct {
     double* band_hi;       /* [npix][4]  componentwise max over the band         */
     int32_t* band_k;       /* [npix][2]  smallest and largest band member count,
                                          -1 when the band is empty               */
+    double* lit_margin;    /* [npix]     bound on the colour change that FP32
+                                         rounding of the gradients can cause
+                                         (0 when unlit)                          */
 } orc_result;
 
 /* ---------------------------------------------------------------- sampling */
@@ -120,6 +131,95 @@ int orc_sample_points(const orc_volume* v, const double* pts, int64_t n, double*
     return 0;
 }
 
+/* ---------------------------------------------------------------- lighting */
+
+/* Gradient of every channel's trilinear field at index-space position p, in
+ * raw intensity per world unit: the central difference over one voxel along
+ * each axis, (x(p + e_a) - x(p - e_a)) / (2 spacing_a).  The six points are
+ * the face neighbours of p in the 3 x 3 x 3 neighbourhood at unit offsets
+ * that the viewer's lighting takes the gradient from.  g is [channels][3]. */
+int orc_gradient(const orc_volume* v, const double p[3], double* g)
+{
+    double hi[4], lo[4];
+    for (int a = 0; a < 3; ++a) {
+        double q[3] = {p[0], p[1], p[2]};
+        q[a] = p[a] + 1.0;
+        orc_sample(v, q, hi);
+        q[a] = p[a] - 1.0;
+        orc_sample(v, q, lo);
+        for (int c = 0; c < v->channels; ++c)
+            g[3 * c + a] = (hi[c] - lo[c]) / (2.0 * v->spacing[a]);
+    }
+    return 0;
+}
+
+/* orc_gradient over n points [n][3]; out is [n][channels][3]. */
+int orc_gradient_points(const orc_volume* v, const double* pts, int64_t n, double* out)
+{
+    for (int64_t q = 0; q < n; ++q)
+        orc_gradient(v, pts + 3 * q, out + (size_t)3 * v->channels * q);
+    return 0;
+}
+
+/* Smallest and largest raw value of channel c among the eight voxels around
+ * p (zero outside the grid). */
+static void tap_range(const orc_volume* v, int c, const double p[3], double* mn, double* mx)
+{
+    long i0 = (long)floor(p[0]), j0 = (long)floor(p[1]), k0 = (long)floor(p[2]);
+    *mn = INFINITY;
+    *mx = -INFINITY;
+    for (int dz = 0; dz <= 1; ++dz)
+        for (int dy = 0; dy <= 1; ++dy)
+            for (int dx = 0; dx <= 1; ++dx) {
+                double w = voxel(v, c, i0 + dx, j0 + dy, k0 + dz);
+                if (w < *mn) *mn = w;
+                if (w > *mx) *mx = w;
+            }
+}
+
+/* Lambert shading of each channel at p: the channel's surface normal is the
+ * unit vector against its gradient, n = -g / |g| (pointing out of bright
+ * structure), and shade = ambient + diffuse * max(0, n . l) with l the unit
+ * light direction; a channel with zero gradient has no surface and takes
+ * ambient + diffuse.  margin[c] bounds how far the shade can move when the
+ * gradient carries an absolute error of up to 2^-19 of the largest voxel
+ * value it reads per difference (FP32 lerp trees): a direction error of at
+ * most 2 |dg| / |g|; zero for an axis whose sixteen voxels are all equal
+ * (every lerp of equal values is exact).  shade and margin are [channels]. */
+int orc_shade(const orc_volume* v, const orc_view* view, const double p[3], double* shade,
+              double* margin)
+{
+    double g[12], l[3] = {view->light_dir[0], view->light_dir[1], view->light_dir[2]};
+    double ln = sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+    for (int a = 0; a < 3; ++a) l[a] /= ln;
+    orc_gradient(v, p, g);
+    for (int c = 0; c < v->channels; ++c) {
+        const double* gc = g + 3 * c;
+        double gn = sqrt(gc[0] * gc[0] + gc[1] * gc[1] + gc[2] * gc[2]);
+        double diff = 1.0;
+        if (gn > 0.0) {
+            double d = -(gc[0] * l[0] + gc[1] * l[1] + gc[2] * l[2]) / gn;
+            diff = d > 0.0 ? d : 0.0;
+        }
+        shade[c] = view->ambient + view->diffuse * diff;
+        double err2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double q[3] = {p[0], p[1], p[2]}, mn1, mx1, mn2, mx2;
+            q[a] = p[a] + 1.0;
+            tap_range(v, c, q, &mn1, &mx1);
+            q[a] = p[a] - 1.0;
+            tap_range(v, c, q, &mn2, &mx2);
+            double mn = mn1 < mn2 ? mn1 : mn2, mx = mx1 > mx2 ? mx1 : mx2;
+            if (mn == mx) continue;
+            double e = ldexp(mx, -19) / (2.0 * v->spacing[a]);
+            err2 += e * e;
+        }
+        double rel = err2 == 0.0 ? 0.0 : (gn > 0.0 ? 2.0 * sqrt(err2) / gn : 1.0);
+        margin[c] = view->diffuse * (rel < 1.0 ? rel : 1.0);
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------- transfer function */
 
 /* One channel's transfer function at normalised intensity x: returns g and
@@ -136,21 +236,34 @@ static double transfer(const orc_transfer* t, double x, double* alpha)
 }
 
 /* Classification of one sample: base alpha is the largest visible channel
- * alpha (capped at 1), colour is the capped sum of the channels' colours. */
+ * alpha (capped at 1), colour is the capped sum of the channels' colours,
+ * each scaled by the channel's shade when the view is lit (shade NULL:
+ * unlit).  *lit_err receives the bound on the colour change that the shade
+ * margins allow (sum over channels of value x largest colour component x
+ * margin). */
 static void classify(const orc_volume* v, const orc_transfer* tf, const double* field,
-                     double* alpha_s, double rgb_s[3])
+                     const double* shade, const double* margin, double* alpha_s,
+                     double rgb_s[3], double* lit_err)
 {
     double full_scale = ldexp(1.0, v->bits) - 1.0;
-    double amax = 0.0, rgb[3] = {0.0, 0.0, 0.0};
+    double amax = 0.0, rgb[3] = {0.0, 0.0, 0.0}, err = 0.0;
     for (int c = 0; c < v->channels; ++c) {
         if (!tf[c].visible) continue;
         double a;
         double g = transfer(&tf[c], field[c] / full_scale, &a);
         if (a > amax) amax = a;
-        for (int q = 0; q < 3; ++q) rgb[q] += g * tf[c].rgb[q];
+        double s = shade ? shade[c] : 1.0;
+        for (int q = 0; q < 3; ++q) rgb[q] += g * s * tf[c].rgb[q];
+        if (shade) {
+            double cmax = tf[c].rgb[0];
+            if (tf[c].rgb[1] > cmax) cmax = tf[c].rgb[1];
+            if (tf[c].rgb[2] > cmax) cmax = tf[c].rgb[2];
+            err += g * cmax * margin[c];
+        }
     }
     *alpha_s = amax < 1.0 ? amax : 1.0;
     for (int q = 0; q < 3; ++q) rgb_s[q] = rgb[q] < 1.0 ? rgb[q] : 1.0;
+    *lit_err = err;
 }
 
 /* ------------------------------------------------------------------ camera */
@@ -293,7 +406,7 @@ static void render_pixel(const job_t* jb, int64_t slot)
 
     const double tau = view->term_alpha, eps = view->band_eps;
     int stopped = 0, k_stop = 0, nominal = 0;
-    double margin = 1.0;
+    double margin = 1.0, margin_lit = 0.0;
 
     if (!miss) {
         double span = (t_exit - t_enter) / view->step - 0.5;
@@ -305,7 +418,7 @@ static void render_pixel(const job_t* jb, int64_t slot)
         int prev_in = fabs(A - tau) <= eps;
         if (prev_in) band_add(blo, bhi, bk, out, 0);
 
-        double field[4];
+        double field[4], shade[4], smargin[4], lit_err;
         for (int k = 0;; ++k) {
             double t = t_enter + (k + 0.5) * view->step;
             if (!(t < t_exit)) break;
@@ -314,8 +427,11 @@ static void render_pixel(const job_t* jb, int64_t slot)
             double p[3];
             for (int a = 0; a < 3; ++a) p[a] = p0[a] + t * d[a];
             orc_sample(v, p, field);
+            if (view->lit) orc_shade(v, view, p, shade, smargin);
             double a_s, rgb_s[3];
-            classify(v, jb->tf, field, &a_s, rgb_s);
+            classify(v, jb->tf, field, view->lit ? shade : NULL, smargin, &a_s, rgb_s,
+                     &lit_err);
+            margin_lit += (1.0 - A) * a_s * lit_err;
             for (int q = 0; q < 3; ++q) C[q] += (1.0 - A) * a_s * rgb_s[q];
             A += (1.0 - A) * a_s;
             finish(view, C, A, out);
@@ -341,6 +457,7 @@ static void render_pixel(const job_t* jb, int64_t slot)
     jb->res.samples[slot] = k_stop;
     jb->res.nominal[slot] = nominal;
     jb->res.count_margin[slot] = margin;
+    jb->res.lit_margin[slot] = margin_lit;
 }
 
 static void* worker(void* arg)
@@ -363,12 +480,16 @@ static void* worker(void* arg)
 int orc_render(const orc_volume* vol, const orc_transfer* tf, const orc_camera* cam,
                const orc_view* view, const int64_t* pixels, int64_t npix,
                double* rgba, int32_t* samples, int32_t* nominal, double* count_margin,
-               double* band_lo, double* band_hi, int32_t* band_k, int nthreads)
+               double* band_lo, double* band_hi, int32_t* band_k, double* lit_margin,
+               int nthreads)
 {
     if (!vol || !tf || !cam || !view || !rgba || !samples || !nominal || !count_margin
-        || !band_lo || !band_hi || !band_k)
+        || !band_lo || !band_hi || !band_k || !lit_margin)
         return -1;
     if (view->width <= 0 || view->height <= 0 || !(view->step > 0.0)) return -1;
+    if (view->lit && !(view->light_dir[0] != 0.0 || view->light_dir[1] != 0.0
+                       || view->light_dir[2] != 0.0))
+        return -1;
     if (!pixels && npix != (int64_t)view->width * view->height) return -1;
 
     job_t jb;
@@ -385,6 +506,7 @@ int orc_render(const orc_volume* vol, const orc_transfer* tf, const orc_camera* 
     jb.res.band_lo = band_lo;
     jb.res.band_hi = band_hi;
     jb.res.band_k = band_k;
+    jb.res.lit_margin = lit_margin;
     jb.next = 0;
 
     if (nthreads <= 1) {

@@ -45,6 +45,15 @@ class Cam:
 
 
 @dataclass
+class Light:
+    """Global directional light: direction points towards the light (world
+    space); a channel's colour is scaled by ambient + diffuse * max(0, n . l)."""
+    direction: tuple = (0.0, 0.0, -1.0)
+    ambient: float = 0.3
+    diffuse: float = 0.7
+
+
+@dataclass
 class Scene:
     """One frame of one workload: voxels [C][Z][Y][X] plus everything a render
     request needs."""
@@ -62,6 +71,7 @@ class Scene:
     spacing: tuple = (1.0, 1.0, 1.0)
     origin: tuple = (0.0, 0.0, 0.0)
     extra: dict = field(default_factory=dict)
+    light: Light = None     # None: unlit
 
 
 # ------------------------------------------------------------------ cameras

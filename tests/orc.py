@@ -18,19 +18,25 @@ def camera(cam):
                          cam.ortho_height, cam.eye_separation, cam.convergence)
 
 
+def light(lt):
+    return None if lt is None else oracle.Light(lt.direction, lt.ambient, lt.diffuse)
+
+
 def eyes(scene):
     return (-1, 1) if scene.stereo else (0,)
 
 
 def render(scene, eye=None, pixels=None, band_eps=1e-3, data=None, tfs=None, cam=None,
-           term_alpha=None, nthreads=None):
-    """Oracle result for one eye of a scene (eye defaults to the first)."""
+           term_alpha=None, nthreads=None, lit=None):
+    """Oracle result for one eye of a scene (eye defaults to the first);
+    lit overrides the scene's light (False: unlit)."""
     if eye is None:
         eye = eyes(scene)[0]
+    lt = scene.light if lit is None else (lit or None)
     return oracle.render(volume(scene, data), transfers(tfs or scene.tfs),
                          camera(cam or scene.cam), scene.width, scene.height, eye,
                          scene.step, scene.term_alpha if term_alpha is None else term_alpha,
-                         band_eps, scene.background, pixels, nthreads)
+                         band_eps, scene.background, pixels, nthreads, light(lt))
 
 
 def render_all(scene, band_eps=1e-3, pixels=None):

@@ -12,7 +12,7 @@ import pytest
 import oracle
 import orc
 import scenes
-from paper_1407_2089_amd.synth import TF, Cam, Scene
+from paper_1407_2089_amd.synth import TF, Cam, Light, Scene
 
 
 # ------------------------------------------------------------------ P1 empty
@@ -396,3 +396,127 @@ def test_p13_anisotropic_sample_count_closed_form():
     r = orc.render(Scene("az", V, 8, [TF(0.5, 1.0)], cam, 3, 3, False, 1.0, 1.0,
                          spacing=(1.0, 1.0, 2.5)))
     assert (r["nominal"] == math.ceil((nz + 1) * 2.5 - 0.5)).all()
+
+
+# ------------------------------------------------------------- P14 lighting
+
+def test_p14_gradient_of_a_linear_field_closed_form():
+    # Central differences reproduce a linear field's slope exactly, per axis
+    # divided by that axis's spacing (pins axis order, spacing and sign).
+    nx, ny, nz = 12, 9, 7
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    coef = [(20, 3, 7, 10), (1, 30, 2, 50)]
+    V = np.stack([a * i + b * j + c * k + d for a, b, c, d in coef]).astype(np.uint16)
+    sp = (2.0, 1.0, 0.5)
+    vol = oracle.Volume(V, 12, spacing=sp, origin=(4.0, -1.0, 2.0))
+    rng = np.random.default_rng(3)
+    pts = rng.uniform((1, 1, 1), (nx - 2, ny - 2, nz - 2), size=(50, 3))
+    g = oracle.gradient(vol, pts)
+    for c, (a, b, cc, _) in enumerate(coef):
+        np.testing.assert_allclose(g[:, c], np.broadcast_to([a / sp[0], b / sp[1], cc / sp[2]],
+                                                            (50, 3)), rtol=1e-12, atol=1e-12)
+
+
+def test_p14_gradient_of_a_quadratic_field_closed_form():
+    # For v = i^2 the trilinear field between voxels is the chord of i^2, and
+    # its central difference over one voxel is exactly 2 p at any interior p
+    # (a one-sided or half-voxel difference, or the nearest voxel's gradient,
+    # gives 2 p +- 1 or 2 round(p) instead).
+    nx = 40
+    V = np.zeros((1, 4, 4, nx), np.uint16)
+    V[0] = (np.arange(nx) ** 2)[None, None, :]
+    vol = oracle.Volume(V, 16)
+    xs = np.linspace(1.0, nx - 2.0, 97)
+    pts = np.stack([xs, np.full_like(xs, 1.5), np.full_like(xs, 1.25)], axis=1)
+    g = oracle.gradient(vol, pts)
+    np.testing.assert_allclose(g[:, 0, 0], 2.0 * xs, rtol=1e-12)
+    assert np.all(g[:, 0, 1:] == 0.0)
+
+
+def test_p14_shade_special_cases():
+    # Linear field with gradient g: the normal is -g / |g|.  A light along the
+    # normal gives ambient + diffuse, against it or across it the ambient
+    # only, at 45 degrees ambient + diffuse / sqrt 2; a flat field has no
+    # surface and gives ambient + diffuse.  Light vectors are not unit length.
+    nx, ny, nz = 8, 8, 8
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    V = (30 * i + 10 * j + 5 * k + 20).astype(np.uint16)[None]
+    vol = oracle.Volume(V, 12)
+    g = np.array([30.0, 10.0, 5.0])
+    n = -g / np.linalg.norm(g)
+    m = np.cross(n, [0.0, 0.0, 1.0])
+    m /= np.linalg.norm(m)
+    ka, kd = 0.2, 0.7
+    p = (3.4, 4.1, 3.7)
+    cases = [(3 * n, ka + kd), (-2 * n, ka), (5 * m, ka), (n + m, ka + kd / math.sqrt(2))]
+    for l, expect in cases:
+        s, marg = oracle.shade(vol, oracle.Light(tuple(l), ka, kd), p)
+        assert abs(s[0] - expect) < 1e-12, (l, s, expect)
+        assert 0.0 < marg[0] < 1e-4
+    flat = oracle.Volume(np.full((1, 6, 6, 6), 900, np.uint16), 12)
+    s, marg = oracle.shade(flat, oracle.Light((1.0, 2.0, 3.0), ka, kd), (2.5, 2.5, 2.5))
+    assert s[0] == ka + kd and marg[0] == 0.0
+
+
+def test_p14_lit_thin_slab_closed_form():
+    # One voxel layer v = 20 i + 10 (uint8), spacing (2, 1, 0.5), seen along
+    # +z by an orthographic camera whose rays cross interior columns.  Each
+    # ray takes two samples, at z = -1/2 and +1/2 (index space), both with
+    # value V / 2 (V = 20 x + 10): raw gradients (5, 0, V / 2) and
+    # (5, 0, -V / 2) per world unit.  With the light l = (0.2, 0, -1) the
+    # first sample faces the light and the second faces away (ambient only).
+    nx, ny = 8, 5
+    V = np.zeros((1, 1, ny, nx), np.uint8)
+    V[0, 0] = (20 * np.arange(nx) + 10)[None, :]
+    m, rgb = 0.9, (1.0, 0.5, 0.25)
+    ka, kd = 0.25, 0.6
+    ldir = np.array([0.2, 0.0, -1.0])
+    cam = Cam("ortho", (7.0, 2.0, -3.0), (0, 0, 1), (0, -1, 0), ortho_height=1.0)
+    sc = Scene("lit slab", V, 8, [TF(0.0, 1.0, 0.0, m, rgb)], cam, 6, 2, False, 0.5, 1.0,
+               spacing=(2.0, 1.0, 0.5))
+    sc.light = Light(tuple(ldir), ka, kd)
+    r = orc.render(sc)
+    assert (r["samples"] == 2).all()
+    lhat = ldir / np.linalg.norm(ldir)
+    for jj in range(2):
+        for ii in range(6):
+            x_world = 7.0 + (2 * (ii + 0.5) / 6 - 1) * 1.5
+            Vx = 20 * (x_world / 2.0) + 10
+            u = 0.5 * Vx / 255.0
+            a = m * u
+            shades = []
+            for gz in (0.5 * Vx, -0.5 * Vx):
+                gv = np.array([5.0, 0.0, gz])
+                shades.append(ka + kd * max(0.0, float(-gv @ lhat) / np.linalg.norm(gv)))
+            assert shades[0] > ka and shades[1] == ka
+            col = a * u * shades[0] + (1 - a) * a * u * shades[1]
+            exp = [col * rgb[0], col * rgb[1], col * rgb[2], a + (1 - a) * a]
+            np.testing.assert_allclose(r["rgba"][jj, ii], exp, rtol=0, atol=1e-12)
+    assert r["lit_margin"].max() < 1e-5
+
+
+def test_p14_lighting_scales_colour_only():
+    # Lighting never changes opacity or sample counts; ambient 1 with no
+    # diffuse term is the unlit image, and a pure ambient term k scales the
+    # colour by k (colour sums kept below the cap, black background).
+    nx, ny, nz = 18, 14, 10
+    V = scenes.random_volume(17, (2, nz, ny, nx), np.uint16, 4096)
+    tfs = [TF(0.1, 0.8, 0.2, 1.2, (0.5, 0.0, 0.2)), TF(0.2, 0.9, -0.3, 0.7, (0.0, 0.5, 0.3))]
+    cam = scenes.mirror_camera(nx, ny, nz, sep=1.5)
+    sc = Scene("lit", V, 12, tfs, cam, 20, 16, True, 0.8, 0.97, spacing=(1.0, 1.5, 0.8))
+    for eye in (-1, 1):
+        base = orc.render(sc, eye, lit=False)
+        sc.light = Light((0.3, -0.5, 0.8), 0.35, 0.65)
+        lit = orc.render(sc, eye)
+        assert np.array_equal(lit["rgba"][..., 3], base["rgba"][..., 3])
+        assert np.array_equal(lit["samples"], base["samples"])
+        assert not np.allclose(lit["rgba"][..., :3], base["rgba"][..., :3], atol=1e-3)
+        sc.light = Light((0.3, -0.5, 0.8), 1.0, 0.0)
+        same = orc.render(sc, eye)
+        assert np.array_equal(same["rgba"], base["rgba"])
+        sc.light = Light((0.3, -0.5, 0.8), 0.4, 0.0)
+        half = orc.render(sc, eye)
+        np.testing.assert_allclose(half["rgba"][..., :3], 0.4 * base["rgba"][..., :3],
+                                   rtol=0, atol=1e-12)
+        assert np.array_equal(half["lit_margin"], np.zeros_like(half["lit_margin"]))
+        sc.light = None
