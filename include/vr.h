@@ -129,6 +129,23 @@ typedef struct {
     float convergence;    /* > 0, perspective                                */
 } vr_camera;
 
+/* Optional lighting: one global directional light (the viewer's lighting
+ * check box, User Interface section).  Each channel's gradient g is the
+ * central difference of its trilinear field over one voxel along each axis,
+ * (x(p + e_a) - x(p - e_a)) / (2 spacing_a) in world units (the six face
+ * points of the 3 x 3 x 3 neighbourhood of the sample); its normal is
+ * n = -g / |g| and its colour contribution is scaled by
+ * ambient + diffuse * max(0, n . l), l = direction / |direction| (ambient +
+ * diffuse where g = 0).  Opacity, early termination and sample counts do not
+ * change.  Under VR_FP16 the gradient is still taken in FP32.  A lit sample
+ * reads six more trilinear samples. */
+typedef struct {
+    int32_t enabled;      /* 0 off (all-zero struct: unlit), 1 on             */
+    float direction[3];   /* world space, towards the light; finite, non-zero */
+    float ambient;        /* [0, 1]                                           */
+    float diffuse;        /* [0, 1]                                           */
+} vr_light;
+
 /* One render request: a frame of a volume seen from a camera, one eye
  * (stereo = 0) or a left / right pair (stereo = 1, perspective only).
  * Samples sit at world distances t_enter + (k + 1/2) step along each ray
@@ -149,6 +166,7 @@ typedef struct {
     float* out_rgba;        /* device, [eyes][height][width][4] float32       */
     int32_t* out_samples;   /* device, [eyes][height][width] or NULL: samples
                                composited per pixel                          */
+    vr_light light;         /* lighting; zero-initialised = off              */
 } vr_render_req;
 
 /* Ticket state reported by vr_poll. */

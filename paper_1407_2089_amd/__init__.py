@@ -59,12 +59,18 @@ class vr_camera(C.Structure):
                 ("convergence", C.c_float)]
 
 
+class vr_light(C.Structure):
+    _fields_ = [("enabled", C.c_int32), ("direction", C.c_float * 3), ("ambient", C.c_float),
+                ("diffuse", C.c_float)]
+
+
 class vr_render_req(C.Structure):
     _fields_ = [("vol", C.c_void_p), ("frame", C.c_int32), ("cam", vr_camera),
                 ("width", C.c_int32), ("height", C.c_int32), ("stereo", C.c_int32),
                 ("step", C.c_float), ("term_alpha", C.c_float),
                 ("background", C.c_float * 4), ("precision", C.c_int32),
-                ("out_rgba", C.c_void_p), ("out_samples", C.c_void_p)]
+                ("out_rgba", C.c_void_p), ("out_samples", C.c_void_p),
+                ("light", vr_light)]
 
 
 class vr_ticket_info(C.Structure):
@@ -258,11 +264,19 @@ def make_camera(cam) -> vr_camera:
                      cam.ortho_height, cam.eye_separation, cam.convergence)
 
 
+def make_light(light):
+    """vr_light from an object with direction, ambient and diffuse (None: off)."""
+    if light is None:
+        return vr_light()
+    return vr_light(1, (C.c_float * 3)(*light.direction), light.ambient, light.diffuse)
+
+
 def make_request(vol, frame, cam, width, height, stereo, step, term_alpha, out_rgba,
-                 background=(0.0, 0.0, 0.0, 0.0), precision=VR_FP32, out_samples=None):
+                 background=(0.0, 0.0, 0.0, 0.0), precision=VR_FP32, out_samples=None,
+                 light=None):
     return vr_render_req(vol, frame, make_camera(cam), width, height, int(bool(stereo)),
                          step, term_alpha, (C.c_float * 4)(*background), precision,
-                         _ptr(out_rgba), _ptr(out_samples))
+                         _ptr(out_rgba), _ptr(out_samples), make_light(light))
 
 
 # --------------------------------------------------------- torch helpers

@@ -183,6 +183,22 @@ vr_status check_request(const vr_ctx* ctx, const vr_render_req* r) {
         return fail(VR_ERR_INVALID_ARG, "precision %d is unknown", r->precision);
     vr_status st = check_camera(r->cam, r->stereo == 1);
     if (st != VR_OK) return st;
+    const vr_light& L = r->light;
+    if (L.enabled != 0 && L.enabled != 1)
+        return fail(VR_ERR_INVALID_ARG, "light.enabled must be 0 or 1");
+    if (L.enabled) {
+        double n2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(L.direction[a]))
+                return fail(VR_ERR_INVALID_ARG, "light.direction[%d] is not finite", a);
+            n2 += (double)L.direction[a] * L.direction[a];
+        }
+        if (!(n2 > 0.0)) return fail(VR_ERR_INVALID_ARG, "light.direction is zero");
+        if (!(L.ambient >= 0.0f) || !(L.ambient <= 1.0f))
+            return fail(VR_ERR_INVALID_ARG, "light.ambient %g outside [0, 1]", L.ambient);
+        if (!(L.diffuse >= 0.0f) || !(L.diffuse <= 1.0f))
+            return fail(VR_ERR_INVALID_ARG, "light.diffuse %g outside [0, 1]", L.diffuse);
+    }
     if ((int64_t)r->width * r->height > 0 && !r->out_rgba)
         return fail(VR_ERR_INVALID_ARG, "out_rgba is NULL");
     return VR_OK;
@@ -356,6 +372,18 @@ void make_params(const vr_render_req& r, const vr_transfer* tf_in, ReqParams* P)
         P->tmin = -std::numeric_limits<float>::infinity();
     }
     for (int a = 0; a < 3; ++a) P->inv_sp[a] = (float)(1.0 / sp[a]);
+    if (r.light.enabled) {
+        double l[3] = {r.light.direction[0], r.light.direction[1], r.light.direction[2]};
+        normalise(l);
+        const double smin = std::min(sp[0], std::min(sp[1], sp[2]));
+        for (int a = 0; a < 3; ++a) {
+            P->light.dir[a] = (float)l[a];
+            P->light.gscale[a] = (float)(smin / sp[a]);
+        }
+        P->light.ka = r.light.ambient;
+        P->light.kd = r.light.diffuse;
+        P->light.on = 1;
+    }
     P->step = r.step;
     P->tau = r.term_alpha;
     const double bga = r.background[3];

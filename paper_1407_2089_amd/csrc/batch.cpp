@@ -5,7 +5,8 @@
 // first, so one large view does not become the tail.  The launch (one kernel
 // per variant present) is captured per stream, variant set and grid size
 // into a HIP graph whose arguments point at fixed device tables; each batch
-// only rewrites the tables.
+// only rewrites the tables.  Lit requests are launched one by one with the
+// plain (lit) kernels on the same stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -233,6 +234,25 @@ static vr_status tune(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
 vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
                         bool allow_tuning) {
     if (n <= 0) return VR_OK;
+    // Lit requests take plain launches on the slot's stream (the batch
+    // kernels are unlit); the rest form the batch.
+    std::vector<ReqParams> unlit;
+    bool any_lit = false;
+    for (int q = 0; q < n && !any_lit; ++q) any_lit = params[q].light.on != 0;
+    if (any_lit) {
+        for (int q = 0; q < n; ++q) {
+            if (!params[q].light.on) {
+                unlit.push_back(params[q]);
+                continue;
+            }
+            const hipError_t e = launch_render(params[q], ctx->plain_tile, ctx->clear_skip,
+                                               s->stream);
+            if (e != hipSuccess) return hip_fail(e, "lit render launch");
+        }
+        params = unlit.data();
+        n = (int)unlit.size();
+        if (n == 0) return VR_OK;
+    }
     TileShape ts = ctx->batch_tile;
     if (!ctx->forced_tile && ctx->autotune) {
         const uint64_t key = shape_class(params, n);

@@ -77,8 +77,9 @@ __global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* 
 // full (same output bits; kept to test and time the transparent-sample skip).
 // Tiles of an eye run super-tile by super-tile (row-major over super-tiles of
 // kSuperW x kSuperH tiles, row-major inside each); the grid covers whole
-// super-tiles, and lanes past the image edge are invalid.
-template <int V, bool kClear>
+// super-tiles, and lanes past the image edge are invalid.  kLit: lit by the
+// request's directional light.
+template <int V, bool kClear, bool kLit>
 __global__ __launch_bounds__(kWave) void render_kernel(ReqParams P, TileShape ts, int supers_x,
                                                        int per_eye) {
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
@@ -89,7 +90,7 @@ __global__ __launch_bounds__(kWave) void render_kernel(ReqParams P, TileShape ts
     const int px = tx * ts.wave_w + lane % ts.wave_w;
     const int py = ty * ts.wave_h + lane / ts.wave_w;
     const bool valid = px < P.width && py < P.height;
-    render_pixel<V, kClear>(P, eye, valid ? px : 0, valid ? py : 0, valid);
+    render_pixel<V, kClear, kLit>(P, eye, valid ? px : 0, valid ? py : 0, valid);
 }
 
 // -------------------------------------------------------- batched render
@@ -192,21 +193,24 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
 }
 
 typedef void (*render_fn)(ReqParams, TileShape, int, int);
-template <int V, bool kClear> constexpr render_fn render_entry() {
-    if constexpr (variant_exists(V)) return render_kernel<V, kClear>;
+template <int V, bool kClear, bool kLit> constexpr render_fn render_entry() {
+    if constexpr (variant_exists(V)) return render_kernel<V, kClear, kLit>;
     else return nullptr;
 }
-template <bool kClear, int... V>
+template <bool kClear, bool kLit, int... V>
 constexpr std::array<render_fn, kVariants> render_table(std::integer_sequence<int, V...>) {
-    return {{render_entry<V, kClear>()...}};
+    return {{render_entry<V, kClear, kLit>()...}};
 }
-static const std::array<render_fn, kVariants> kRender[2] = {
-    render_table<false>(std::make_integer_sequence<int, kVariants>{}),
-    render_table<true>(std::make_integer_sequence<int, kVariants>{})};
+// [lit][clear_skip][variant]
+static const std::array<render_fn, kVariants> kRender[2][2] = {
+    {render_table<false, false>(std::make_integer_sequence<int, kVariants>{}),
+     render_table<true, false>(std::make_integer_sequence<int, kVariants>{})},
+    {render_table<false, true>(std::make_integer_sequence<int, kVariants>{}),
+     render_table<true, true>(std::make_integer_sequence<int, kVariants>{})}};
 
 hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_skip,
                          hipStream_t s) {
-    if (P.variant < 0 || P.variant >= kVariants || !kRender[0][P.variant])
+    if (P.variant < 0 || P.variant >= kVariants || !kRender[0][0][P.variant])
         return hipErrorInvalidValue;
     if (ts.wave_w <= 0 || ts.wave_h <= 0 || ts.wave_w * ts.wave_h != kWave)
         return hipErrorInvalidValue;
@@ -215,7 +219,8 @@ hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_ski
     const long long blocks = per_eye * P.eyes;
     if (blocks == 0) return hipSuccess;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(kRender[clear_skip ? 1 : 0][P.variant], dim3((unsigned)blocks),
+    hipLaunchKernelGGL(kRender[P.light.on ? 1 : 0][clear_skip ? 1 : 0][P.variant],
+                       dim3((unsigned)blocks),
                        dim3(kWave), 0, s, P, ts, (int)supers_x, (int)per_eye);
     return hipGetLastError();
 }

@@ -407,7 +407,40 @@ template <int V> struct Variant {
 
 // One pixel of one eye: returns nothing, writes RGBA (and the sample count).
 // `valid` false lanes take part in the wave's loop structure but do no work.
-template <int V, bool kClear = true>
+// Lambert shade of every channel at stored-coordinate point q: the gradient
+// of each channel's trilinear field by central differences over one voxel per
+// axis (six FP32 samples, also under FP16 sampling: FP16 lerps would turn a
+// small gradient's direction), the normal against it, one directional light.
+template <int C, bool U16, bool PAIRS, typename Word>
+__device__ __forceinline__ void shade_at(const ReqParams& P, const Sampler& S, const float (&q)[3],
+                                         float (&shade)[C]) {
+    float g[3][C];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        float hi[C], lo[C];
+        interpolate<C, U16, false>(fetch<Word, PAIRS>(P.g, S, a == 0 ? q[0] + 1.0f : q[0],
+                                                      a == 1 ? q[1] + 1.0f : q[1],
+                                                      a == 2 ? q[2] + 1.0f : q[2]), hi);
+        interpolate<C, U16, false>(fetch<Word, PAIRS>(P.g, S, a == 0 ? q[0] - 1.0f : q[0],
+                                                      a == 1 ? q[1] - 1.0f : q[1],
+                                                      a == 2 ? q[2] - 1.0f : q[2]), lo);
+#pragma unroll
+        for (int c = 0; c < C; ++c) g[a][c] = (hi[c] - lo[c]) * P.light.gscale[a];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const float gg = fmaf(g[0][c], g[0][c], fmaf(g[1][c], g[1][c], g[2][c] * g[2][c]));
+        const float dot = -fmaf(g[0][c], P.light.dir[0],
+                                fmaf(g[1][c], P.light.dir[1], g[2][c] * P.light.dir[2]));
+        // gg below 2^-100 (never reached by a non-zero difference of raw
+        // samples at a sane spacing ratio) counts as no gradient, keeping
+        // rsqrt away from denormals.
+        const float diff = gg > 0x1p-100f ? fmaxf(dot, 0.0f) * rsqrtf(gg) : 1.0f;
+        shade[c] = fmaf(P.light.kd, diff, P.light.ka);
+    }
+}
+
+template <int V, bool kClear = true, bool kLit = false>
 __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px, int py,
                                              bool valid) {
     constexpr int C = Variant<V>::C;
@@ -480,10 +513,19 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
     // the arithmetic when that holds for all of its lanes, the common case in
     // the empty, below-floor space around stained structures.
     const bool clear_ok = kClear && P.clear.ok != 0;
-    auto composite = [&](const Taps<Word>& t, bool on) {
+    // Lit (kLit): each channel's colour term is scaled by its shade at the
+    // sample point (the opacity is not).
+    auto composite = [&](const Taps<Word>& t, bool on, int j) {
         if (!on || (clear_ok && transparent<C, U16>(t, P.clear))) return;
         float x[C];
         interpolate<C, U16, F16>(t, x);
+        float shade[C];
+        if constexpr (kLit) {
+            const float sj = fmaf((float)j, P.step, half_step);
+            const float q[3] = {fmaf(sj, d[0], pe[0]), fmaf(sj, d[1], pe[1]),
+                                fmaf(sj, d[2], pe[2])};
+            shade_at<C, U16, PAIRS, Word>(P, S, q, shade);
+        }
         float amax = 0.0f, r = 0.0f, gg = 0.0f, bb = 0.0f;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -491,9 +533,10 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
                                                    1.0f);
             const float g = u * fmaf(tf[c].curve, u, tf[c].one_m_curve);
             amax = fmaxf(amax, tf[c].alpha_mul * g);
-            r = fmaf(g, tf[c].rgb[0], r);
-            gg = fmaf(g, tf[c].rgb[1], gg);
-            bb = fmaf(g, tf[c].rgb[2], bb);
+            const float gc = kLit ? g * shade[c] : g;
+            r = fmaf(gc, tf[c].rgb[0], r);
+            gg = fmaf(gc, tf[c].rgb[1], gg);
+            bb = fmaf(gc, tf[c].rgb[2], bb);
         }
         const float a_s = fminf(amax, 1.0f);
         const float wgt = (1.0f - A) * a_s;
@@ -521,11 +564,11 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         bool live;
         do {
             const Taps<Word> b = fetch_at(k + 1);
-            composite(a, true);
+            composite(a, true, k);
             ++k;
             const bool on = k < n && A < tau;
             a = fetch_at(k + 1);
-            composite(b, on);
+            composite(b, on, k);
             k += on ? 1 : 0;
             live = on && k < n && A < tau;
         } while (live);

@@ -67,6 +67,17 @@ struct ChanTF {
     float rgb[3];        // 0 for an invisible channel
 };
 
+// Global directional light of a request.  A channel's gradient is taken in
+// raw units per voxel along each axis and scaled by gscale = min spacing /
+// spacing (the world-space direction, kept in range); its shade is
+// ka + kd * max(0, -g . dir / |g|), or ka + kd where g = 0.
+struct Light {
+    float dir[3];        // unit, world space, towards the light
+    float ka, kd;        // ambient and diffuse weights
+    float gscale[3];
+    int32_t on;
+};
+
 // Transparency thresholds of a request.  A sample whose eight taps of every
 // channel c are at most tmax[c] (raw units) has opacity exactly 0 in the
 // kernel's own arithmetic (FP32 or FP16 interpolation), so compositing it
@@ -91,6 +102,7 @@ struct ReqParams {
     int32_t variant;
     ChanTF tf[kMaxChannels];
     Transparent clear;      // transparent-sample test of this request's TFs
+    Light light;
     // Rays.  Index-space origin p0 = o0[eye] + sx * ou + sy * ov; world
     // direction w = base[eye] + sx * du + sy * dv, unit-normalised, then
     // index-space direction d = w * inv_sp.

@@ -30,7 +30,7 @@ def request_for(vol, scene, out, samples=None, precision=vr.VR_FP32, frame=0, ca
     return vr.make_request(vol.ptr, frame, cam or scene.cam, scene.width, scene.height,
                            scene.stereo, scene.step,
                            scene.term_alpha if term_alpha is None else term_alpha, out,
-                           scene.background, precision, samples)
+                           scene.background, precision, samples, scene.light)
 
 
 def alloc_out(scene):
@@ -67,16 +67,22 @@ def compare(rgba, samples, ref, tol, count_slack=2e-3, pixels=None):
     oracle's band [band_lo - tol, band_hi + tol].  Sample counts must equal
     the oracle's, except by one where the real-valued count is within
     count_slack of an integer, and anywhere inside the band's count range.
+    Lit renders widen each pixel's colour tolerance by the oracle's
+    lit_margin (the reach of FP32 gradient rounding).
     Returns a stats dict; raises AssertionError on failure."""
     rgba = np.asarray(rgba, np.float64).reshape(-1, 4)
     ref_rgba = ref["rgba"].reshape(-1, 4)
     lo = ref["band_lo"].reshape(-1, 4)
     hi = ref["band_hi"].reshape(-1, 4)
     bk = ref["band_k"].reshape(-1, 2)
-    err = np.abs(rgba - ref_rgba).max(-1)
+    tolv = np.full(rgba.shape, float(tol))
+    if "lit_margin" in ref:
+        tolv[:, :3] += ref["lit_margin"].reshape(-1)[:, None]
+    err_c = np.abs(rgba - ref_rgba)
+    err = err_c.max(-1)
     in_band = bk[:, 0] >= 0
-    band_ok = in_band & np.all((rgba >= lo - tol) & (rgba <= hi + tol), axis=-1)
-    passed = (err <= tol) | band_ok
+    band_ok = in_band & np.all((rgba >= lo - tolv) & (rgba <= hi + tolv), axis=-1)
+    passed = np.all(err_c <= tolv, axis=-1) | band_ok
     n_fail = int((~passed).sum())
     stats = {"max_err": float(err.max()) if err.size else 0.0,
              "max_err_outside_band": float(err[~in_band].max()) if (~in_band).any() else 0.0,
