@@ -23,6 +23,11 @@ PEAK_HBM_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "render_2ch_u16_realistic_stereo_counters.txt")
 
 
+def _light():
+    from paper_1407_2089_amd.synth import Light
+    return Light((0.4, -0.3, -0.8), 0.3, 0.7)
+
+
 def render_kernel_hash():
     """sha256 of the render kernel's source (march.h, params.h and the plain
     render kernel's part of kernels.hip)."""
@@ -78,9 +83,10 @@ def log(msg):
 
 
 def cpu_baseline(scene, target_s=10.0):
-    """Time the FP64 oracle on the host: the whole stereo pair, repeated until
-    about target_s seconds have passed, on every host thread; plus one
-    thread on 2^16 seeded pixels per eye."""
+    """Time the FP64 oracle on the host: the whole stereo pair (lit: 2^18
+    seeded pixels per eye), repeated until about target_s seconds have
+    passed, on every host thread; plus one thread on 2^16 seeded pixels per
+    eye."""
     import numpy as np
 
     import oracle
@@ -90,29 +96,34 @@ def cpu_baseline(scene, target_s=10.0):
     c = scene.cam
     cam = oracle.Camera(c.projection, c.center, c.forward, c.up, c.fov_y, c.ortho_height,
                         c.eye_separation, c.convergence)
+    lt = scene.light
+    light = None if lt is None else oracle.Light(lt.direction, lt.ambient, lt.diffuse)
 
     def run(pixels, threads):
         s = 0
         for eye in (-1, 1):
             r = oracle.render(ov, tfs, cam, scene.width, scene.height, eye, scene.step,
-                              scene.term_alpha, pixels=pixels, nthreads=threads)
+                              scene.term_alpha, pixels=pixels, nthreads=threads, light=light)
             s += int(r["samples"].sum())
         return s
 
+    rng = np.random.default_rng(12345)
+    npix = scene.width * scene.height
+    many = None if light is None else rng.choice(npix, size=min(npix, 1 << 18), replace=False)
     t0 = time.perf_counter()
     samples, reps = 0, 0
     while reps == 0 or time.perf_counter() - t0 < target_s:
-        samples += run(None, cores)
+        samples += run(many, cores)
         reps += 1
     dt = time.perf_counter() - t0
-    rng = np.random.default_rng(12345)
-    pix = rng.choice(scene.width * scene.height, size=1 << 16, replace=False)
+    pix = rng.choice(npix, size=1 << 16, replace=False)
     t1 = time.perf_counter()
     s1 = run(pix, 1)
     dt1 = time.perf_counter() - t1
+    what = (f"the whole stereo pair ({2 * npix} rays)" if many is None
+            else f"2 x {many.size} seeded pixels, lit")
     return {"value": samples / dt, "unit": "ray-samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"the whole stereo pair ({2 * scene.width * scene.height} rays) x {reps}, "
-                      f"FP64, {dt:.1f} s on {cores} threads",
+            "sample": f"{what} x {reps}, FP64, {dt:.1f} s on {cores} threads",
             "value_1thread": s1 / dt1,
             "sample_1thread": f"2 x 65536 seeded pixels, {dt1:.1f} s"}
 
@@ -174,6 +185,9 @@ def main():
                          "pairs (default; two 16-byte loads per sample for the realistic "
                          "frame, 2.2x the storage) or plain bricks (the library's default "
                          "layout)")
+    ap.add_argument("--lit", action="store_true",
+                    help="light the realistic frame (one directional light, gradients from "
+                         "central differences); also times the unlit kernel for the ratio")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-gb", type=float, default=150.0)
     ap.add_argument("--serve-rates", default="25,100,400,1000,1600,2400,3200,4000")
@@ -226,6 +240,8 @@ def main():
 
     log("generating workload")
     sc = synth.realistic_scene()
+    if args.lit:
+        sc.light = _light()
     ctx = vr.Context(0)
     c, nz, ny, nx = sc.volume.shape
     brick = tuple(int(b) for b in args.brick.split(","))
@@ -243,37 +259,45 @@ def main():
 
     # Count the composited samples of one step (the frame is the same every step).
     req_count = vr.make_request(vol.ptr, 0, sc.cam, sc.width, sc.height, True, sc.step,
-                                sc.term_alpha, out, precision=prec, out_samples=smp)
+                                sc.term_alpha, out, precision=prec, out_samples=smp,
+                                light=sc.light)
     vr.vr_render(ctx.ptr, req_count, stream)
     torch.cuda.synchronize()
     samples_per_step = int(smp.sum().item())
     req = vr.make_request(vol.ptr, 0, sc.cam, sc.width, sc.height, True, sc.step,
-                          sc.term_alpha, out, precision=prec)
+                          sc.term_alpha, out, precision=prec, light=sc.light)
 
-    log(f"warmup {args.warmup}")
-    for _ in range(args.warmup):
-        vr.vr_render(ctx.ptr, req, stream)
-    torch.cuda.synchronize()
+    def timed(r):
+        log(f"warmup {args.warmup}")
+        for _ in range(args.warmup):
+            vr.vr_render(ctx.ptr, r, stream)
+        torch.cuda.synchronize()
+        log(f"timing {args.steps} steps")
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ev[k][0].record(stream)
+            vr.vr_render(ctx.ptr, r, stream)
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return wall, float(np.mean([a.elapsed_time(b) for a, b in ev]))
 
-    log(f"timing {args.steps} steps")
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ev[k][0].record(stream)
-        vr.vr_render(ctx.ptr, req, stream)
-        ev[k][1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    wall, kernel_ms = timed(req)
     ms_per_step = 1000.0 * wall / args.steps
     value = samples_per_step * args.steps / wall
+    unlit_ms = None
+    if args.lit:
+        log("unlit kernel for the ratio")
+        _, unlit_ms = timed(vr.make_request(vol.ptr, 0, sc.cam, sc.width, sc.height, True,
+                                            sc.step, sc.term_alpha, out, precision=prec))
 
     bytes_per_sample = 8 * c * 2
     alg_bytes = samples_per_step * bytes_per_sample
     headline_layout = (args.precision == "fp32" and brick == (0, 0, 0) and not args.tile
-                       and pairs)
+                       and pairs and not args.lit)
     counters = measured_counters() if headline_layout else {}
     traffic = counters.get("traffic")
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
@@ -291,7 +315,8 @@ def main():
         "dtype": "f16-sample/f32-composite" if prec == vr.VR_FP16 else "f32",
         "data": "synthetic",
         "config": {"workload": "realistic frame: 2ch u16-12 512x512x64 cells+vessels, "
-                               "perspective stereo 1920x1080 per eye, step 1, alpha 0.99",
+                               "perspective stereo 1920x1080 per eye, step 1, alpha 0.99"
+                               + (", lit (one directional light)" if args.lit else ""),
                    "eyes": 2, "width": sc.width, "height": sc.height, "brick": list(brick),
                    "layout": args.layout, "storage_bytes": vol.bytes,
                    "tile": args.tile or "8,8",
@@ -301,7 +326,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "traffic_unit": "bytes/launch (L2-to-fabric FETCH_SIZE + WRITE_SIZE, "
                                      "copy-calibrated)",
-                     "kernel": f"render_kernel<2ch,u16,{args.precision},{args.layout}>",
+                     "kernel": f"render_kernel<2ch,u16,{args.precision},{args.layout}"
+                               + (",lit>" if args.lit else ">"),
                      "kernel_ms": kernel_ms, "bytes_per_launch": alg_bytes,
                      # effective bytes price every tap as an HBM byte; the measured
                      # fabric-side rate of the same launches, for comparison:
@@ -311,6 +337,14 @@ def main():
                      "valu_busy": counters.get("valu_busy"),
                      "ta_busy": counters.get("ta_busy")},
     }
+    if args.lit:
+        result["config"]["light"] = {"direction": list(sc.light.direction),
+                                     "ambient": sc.light.ambient, "diffuse": sc.light.diffuse}
+        # effective bytes count the sample's own 8 taps only; the six gradient
+        # samples of each shaded sample are not priced
+        result["roofline"]["bytes_note"] = "8 taps per sample; gradient samples not counted"
+        result["unlit_kernel_ms"] = unlit_ms
+        result["lit_over_unlit"] = kernel_ms / unlit_ms
     vol.destroy()
     ctx.close()
     if not args.no_cpu:
