@@ -19,7 +19,9 @@ __all__ = [
     "vr_create_volume", "vr_upload_frame", "vr_destroy_volume", "vr_set_transfer",
     "vr_render", "vr_render_batch", "vr_submit", "vr_poll", "vr_release",
     "vr_last_error", "vr_debug_sample", "Context", "Volume", "VR_U8", "VR_U16",
-    "VR_FP32", "VR_FP16", "VR_ORTHO", "VR_PERSPECTIVE",
+    "VR_FP32", "VR_FP16", "VR_ORTHO", "VR_PERSPECTIVE", "vr_denoise_workspace_bytes",
+    "vr_remove_background", "vr_mrf_denoise", "gaussian_weights", "remove_background",
+    "mrf_denoise",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvr.so")
@@ -73,6 +75,20 @@ class vr_render_req(C.Structure):
                 ("light", vr_light)]
 
 
+class vr_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("dtype", C.c_int32),
+                ("bits", C.c_int32)]
+
+
+class vr_lowpass(C.Structure):
+    _fields_ = [("w", C.POINTER(C.c_uint32) * 3), ("taps", C.c_int32 * 3), ("shift", C.c_int32)]
+
+
+class vr_mrf_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("delta", C.c_int32), ("sigma", C.c_double),
+                ("rms", C.c_double)]
+
+
 class vr_ticket_info(C.Structure):
     _fields_ = [("state", C.c_int32), ("err", C.c_int32), ("t_arrive_ns", C.c_uint64),
                 ("t_admit_ns", C.c_uint64), ("t_start_ns", C.c_uint64),
@@ -105,6 +121,11 @@ def lib():
             "vr_poll": [P, C.c_uint64, C.POINTER(vr_ticket_info)],
             "vr_release": [P, C.c_uint64],
             "vr_debug_sample": [P, C.c_int32, P, C.c_int32, P, P],
+            "vr_denoise_workspace_bytes": [C.POINTER(vr_grid), C.POINTER(C.c_uint64)],
+            "vr_remove_background": [P, C.POINTER(vr_grid), C.POINTER(vr_lowpass), P, P, P, P,
+                                     C.c_uint64, P],
+            "vr_mrf_denoise": [P, C.POINTER(vr_grid), C.c_int32, P, P, P, C.c_uint64, P,
+                               C.POINTER(vr_mrf_info)],
             "vr_test_fake_backend": [P, C.c_int32, C.c_double, C.c_int32, C.c_int32],
             "vr_test_batch_tile": [P, C.c_int32, C.c_int32],
             "vr_test_plain_tile": [P, C.c_int32, C.c_int32],
@@ -215,6 +236,91 @@ def vr_release(ctx, ticket: int):
 
 def vr_debug_sample(vol, frame: int, pts, n: int, out, stream=None):
     _check(lib().vr_debug_sample(vol, frame, _ptr(pts), n, _ptr(out), _stream(stream)))
+
+
+# ------------------------------------------------------------- denoising
+
+def make_grid(nx, ny, nz, dtype, bits):
+    return vr_grid(nx, ny, nz, dtype, bits)
+
+
+def vr_denoise_workspace_bytes(grid) -> int:
+    n = C.c_uint64()
+    _check(lib().vr_denoise_workspace_bytes(C.byref(grid), C.byref(n)))
+    return n.value
+
+
+def make_lowpass(wx, wy, wz, shift):
+    """vr_lowpass from three integer weight lists (kept alive on the struct)."""
+    arrs = [(C.c_uint32 * len(w))(*[int(v) for v in w]) for w in (wx, wy, wz)]
+    lp = vr_lowpass((C.POINTER(C.c_uint32) * 3)(*[C.cast(a, C.POINTER(C.c_uint32))
+                                                    for a in arrs]),
+                    (C.c_int32 * 3)(*[len(w) for w in (wx, wy, wz)]), int(shift))
+    lp._keep = arrs
+    return lp
+
+
+def vr_remove_background(ctx, grid, lp, src, dst, background, workspace, workspace_bytes,
+                         stream=None):
+    _check(lib().vr_remove_background(ctx, C.byref(grid), C.byref(lp), _ptr(src), _ptr(dst),
+                                      _ptr(background), _ptr(workspace), workspace_bytes,
+                                      _stream(stream)))
+
+
+def vr_mrf_denoise(ctx, grid, max_iters, src, dst, workspace, workspace_bytes, stream=None):
+    info = vr_mrf_info()
+    _check(lib().vr_mrf_denoise(ctx, C.byref(grid), max_iters, _ptr(src), _ptr(dst),
+                                _ptr(workspace), workspace_bytes, _stream(stream),
+                                C.byref(info)))
+    return info
+
+
+def gaussian_weights(sigma, shift=14, radius=None):
+    """Integer weights of a sampled Gaussian (radius ceil(3 sigma), at most
+    64) that sum to exactly 2^shift: rounded, the remainder put on the
+    centre tap."""
+    import math
+    r = min(64, int(math.ceil(3.0 * sigma))) if radius is None else int(radius)
+    g = [math.exp(-0.5 * (k / sigma) ** 2) for k in range(-r, r + 1)]
+    tot = sum(g)
+    w = [int(round((1 << shift) * x / tot)) for x in g]
+    w[r] += (1 << shift) - sum(w)
+    return w
+
+
+def _grid_of(vol, bits):
+    import torch
+    nz, ny, nx = vol.shape
+    dtype = VR_U8 if vol.dtype == torch.uint8 else VR_U16
+    return make_grid(nx, ny, nz, dtype, bits)
+
+
+def _workspace(grid, device):
+    import torch
+    n = vr_denoise_workspace_bytes(grid)
+    return torch.empty(n, dtype=torch.uint8, device=device), n
+
+
+def remove_background(ctx, vol, wx, wy, wz, shift, bits, stream=None):
+    """Background removal of a [Z][Y][X] uint8 / int16-viewed uint16 device
+    tensor: returns (denoised, background) as new tensors of the same type."""
+    import torch
+    grid = _grid_of(vol, bits)
+    ws, n = _workspace(grid, vol.device)
+    dst, bg = torch.empty_like(vol), torch.empty_like(vol)
+    vr_remove_background(ctx.ptr, grid, make_lowpass(wx, wy, wz, shift), vol, dst, bg, ws, n,
+                         stream)
+    return dst, bg
+
+
+def mrf_denoise(ctx, vol, bits, max_iters, stream=None):
+    """Sign-diffusion denoising of a [Z][Y][X] device tensor: (result, info)."""
+    import torch
+    grid = _grid_of(vol, bits)
+    ws, n = _workspace(grid, vol.device)
+    dst = torch.empty_like(vol)
+    info = vr_mrf_denoise(ctx.ptr, grid, max_iters, vol, dst, ws, n, stream)
+    return dst, info
 
 
 def vr_test_batch_tile(ctx, wave_w=0, wave_h=0):

@@ -26,7 +26,9 @@ def test_library_exports_every_declared_symbol():
     L = vr.lib()
     names = declared_symbols()
     assert "vr_render" in names and "vr_submit" in names and len(names) == 14
-    for n in names + declared_symbols("vr_test.h"):
+    dn = declared_symbols("vr_denoise.h")
+    assert dn == ["vr_denoise_workspace_bytes", "vr_mrf_denoise", "vr_remove_background"]
+    for n in names + declared_symbols("vr_test.h") + dn:
         assert hasattr(L, n), n
 
 
@@ -335,3 +337,71 @@ def test_transparent_threshold_is_safe_and_tight(lo, hi, bits):
     floor_raw = F(float(np.float32(lo))) * full
     assert t <= floor_raw
     assert t >= floor_raw / margin - 2
+
+
+# ------------------------------------------------------------- denoising
+
+def test_denoise_workspace_bytes():
+    g = vr.make_grid(100, 37, 9, vr.VR_U16, 12)
+    vol = (100 * 37 * 9 * 2 + 255) // 256 * 256
+    assert vr.vr_denoise_workspace_bytes(g) == 2 * vol + 256 + 65536
+    g = vr.make_grid(1, 1, 1, vr.VR_U8, 8)
+    assert vr.vr_denoise_workspace_bytes(g) == 2 * 256 + 256 + 65536
+
+
+@pytest.mark.parametrize("grid", [(0, 4, 4, 1, 8), (4, 4, 4, 3, 8), (4, 4, 4, 1, 12),
+                                  (4, 4, 4, 2, 8), (4, 4, 4, 2, 17), (2048, 2048, 512, 1, 8)])
+def test_denoise_rejects_bad_grids(grid):
+    g = vr.make_grid(*grid)
+    with pytest.raises(vr.VrError) as e:
+        vr.vr_denoise_workspace_bytes(g)
+    assert e.value.status == vr.VR_ERR_INVALID_ARG
+
+
+BASE = 1 << 40
+GOOD_W = [1, 2, 1]
+
+
+def bg_call(vctx, g, lp, src=BASE, dst=BASE + (1 << 30), bg=None, ws=BASE + (2 << 30), n=None):
+    n = vr.vr_denoise_workspace_bytes(g) if n is None else n
+    return vr.vr_remove_background(vctx, g, lp, src, dst, bg, ws, n)
+
+
+def test_remove_background_validation(vctx):
+    g = vr.make_grid(40, 30, 20, vr.VR_U16, 12)
+    ok = vr.make_lowpass(GOOD_W, [4], vr.gaussian_weights(2.0, 2), 2)
+    expect(vr.VR_ERR_UNSUPPORTED, lambda: bg_call(vctx, g, ok))
+    expect(vr.VR_ERR_UNSUPPORTED, lambda: bg_call(vctx, g, ok, bg=BASE + (3 << 30)))
+    bad = [vr.make_lowpass([1, 2, 2], GOOD_W, GOOD_W, 2),      # sum 5
+           vr.make_lowpass([1, 3], GOOD_W, GOOD_W, 2),         # even taps
+           vr.make_lowpass([1] * 131, GOOD_W, GOOD_W, 2),      # too many taps
+           vr.make_lowpass([0, 2 ** 17, 0], [2 ** 17], [2 ** 17], 17)]  # shift > 16
+    for lp in bad:
+        expect(vr.VR_ERR_INVALID_ARG, lambda: bg_call(vctx, g, lp))
+    expect(vr.VR_ERR_INVALID_ARG, lambda: bg_call(vctx, g, ok, n=1000))             # small workspace
+    expect(vr.VR_ERR_INVALID_ARG, lambda: bg_call(vctx, g, ok, dst=BASE + 100))     # overlaps src
+    expect(vr.VR_ERR_INVALID_ARG, lambda: bg_call(vctx, g, ok, bg=BASE + (2 << 30) + 512))  # in ws
+    expect(vr.VR_ERR_INVALID_ARG, lambda: bg_call(vctx, g, ok, src=None))
+    # buffers that only touch are fine
+    expect(vr.VR_ERR_UNSUPPORTED, lambda: bg_call(vctx, g, ok, dst=BASE + 40 * 30 * 20 * 2))
+
+
+def test_gaussian_weights_sum_to_a_power_of_two():
+    for sigma, shift in [(0.5, 8), (1.0, 14), (2.5, 16), (30.0, 16)]:
+        w = vr.gaussian_weights(sigma, shift)
+        assert sum(w) == 1 << shift and len(w) % 2 == 1 and len(w) <= 129
+        assert w == w[::-1] and max(w) == w[len(w) // 2]
+
+
+def test_mrf_validation(vctx):
+    g = vr.make_grid(16, 16, 16, vr.VR_U8, 8)
+    n = vr.vr_denoise_workspace_bytes(g)
+    expect(vr.VR_ERR_UNSUPPORTED, vr.vr_mrf_denoise, vctx, g, 10, BASE, BASE + 8192,
+           BASE + 65536, n)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_mrf_denoise, vctx, g, -1, BASE, BASE + 8192,
+           BASE + 65536, n)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_mrf_denoise, vctx, g, 10, BASE, BASE + 100,
+           BASE + 65536, n)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_mrf_denoise, vctx, g, 10, BASE, BASE + 8192,
+           BASE + 65536, n - 1)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_mrf_denoise, vctx, g, 10, BASE, None, BASE + 65536, n)

@@ -1,0 +1,189 @@
+"""GPU parity of the pre-render denoisers (Methods, Background Noise Removal)
+against the exact-integer oracle: background removal (low-pass, subtraction,
+3x3x3 median) and the sign-diffusion iteration, bit for bit, on ragged and
+degenerate shapes that span several tiles; at the full frame size on crops
+the oracle computes exactly and through properties that hold at any size."""
+import numpy as np
+import pytest
+
+import paper_1407_2089_amd as vr
+from oracle import denoise as dn
+from paper_1407_2089_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    torch.cuda.init()
+    c = vr.Context(0)
+    yield c
+    try:
+        c.close()
+    except vr.VrError:
+        pass
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def to_dev(a):
+    import torch
+    a = np.ascontiguousarray(a)
+    return torch.from_numpy(a.view(np.int16) if a.dtype == np.uint16 else a).cuda()
+
+
+def to_host(t, dtype):
+    a = t.cpu().numpy()
+    return a.view(np.uint16) if dtype == np.uint16 else a
+
+
+def noisy_volume(shape, dtype, bits, seed):
+    """Blobs plus a slow background ramp plus shot noise."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    full = (1 << bits) - 1
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    v = 0.1 * full * (x / max(nx, 1) + 0.5 * y / max(ny, 1))
+    for _ in range(max(1, nx * ny * nz // 4000)):
+        c = rng.uniform(0, 1, 3) * np.array([nz, ny, nx])
+        s = rng.uniform(1.0, 3.0)
+        v = v + rng.uniform(0.3, 0.8) * full * np.exp(
+            -((z - c[0]) ** 2 + (y - c[1]) ** 2 + (x - c[2]) ** 2) / (2 * s * s))
+    v = v + rng.normal(0, 0.03 * full, size=shape)
+    return np.clip(np.rint(v), 0, full).astype(dtype)
+
+
+SHAPES = [(1, 1, 1), (1, 5, 3), (3, 2, 300), (9, 33, 70), (70, 67, 130), (66, 130, 7)]
+KERNELS = {
+    "gauss": (vr.gaussian_weights(2.0, 14), vr.gaussian_weights(1.5, 14),
+              vr.gaussian_weights(3.0, 14), 14),
+    "wide": (vr.gaussian_weights(20.0, 16), vr.gaussian_weights(10.0, 16),
+             [1 << 14, 1 << 15, 1 << 14], 16),
+    "odd": ([0, 0, 4], [4], [1, 0, 3], 2),
+}
+
+
+@pytest.mark.parametrize("kern", list(KERNELS))
+@pytest.mark.parametrize("dtype,bits", [(np.uint8, 8), (np.uint16, 12), (np.uint16, 16)])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_background_removal_bitwise(ctx, shape, dtype, bits, kern):
+    wx, wy, wz, shift = KERNELS[kern]
+    log(f"background {shape} {dtype.__name__}-{bits} {kern}")
+    v = noisy_volume(shape, dtype, bits, sum(shape) + bits)
+    out, b = vr.remove_background(ctx, to_dev(v), wx, wy, wz, shift, bits)
+    exp, exp_b = dn.remove_background(v, wx, wy, wz, shift)
+    assert np.array_equal(to_host(b, dtype), exp_b)
+    assert np.array_equal(to_host(out, dtype), exp)
+
+
+def test_background_removal_repeats_on_one_workspace(ctx):
+    import torch
+    v = noisy_volume((20, 40, 50), np.uint16, 12, 3)
+    g = vr.make_grid(50, 40, 20, vr.VR_U16, 12)
+    n = vr.vr_denoise_workspace_bytes(g)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    src = to_dev(v)
+    w = vr.gaussian_weights(2.0, 14)
+    lp = vr.make_lowpass(w, w, w, 14)
+    outs = []
+    for _ in range(3):
+        dst = torch.empty_like(src)
+        vr.vr_remove_background(ctx.ptr, g, lp, src, dst, None, ws, n)
+        outs.append(dst)
+    torch.cuda.synchronize()
+    exp, _ = dn.remove_background(v, w, w, w, 14)
+    for o in outs:
+        assert np.array_equal(to_host(o, np.uint16), exp)
+
+
+MRF_SHAPES = [(1, 1, 1), (2, 2, 2), (1, 9, 40), (9, 33, 70), (40, 45, 130)]
+
+
+@pytest.mark.parametrize("dtype,bits", [(np.uint8, 8), (np.uint16, 12)])
+@pytest.mark.parametrize("shape", MRF_SHAPES)
+def test_mrf_bitwise(ctx, shape, dtype, bits):
+    log(f"mrf {shape} {dtype.__name__}-{bits}")
+    v = noisy_volume(shape, dtype, bits, 7 + sum(shape))
+    for max_iters in (0, 1, 3, 400):
+        out, info = vr.mrf_denoise(ctx, to_dev(v), bits, max_iters)
+        exp, n, sigma, delta = dn.mrf(v, bits, max_iters)
+        assert (info.iterations, info.delta) == (n, delta), (max_iters, info.iterations, n)
+        assert info.sigma == sigma
+        assert np.array_equal(to_host(out, dtype), exp)
+    log(f"  iterations {info.iterations} sigma {info.sigma:.3f} rms {info.rms:.3f}")
+
+
+def test_mrf_degenerate_volumes(ctx):
+    # constant (no step), linear ramp (no noise, stops at once), two values
+    c = np.full((5, 6, 7), 77, np.uint8)
+    out, info = vr.mrf_denoise(ctx, to_dev(c), 8, 50)
+    assert info.delta == 0 and info.iterations == 0 and np.array_equal(to_host(out, np.uint8), c)
+    r = np.zeros((5, 6, 7), np.uint16)
+    r[:] = (3 * np.arange(7))[None, None, :]
+    out, info = vr.mrf_denoise(ctx, to_dev(r), 12, 50)
+    assert info.sigma == 0.0 and info.iterations == 0
+    assert np.array_equal(to_host(out, np.uint16), r)
+    t = np.zeros((6, 6, 6), np.uint16)
+    t[::2] = 4000
+    out, info = vr.mrf_denoise(ctx, to_dev(t), 12, 20)
+    exp, n, _, delta = dn.mrf(t, 12, 20)
+    assert (info.iterations, info.delta) == (n, delta) == (n, 4000)
+    assert np.array_equal(to_host(out, np.uint16), exp)
+
+
+# --------------------------------------------------- full frame size
+
+FULL = (64, 1024, 1024)   # one channel of a 1024 x 1024 x 64 confocal frame
+
+
+@pytest.fixture(scope="module")
+def full_frame():
+    """The vessel channel (uint16, 12-bit) of a generated 2-channel frame."""
+    frame = synth.DeviceSeries((FULL[2], FULL[1], FULL[0]), 2, 12, 11).frame(0)
+    return np.ascontiguousarray(frame[1].cpu().numpy().view(np.uint16))
+
+
+def test_background_removal_full_frame_on_crops(ctx, full_frame):
+    import torch
+    v = full_frame
+    wx = wy = vr.gaussian_weights(16.0, 16)
+    wz = vr.gaussian_weights(4.0, 16)
+    out, b = vr.remove_background(ctx, to_dev(v), wx, wy, wz, 16, 12)
+    torch.cuda.synchronize()
+    out, b = to_host(out, np.uint16), to_host(b, np.uint16)
+    r = np.array([len(wz) // 2, len(wy) // 2, len(wx) // 2]) + 2
+    rng = np.random.default_rng(4)
+    pts = [np.array([0, 0, 0]), np.array(FULL) - 1, np.array([FULL[0] // 2, 0, FULL[2] - 1])]
+    pts += [rng.integers(0, FULL) for _ in range(5)]
+    for p in pts:
+        lo = np.maximum(p - r, 0)
+        hi = np.minimum(p + r + 1, FULL)
+        crop = v[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]]
+        e, eb = dn.remove_background(crop, wx, wy, wz, 16)
+        q = tuple(p - lo)
+        assert out[tuple(p)] == e[q] and b[tuple(p)] == eb[q], p
+        # the voxel's 3x3x3 neighbourhood inside the crop's exact region too
+        sl = tuple(slice(max(int(c) - 1, 0), int(c) + 2) for c in q)
+        gsl = tuple(slice(max(int(c) - 1, 0), int(c) + 2) for c in p)
+        assert np.array_equal(b[gsl], eb[sl])
+
+
+def test_mrf_full_frame_first_steps_and_properties(ctx, full_frame):
+    v = full_frame
+    sigma, _, _ = dn.noise_sigma(v)
+    delta = dn.min_gap(v)
+    I = v.astype(np.int64)
+    for k in (1, 2):
+        out, info = vr.mrf_denoise(ctx, to_dev(v), 12, k)
+        assert info.sigma == sigma and info.delta == delta
+        I = dn.mrf_step(I, delta, 4095)
+        if info.iterations == k:
+            assert np.array_equal(to_host(out, np.uint16).astype(np.int64), I)
+    out, info = vr.mrf_denoise(ctx, to_dev(v), 12, 500)
+    d = to_host(out, np.uint16).astype(np.int64) - v.astype(np.int64)
+    assert float((d ** 2).sum()) <= sigma * sigma * v.size
+    assert np.abs(d).max() <= info.iterations * delta
+    log(f"full mrf: iterations {info.iterations} sigma {info.sigma:.3f} rms {info.rms:.3f}")
