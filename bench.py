@@ -128,6 +128,28 @@ def cpu_baseline(scene, target_s=10.0):
             "sample_1thread": f"2 x 65536 seeded pixels, {dt1:.1f} s"}
 
 
+def denoise_cpu_baseline(crop=(256, 256, 64)):
+    """The denoising oracle (numpy, one thread) on a crop of the same frame:
+    bounded CPU work."""
+    import numpy as np
+
+    from oracle import denoise as dn
+    from paper_1407_2089_amd import workloads
+    vol, (wx, wy, wz) = workloads.denoise_setup()
+    cx, cy, cz = crop
+    v = vol[:cz, :cy, :cx].cpu().numpy().view(np.uint16).copy()
+    t0 = time.perf_counter()
+    dn.remove_background(v, wx, wy, wz, 16)
+    t_bg = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, iters, _, _ = dn.mrf(v, 12, 50)
+    t_mrf = time.perf_counter() - t0
+    return {"kind": "oracle", "cores": 1, "unit": "voxels/s",
+            "sample": f"{cx}x{cy}x{cz} crop of the frame, numpy int64, one thread",
+            "background_voxels_per_s": v.size / t_bg,
+            "mrf_voxel_steps_per_s": v.size * (iters + 1) / t_mrf, "mrf_iterations": iters}
+
+
 def tiny(args):
     """Launch-bound small case: 1-channel u8 64x64x32, ortho mono 256x256."""
     import numpy as np
@@ -173,11 +195,12 @@ def main():
     ap.add_argument("--mode", choices=["render", "copy"], default="render",
                     help="copy: a plain 1 GiB device copy, to calibrate HBM byte counters")
     ap.add_argument("--workload", choices=["realistic", "tiny", "batch", "serve", "precision",
-                                           "layout"],
+                                           "layout", "denoise"],
                     default="realistic",
                     help="realistic (default): one stereo 1920x1080 frame per step; batch: 64 "
                          "mixed requests, batched vs plain launches; serve: Poisson arrivals "
-                         "on resident datasets, p50/p99; precision: 48-frame series FP32/FP16")
+                         "on resident datasets, p50/p99; precision: 48-frame series FP32/FP16; "
+                         "denoise: background removal and MRF of a 1024x1024x64 channel")
     ap.add_argument("--brick", default="0,0,0", help="brick edge per axis (0,0,0 = default)")
     ap.add_argument("--tile", default="", help="wave_w,wave_h (pixels per wave) of vr_render")
     ap.add_argument("--layout", choices=["bricks", "pairs"], default="pairs",
@@ -228,6 +251,10 @@ def main():
             res = workloads.precision(ctx)
         elif args.workload == "layout":
             res = workloads.layout_sweep(ctx)
+        elif args.workload == "denoise":
+            res = workloads.denoise(ctx)
+            if not args.no_cpu:
+                res["cpu_baseline"] = denoise_cpu_baseline()
         else:
             rates = tuple(int(r) for r in args.serve_rates.split(","))
             res = workloads.serving(ctx, total_gb=args.serve_gb, seconds=args.serve_seconds,

@@ -42,7 +42,8 @@ typedef struct {
 } vr_lowpass;
 
 /* Device workspace bytes that the two calls below need for `grid`: two
- * volumes of the voxel type plus 64 KiB + 256 bytes of tables. */
+ * volumes of the voxel type (each rounded up to 256 bytes) plus
+ * 1 MiB + 64 KiB + 256 bytes of tables. */
 vr_status vr_denoise_workspace_bytes(const vr_grid* grid, uint64_t* bytes);
 
 /* Stem-cell channel, eq. (1): B = the low-pass of src, then

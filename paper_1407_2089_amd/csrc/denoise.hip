@@ -17,11 +17,18 @@ namespace {
 
 constexpr int kMaxTaps = 129;
 constexpr int kThreads = 256;
+// Each lane filters one line and produces kRun consecutive outputs along it:
+// kRun x kRun multiply-adds per kRun LDS reads.  Weights are padded with
+// zeros to a multiple of kRun.
+constexpr int kRun = 16;
+constexpr int kPadTaps = (kMaxTaps + kRun - 1) / kRun * kRun;   // 144
 
-// One axis of the low-pass, passed by value (kernel argument segment).
+// One axis of the low-pass, passed by value (kernel argument segment; the
+// weights are read with scalar loads).
 struct Axis1D {
-    uint32_t w[kMaxTaps];
-    int32_t taps;
+    uint32_t w[kPadTaps];
+    int32_t taps;      // odd, <= kMaxTaps
+    int32_t padded;    // taps rounded up to a multiple of kRun
     int32_t shift;
 };
 
@@ -30,72 +37,134 @@ struct Dims {
 };
 
 // ------------------------------------------------------------- low-pass
-// Pass along x: a block filters 256 consecutive voxels of one row from an LDS
-// copy of the row segment and its clamped halo.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void lowpass_x(const T* __restrict__ src,
-                                                      T* __restrict__ dst, Dims d, Axis1D k) {
-    __shared__ uint32_t tile[kThreads + kMaxTaps - 1];
-    __shared__ uint32_t w[kMaxTaps];
-    const int tid = threadIdx.x;
-    const int r = (k.taps - 1) >> 1;
-    const int tiles_x = (d.nx + kThreads - 1) / kThreads;
-    const int row = (int)blockIdx.x / tiles_x;
-    const int x0 = ((int)blockIdx.x - row * tiles_x) * kThreads;
-    const size_t base = (size_t)row * d.nx;
-    for (int i = tid; i < k.taps; i += kThreads) w[i] = k.w[i];
-    for (int i = tid; i < kThreads + 2 * r; i += kThreads) {
-        const int x = min(max(x0 - r + i, 0), d.nx - 1);
-        tile[i] = src[base + x];
-    }
-    __syncthreads();
-    const int x = x0 + tid;
-    if (x >= d.nx) return;
-    uint32_t acc = 1u << (k.shift - 1);
-    for (int j = 0; j < k.taps; ++j) acc += __umul24(w[j], tile[tid + j]);
-    dst[base + x] = (T)(acc >> k.shift);
+// A block filters 64 lines over 64 outputs each (4 waves x kRun outputs).
+// The lines' inputs, from 64 + 2r before clamping, sit in LDS as
+// tile[lane * pitch + row] (pitch odd: the 64 lanes of a read hit distinct
+// banks).  Rows past the loaded span are read only against zero weights.
+constexpr int kOut = (kThreads / 64) * kRun;                // 64 outputs per line
+// A wave's run reads rows wave * kRun .. wave * kRun + padded + kRun - 1
+// (the last chunk's final row against no weight at all).
+constexpr int kRows = kOut + kPadTaps;                      // 208 rows
+constexpr int kPitch = kRows | 1;                            // odd pitch, 209
+
+// acc += w * x with both factors below 2^24 (weights <= 2^16, voxels <= 2^16):
+// one full-rate v_mad_u32_u24 (left to itself the compiler pairs products
+// into v_add3_u32, three instructions per two multiply-adds).
+__device__ __forceinline__ void mad24(uint32_t& acc, uint32_t w, uint32_t x) {
+    asm("v_mad_u32_u24 %0, %1, %2, %0" : "+v"(acc) : "s"(w), "v"(x));
 }
 
-// Pass along y or z (stride sa between neighbours on the axis): a block
-// filters 64 outputs along the axis for 64 consecutive x, from an LDS copy of
-// the (64 + 2r) x 64 input patch (rows clamped at the axis ends).
-constexpr int kLine = 64;
-template <typename T>
-__global__ __launch_bounds__(kThreads) void lowpass_strided(const T* __restrict__ src,
-                                                            T* __restrict__ dst, Dims d, int na,
-                                                            int no, long long sa, long long so,
-                                                            Axis1D k) {
-    __shared__ uint32_t tile[(kLine + kMaxTaps - 1) * 64];
-    __shared__ uint32_t w[kMaxTaps];
+__device__ __forceinline__ void filter_run(const uint32_t* __restrict__ t, const Axis1D& k,
+                                           uint32_t (&acc)[kRun]) {
+    uint32_t a[kRun], b[kRun];
+#pragma unroll
+    for (int m = 0; m < kRun; ++m) {
+        acc[m] = 1u << (k.shift - 1);
+        a[m] = t[m];
+    }
+    for (int q0 = 0; q0 < k.padded; q0 += kRun) {
+#pragma unroll
+        for (int m = 0; m < kRun; ++m) b[m] = t[q0 + kRun + m];
+#pragma unroll
+        for (int dq = 0; dq < kRun; ++dq) {
+            const uint32_t w = k.w[q0 + dq];
+#pragma unroll
+            for (int m = 0; m < kRun; ++m) mad24(acc[m], w, m + dq < kRun ? a[m + dq] : b[m + dq - kRun]);
+        }
+#pragma unroll
+        for (int m = 0; m < kRun; ++m) a[m] = b[m];
+    }
+}
+
+// Generic line pass.  Line l of the block is (line0 + l); element i of a line
+// sits at base(line) + i * step.  For the x pass the lines are rows (step 1);
+// for y and z the lines are columns at consecutive x (step nx or nx ny).
+// line_base maps a line index to its first element; n_lines lines exist.
+template <typename T, int AXIS>
+__global__ __launch_bounds__(kThreads) void lowpass_pass(const T* __restrict__ src,
+                                                         T* __restrict__ dst, Dims d, Axis1D k) {
+    __shared__ uint32_t tile[64 * kPitch];
     const int tid = threadIdx.x;
     const int r = (k.taps - 1) >> 1;
-    const int tiles_x = (d.nx + 63) / 64;
-    const int tiles_a = (na + kLine - 1) / kLine;
+    // line geometry: length na along the axis, stride sa; lines indexed by
+    // (x, y, z) with the axis coordinate removed
+    const int na = AXIS == 0 ? d.nx : AXIS == 1 ? d.ny : d.nz;
+    const long long sa = AXIS == 0 ? 1 : AXIS == 1 ? (long long)d.nx : (long long)d.nx * d.ny;
+    const int tiles_a = (na + kOut - 1) / kOut;
     int b = (int)blockIdx.x;
-    const int tx = b % tiles_x;
-    b /= tiles_x;
     const int ta = b % tiles_a;
-    const int o = b / tiles_a;
-    if (o >= no) return;
-    const int x0 = tx * 64, a0 = ta * kLine;
-    for (int i = tid; i < k.taps; i += kThreads) w[i] = k.w[i];
-    const int rows = kLine + 2 * r;
-    for (int i = tid; i < rows * 64; i += kThreads) {
-        const int row = i >> 6, lane = i & 63;
-        const int a = min(max(a0 - r + row, 0), na - 1);
-        const int x = x0 + lane;
-        tile[i] = x < d.nx ? (uint32_t)src[(size_t)(o * so + a * sa) + x] : 0u;
+    b /= tiles_a;
+    const int a0 = ta * kOut;
+    // 64 lines per block: for x, 64 consecutive rows (y, z); for y and z,
+    // 64 consecutive x of one (z) or (y) plane line
+    int lines_valid;
+    long long base_of_line0, line_stride;
+    if (AXIS == 0) {
+        const int row0 = b * 64;
+        lines_valid = min(64, d.ny * d.nz - row0);
+        base_of_line0 = (long long)row0 * d.nx;
+        line_stride = d.nx;
+    } else {
+        const int tiles_x = (d.nx + 63) / 64;
+        const int x0 = (b % tiles_x) * 64;
+        const int o = b / tiles_x;     // z for the y pass, y for the z pass
+        lines_valid = min(64, d.nx - x0);
+        base_of_line0 = AXIS == 1 ? (long long)o * d.nx * d.ny + x0 : (long long)o * d.nx + x0;
+        line_stride = 1;
+    }
+    if (lines_valid <= 0) return;
+    // load rows a0 - r .. a0 + kOut + r - 1 (clamped) of every valid line
+    // (unrolled so that several loads are in flight per thread)
+    const int span = kOut + 2 * r;
+    if (AXIS == 0) {
+        // a wave loads every fourth line, its lanes consecutive x of it
+        const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll 4
+        for (int l = wave; l < 64; l += kThreads / 64) {
+            if (l >= lines_valid) break;
+            const long long lb = base_of_line0 + l * line_stride;
+#pragma unroll
+            for (int row = lane; row < kOut + 2 * (kMaxTaps / 2); row += 64) {
+                if (row >= span) break;
+                const int a = min(max(a0 - r + row, 0), na - 1);
+                tile[l * kPitch + row] = src[lb + a];
+            }
+        }
+    } else {
+        // coalesced across lines: consecutive threads take consecutive x
+#pragma unroll 8
+        for (int i = tid; i < 64 * span; i += kThreads) {
+            const int row = i >> 6, l = i & 63;
+            if (l >= lines_valid) continue;
+            const int a = min(max(a0 - r + row, 0), na - 1);
+            tile[l * kPitch + row] = src[base_of_line0 + l + a * sa];
+        }
     }
     __syncthreads();
-    const int lane = tid & 63, grp = tid >> 6;
-    const int x = x0 + lane;
-    if (x >= d.nx) return;
-    for (int j = grp; j < kLine; j += kThreads / 64) {
-        const int a = a0 + j;
-        if (a >= na) break;
-        uint32_t acc = 1u << (k.shift - 1);
-        for (int q = 0; q < k.taps; ++q) acc += __umul24(w[q], tile[(j + q) * 64 + lane]);
-        dst[(size_t)(o * so + a * sa) + x] = (T)(acc >> k.shift);
+    const int lane = tid & 63, wave = tid >> 6;
+    uint32_t acc[kRun];
+    filter_run(tile + lane * kPitch + wave * kRun, k, acc);
+    if (AXIS == 0) {
+        // The lanes hold rows: stage the results in LDS and store them row
+        // by row so that consecutive threads write consecutive x.
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kRun; ++m) tile[lane * kPitch + wave * kRun + m] = acc[m] >> k.shift;
+        __syncthreads();
+        for (int i = tid; i < 64 * kOut; i += kThreads) {
+            const int l = i / kOut, o = i - l * kOut;
+            const int a = a0 + o;
+            if (l < lines_valid && a < na)
+                dst[base_of_line0 + l * line_stride + a] = (T)tile[l * kPitch + o];
+        }
+        return;
+    }
+    if (lane >= lines_valid) return;
+    const long long lb = base_of_line0 + lane * line_stride;
+#pragma unroll
+    for (int m = 0; m < kRun; ++m) {
+        const int a = a0 + wave * kRun + m;
+        if (a < na) dst[lb + a * sa] = (T)(acc[m] >> k.shift);
     }
 }
 
@@ -211,6 +280,34 @@ __global__ void mark_values(const T* __restrict__ src, uint8_t* __restrict__ pre
     if (i < n) presence[src[i]] = 1;
 }
 
+// The reductions run on a grid of at most kReduceBlocks blocks that stride
+// over the volume, so that only that many atomic adds meet at one address.
+constexpr int kReduceBlocks = 2048;
+// The iteration writes one partial pair per block instead (no contention).
+constexpr int kStepBlocks = 8192;
+
+// Sum over the block of two unsigned 64-bit values into out[0], out[1]
+// (a plain store from thread 0).
+__device__ __forceinline__ void block_sum(unsigned long long a, unsigned long long b,
+                                          unsigned long long* out) {
+    __shared__ unsigned long long ta[kThreads], tb[kThreads];
+    const int tid = threadIdx.x;
+    ta[tid] = a;
+    tb[tid] = b;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            ta[tid] += ta[tid + s];
+            tb[tid] += tb[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out[0] = ta[0];
+        out[1] = tb[0];
+    }
+}
+
 // Sum over the block of two unsigned 64-bit values, then one atomic add each.
 __device__ __forceinline__ void block_add(unsigned long long a, unsigned long long b,
                                           unsigned long long* out) {
@@ -232,28 +329,23 @@ __device__ __forceinline__ void block_add(unsigned long long a, unsigned long lo
     }
 }
 
-__device__ __forceinline__ void coords(int i, const Dims& d, int& x, int& y, int& z) {
-    x = i % d.nx;
-    const int r = i / d.nx;
-    y = r % d.ny;
-    z = r / d.ny;
-}
-
-// Sum of |6-neighbour Laplacian| over interior voxels -> out[0].
+// Sum of |6-neighbour Laplacian| over interior voxels -> out[0].  Blocks
+// stride over rows (y, z); threads over x.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void laplacian_sum(const T* __restrict__ src, Dims d, int n,
+__global__ __launch_bounds__(kThreads) void laplacian_sum(const T* __restrict__ src, Dims d,
                                                           unsigned long long* out) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
     unsigned long long s = 0;
-    if (i < n) {
-        int x, y, z;
-        coords(i, d, x, y, z);
-        if (x > 0 && y > 0 && z > 0 && x < d.nx - 1 && y < d.ny - 1 && z < d.nz - 1) {
-            const long long sx = 1, sy = d.nx, sz = (long long)d.nx * d.ny;
-            const int lap = (int)src[i - sx] + (int)src[i + sx] + (int)src[i - sy] +
-                            (int)src[i + sy] + (int)src[i - sz] + (int)src[i + sz] -
-                            6 * (int)src[i];
-            s = (unsigned long long)(lap < 0 ? -lap : lap);
+    const long long sy = d.nx, sz = (long long)d.nx * d.ny;
+    const int rows = d.ny * d.nz;
+    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int y = r % d.ny, z = r / d.ny;
+        if (y == 0 || z == 0 || y == d.ny - 1 || z == d.nz - 1) continue;
+        const T* row = src + (size_t)r * d.nx;
+        for (int x = 1 + threadIdx.x; x < d.nx - 1; x += kThreads) {
+            const int lap = (int)row[x - 1] + (int)row[x + 1] + (int)row[x - sy] +
+                            (int)row[x + sy] + (int)row[x - sz] + (int)row[x + sz] -
+                            6 * (int)row[x];
+            s += (unsigned long long)(lap < 0 ? -lap : lap);
         }
     }
     block_add(s, 0, out);
@@ -262,34 +354,73 @@ __global__ __launch_bounds__(kThreads) void laplacian_sum(const T* __restrict__ 
 __device__ __forceinline__ int sgn(int v) { return (v > 0) - (v < 0); }
 
 // One iteration: out = clamp(cur + delta sgn(sum sgn(nb - cur)), 0, full);
-// out[0] += sum (out - orig)^2, out[1] += voxels that changed.
+// the block's sum of (out - orig)^2 and count of changed voxels go to
+// partial[2 b], partial[2 b + 1] (plain stores; reduce_partials adds them).
+// Blocks stride over rows (y, z); a thread takes kUnroll voxels of a row at
+// a time and loads all their neighbours first (clamped into the row's
+// planes, so every load is in bounds; a neighbour outside the volume is then
+// left out of the sum), so that those loads are in flight together.
+constexpr int kUnroll = 4;
 template <typename T>
 __global__ __launch_bounds__(kThreads) void mrf_step(const T* __restrict__ cur,
                                                      const T* __restrict__ orig,
-                                                     T* __restrict__ nxt, Dims d, int n,
-                                                     int delta, int full,
-                                                     unsigned long long* sums) {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
+                                                     T* __restrict__ nxt, Dims d, int delta,
+                                                     int full,
+                                                     unsigned long long* __restrict__ partial) {
     unsigned long long ss = 0, changed = 0;
-    if (i < n) {
-        int x, y, z;
-        coords(i, d, x, y, z);
-        const long long sy = d.nx, sz = (long long)d.nx * d.ny;
-        const int c = (int)cur[i];
-        int s = 0;
-        if (x > 0) s += sgn((int)cur[i - 1] - c);
-        if (x < d.nx - 1) s += sgn((int)cur[i + 1] - c);
-        if (y > 0) s += sgn((int)cur[i - sy] - c);
-        if (y < d.ny - 1) s += sgn((int)cur[i + sy] - c);
-        if (z > 0) s += sgn((int)cur[i - sz] - c);
-        if (z < d.nz - 1) s += sgn((int)cur[i + sz] - c);
-        const int v = min(max(c + delta * sgn(s), 0), full);
-        nxt[i] = (T)v;
-        const long long dv = (long long)v - (long long)orig[i];
-        ss = (unsigned long long)(dv * dv);
-        changed = v != c;
+    const int rows = d.ny * d.nz;
+    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int y = r % d.ny, z = r / d.ny;
+        const size_t base = (size_t)r * d.nx;
+        const T* c0 = cur + base;
+        const T* ym = c0 - (y > 0 ? d.nx : 0);
+        const T* yp = c0 + (y < d.ny - 1 ? d.nx : 0);
+        const size_t plane = (size_t)d.nx * d.ny;
+        const T* zm = c0 - (z > 0 ? plane : 0);
+        const T* zp = c0 + (z < d.nz - 1 ? plane : 0);
+        for (int x0 = 0; x0 < d.nx; x0 += kThreads * kUnroll) {
+            int c[kUnroll], l[kUnroll], rr[kUnroll], a[kUnroll], b[kUnroll], e[kUnroll],
+                f[kUnroll], o[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int x = min(x0 + u * kThreads + (int)threadIdx.x, d.nx - 1);
+                c[u] = c0[x];
+                l[u] = c0[max(x - 1, 0)];
+                rr[u] = c0[min(x + 1, d.nx - 1)];
+                a[u] = ym[x];
+                b[u] = yp[x];
+                e[u] = zm[x];
+                f[u] = zp[x];
+                o[u] = orig[base + x];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int x = x0 + u * kThreads + (int)threadIdx.x;
+                if (x >= d.nx) continue;
+                // a clamped neighbour equals the voxel itself: sgn(0) = 0
+                const int s = sgn(l[u] - c[u]) + sgn(rr[u] - c[u]) + sgn(a[u] - c[u]) +
+                              sgn(b[u] - c[u]) + sgn(e[u] - c[u]) + sgn(f[u] - c[u]);
+                const int v = min(max(c[u] + delta * sgn(s), 0), full);
+                nxt[base + x] = (T)v;
+                const long long dv = (long long)v - (long long)o[u];
+                ss += (unsigned long long)(dv * dv);
+                changed += v != c[u];
+            }
+        }
     }
-    block_add(ss, changed, sums);
+    block_sum(ss, changed, partial + 2 * blockIdx.x);
+}
+
+// sums[0..1] = the totals of n block partials (one block).
+__global__ __launch_bounds__(kThreads) void reduce_partials(
+    const unsigned long long* __restrict__ partial, int n, unsigned long long* sums) {
+    unsigned long long a = 0, b = 0;
+#pragma unroll 8
+    for (int i = threadIdx.x; i < n; i += kThreads) {
+        a += partial[2 * i];
+        b += partial[2 * i + 1];
+    }
+    block_sum(a, b, sums);
 }
 
 // --------------------------------------------------------------- host
@@ -317,7 +448,13 @@ uint64_t raw_bytes(const vr_grid& g) {
 
 uint64_t volume_bytes(const vr_grid& g) { return align256(raw_bytes(g)); }
 
-uint64_t workspace_need(const vr_grid& g) { return 2 * volume_bytes(g) + 256 + 65536; }
+// Workspace: two volumes, 256 bytes of sums, 64 KiB of value presence flags,
+// 1 MiB for per-block partial sums.
+constexpr uint64_t kPartialBytes = 1ull << 20;
+static_assert(16ull * kStepBlocks <= kPartialBytes, "partials fit their table");
+uint64_t workspace_need(const vr_grid& g) {
+    return 2 * volume_bytes(g) + 256 + 65536 + kPartialBytes;
+}
 
 vr_status check_ctx(const vr_ctx* ctx) {
     if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
@@ -336,6 +473,7 @@ vr_status check_axis(const uint32_t* w, int taps, int shift, const char* name, A
     std::memset(out, 0, sizeof *out);
     for (int i = 0; i < taps; ++i) out->w[i] = w[i];
     out->taps = taps;
+    out->padded = (taps + kRun - 1) / kRun * kRun;
     out->shift = shift;
     return VR_OK;
 }
@@ -347,21 +485,16 @@ hipError_t enqueue_background(const vr_grid& g, const Axis1D (&ax)[3], const T* 
     T* t1 = (T*)ws;
     T* t2 = (T*)(ws + volume_bytes(g));
     T* b = bg ? bg : t1;
-    const int tiles_x256 = (g.nx + kThreads - 1) / kThreads;
-    hipLaunchKernelGGL(lowpass_x<T>, dim3((unsigned)((long long)tiles_x256 * g.ny * g.nz)),
-                       dim3(kThreads), 0, s, src, t1, d, ax[0]);
-    const int tiles_x64 = (g.nx + 63) / 64;
-    const long long plane = (long long)g.nx * g.ny;
-    // y: axis stride nx, outer index z (stride nx ny)
-    const int ty = (g.ny + kLine - 1) / kLine;
-    hipLaunchKernelGGL(lowpass_strided<T>, dim3((unsigned)((long long)tiles_x64 * ty * g.nz)),
-                       dim3(kThreads), 0, s, (const T*)t1, t2, d, g.ny, g.nz, (long long)g.nx,
-                       plane, ax[1]);
-    // z: axis stride nx ny, outer index y (stride nx)
-    const int tz = (g.nz + kLine - 1) / kLine;
-    hipLaunchKernelGGL(lowpass_strided<T>, dim3((unsigned)((long long)tiles_x64 * tz * g.ny)),
-                       dim3(kThreads), 0, s, (const T*)t2, b, d, g.nz, g.ny, plane,
-                       (long long)g.nx, ax[2]);
+    const long long tx = (g.nx + 63) / 64;
+    const long long bx = (long long)((g.nx + kOut - 1) / kOut) * ((g.ny * g.nz + 63) / 64);
+    const long long by = (long long)((g.ny + kOut - 1) / kOut) * tx * g.nz;
+    const long long bz = (long long)((g.nz + kOut - 1) / kOut) * tx * g.ny;
+    hipLaunchKernelGGL((lowpass_pass<T, 0>), dim3((unsigned)bx), dim3(kThreads), 0, s, src, t1,
+                       d, ax[0]);
+    hipLaunchKernelGGL((lowpass_pass<T, 1>), dim3((unsigned)by), dim3(kThreads), 0, s,
+                       (const T*)t1, t2, d, ax[1]);
+    hipLaunchKernelGGL((lowpass_pass<T, 2>), dim3((unsigned)bz), dim3(kThreads), 0, s,
+                       (const T*)t2, b, d, ax[2]);
     const long long blocks = (long long)((g.nx + kMX - 1) / kMX) * ((g.ny + kMY - 1) / kMY) *
                              ((g.nz + kMZ - 1) / kMZ);
     hipLaunchKernelGGL(subtract_median<T>, dim3((unsigned)blocks), dim3(kThreads), 0, s, src,
@@ -378,12 +511,15 @@ vr_status run_mrf(const vr_grid& g, int max_iters, const T* src, T* dst, uint8_t
     T* spare = (T*)ws;
     unsigned long long* sums = (unsigned long long*)(ws + 2 * vb);
     uint8_t* presence = ws + 2 * vb + 256;
+    unsigned long long* partial = (unsigned long long*)(ws + 2 * vb + 256 + 65536);
+    const int sblocks = std::min(g.ny * g.nz, kStepBlocks);
     const int blocks = (n + kThreads - 1) / kThreads;
+    const int rblocks = std::min(g.ny * g.nz, kReduceBlocks);
     hipError_t e;
     hipLaunchKernelGGL(fill_u32, dim3(64), dim3(kThreads), 0, s, (uint32_t*)sums, 64, 0u);
     hipLaunchKernelGGL(fill_u32, dim3(64), dim3(kThreads), 0, s, (uint32_t*)presence, 16384, 0u);
     hipLaunchKernelGGL(mark_values<T>, dim3(blocks), dim3(kThreads), 0, s, src, presence, n);
-    hipLaunchKernelGGL(laplacian_sum<T>, dim3(blocks), dim3(kThreads), 0, s, src, d, n, sums);
+    hipLaunchKernelGGL(laplacian_sum<T>, dim3(rblocks), dim3(kThreads), 0, s, src, d, sums);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "denoise launch");
     std::vector<uint8_t> seen(65536);
     unsigned long long h[2] = {0, 0};
@@ -410,9 +546,10 @@ vr_status run_mrf(const vr_grid& g, int max_iters, const T* src, T* dst, uint8_t
     if (delta > 0) {
         while (kept < max_iters) {
             T* out = (kept % 2 == 0) ? dst : spare;
-            hipLaunchKernelGGL(fill_u32, dim3(1), dim3(64), 0, s, (uint32_t*)sums, 4, 0u);
-            hipLaunchKernelGGL(mrf_step<T>, dim3(blocks), dim3(kThreads), 0, s, cur, src, out,
-                               d, n, delta, full, sums);
+            hipLaunchKernelGGL(mrf_step<T>, dim3(sblocks), dim3(kThreads), 0, s, cur, src, out,
+                               d, delta, full, partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s,
+                               (const unsigned long long*)partial, sblocks, sums);
             if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "mrf step launch");
             if ((e = hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess ||
                 (e = hipStreamSynchronize(s)) != hipSuccess)

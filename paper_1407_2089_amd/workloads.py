@@ -1,4 +1,4 @@
-"""Workload runners for the batching, serving and precision measurements.
+"""Workload runners for the batching, serving, precision and denoising measurements.
 
 Each runner builds its seeded synthetic inputs on the GPU, drives libvr
 through the binding and returns a dict of measurements.  No rendering
@@ -12,8 +12,9 @@ import time
 import numpy as np
 
 from . import synth
-from . import (VR_FP16, VR_FP32, VR_U8, VR_U16, Volume, make_request, vr_poll, vr_release,
-               vr_render, vr_render_batch, vr_submit)
+from . import (VR_FP16, VR_FP32, VR_U8, VR_U16, Volume, gaussian_weights, make_grid,
+               make_lowpass, make_request, vr_denoise_workspace_bytes, vr_mrf_denoise, vr_poll,
+               vr_release, vr_remove_background, vr_render, vr_render_batch, vr_submit)
 
 SIZES_BATCH = [(960, 540), (1280, 720), (1600, 900), (1920, 1080)]
 SIZES_SERVE = [(960, 540), (1920, 1080), (2560, 1440), (3840, 2160)]
@@ -206,6 +207,75 @@ def precision(ctx, frames=48, seed=3, reps=2):
         res[name] = {"samples_per_s": total / dt, "stereo_fps": frames / dt,
                      "eff_GBps": total * 32 / dt / 1e9, "samples_per_series": total}
     vol.destroy()
+    return res
+
+
+# ------------------------------------------------------------------ denoise
+
+DENOISE_DIMS = (1024, 1024, 64)
+DENOISE_SIGMA = (16.0, 16.0, 4.0)
+
+
+def denoise_setup(seed=11):
+    """One 12-bit uint16 channel (the vessel channel of a generated
+    1024x1024x64 confocal-like frame) as a [Z][Y][X] device tensor, and the
+    quantised Gaussian weights (sigma 16, 16, 4 voxels; sums 2^16)."""
+    frame = synth.DeviceSeries(DENOISE_DIMS, 2, 12, seed).frame(0)
+    vol = frame[1].contiguous()
+    w = [gaussian_weights(s, 16) for s in DENOISE_SIGMA]
+    return vol, w
+
+
+def denoise(ctx, reps=10, max_iters=500):
+    """Background removal (eq. (1)) and the sign-diffusion iteration
+    (eqs. (2)-(3)) of one 1024x1024x64 uint16 channel resident in HBM."""
+    import torch
+    log("denoise: generating frame")
+    vol, (wx, wy, wz) = denoise_setup()
+    nx, ny, nz = DENOISE_DIMS
+    n = nx * ny * nz
+    grid = make_grid(nx, ny, nz, VR_U16, 12)
+    ws_bytes = vr_denoise_workspace_bytes(grid)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    dst, bg = torch.empty_like(vol), torch.empty_like(vol)
+    lp = make_lowpass(wx, wy, wz, 16)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        vr_remove_background(ctx.ptr, grid, lp, vol, dst, bg, ws, ws_bytes, stream)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        vr_remove_background(ctx.ptr, grid, lp, vol, dst, bg, ws, ws_bytes, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    bg_ms = float(np.median(times))
+    taps = [len(wx), len(wy), len(wz)]
+    res = {"workload": f"denoise: 1 channel u16-12 {nx}x{ny}x{nz} (vessel channel), "
+                       f"Gaussian background sigma {DENOISE_SIGMA} ({taps} taps), 3x3x3 median; "
+                       f"sign-diffusion MRF, max {max_iters} iterations",
+           "voxels": n,
+           "background": {"ms": bg_ms, "voxels_per_s": n / (bg_ms * 1e-3),
+                          # per voxel: three passes read + write 2 B each, the
+                          # median reads L and B and writes the result
+                          "alg_bytes": 18 * n, "eff_GBps": 18 * n / (bg_ms * 1e-3) / 1e9,
+                          "macs_per_voxel": sum(taps)}}
+    mrf_dst = torch.empty_like(vol)
+    vr_mrf_denoise(ctx.ptr, grid, 2, vol, mrf_dst, ws, ws_bytes, stream)  # warm-up
+    t0 = time.perf_counter()
+    info = vr_mrf_denoise(ctx.ptr, grid, max_iters, vol, mrf_dst, ws, ws_bytes, stream)
+    wall = time.perf_counter() - t0
+    steps = info.iterations + (1 if info.iterations < max_iters else 0)  # the rejected step too
+    res["mrf"] = {"iterations": info.iterations, "steps_run": steps, "sigma": info.sigma,
+                  "delta": info.delta, "rms": info.rms, "wall_ms": wall * 1e3,
+                  "ms_per_step": wall * 1e3 / max(steps, 1),
+                  "voxel_steps_per_s": n * steps / wall,
+                  # per voxel and step: read the current and the original
+                  # image, write the next one
+                  "alg_bytes_per_step": 6 * n}
+    del ws
     return res
 
 
