@@ -195,12 +195,13 @@ def main():
     ap.add_argument("--mode", choices=["render", "copy"], default="render",
                     help="copy: a plain 1 GiB device copy, to calibrate HBM byte counters")
     ap.add_argument("--workload", choices=["realistic", "tiny", "batch", "serve", "precision",
-                                           "layout", "denoise"],
+                                           "layout", "denoise", "stream"],
                     default="realistic",
                     help="realistic (default): one stereo 1920x1080 frame per step; batch: 64 "
                          "mixed requests, batched vs plain launches; serve: Poisson arrivals "
                          "on resident datasets, p50/p99; precision: 48-frame series FP32/FP16; "
-                         "denoise: background removal and MRF of a 1024x1024x64 channel")
+                         "denoise: background removal and MRF of a 1024x1024x64 channel; stream: "
+                         "playback of the 48-frame series from pinned host memory")
     ap.add_argument("--brick", default="0,0,0", help="brick edge per axis (0,0,0 = default)")
     ap.add_argument("--tile", default="", help="wave_w,wave_h (pixels per wave) of vr_render")
     ap.add_argument("--layout", choices=["bricks", "pairs"], default="pairs",
@@ -251,6 +252,8 @@ def main():
             res = workloads.precision(ctx)
         elif args.workload == "layout":
             res = workloads.layout_sweep(ctx)
+        elif args.workload == "stream":
+            res = workloads.streaming(ctx)
         elif args.workload == "denoise":
             res = workloads.denoise(ctx)
             if not args.no_cpu:

@@ -209,6 +209,35 @@ vr_status vr_create_volume(vr_ctx* ctx, const vr_volume_desc* desc, void* dev_st
 vr_status vr_upload_frame(vr_volume* vol, int32_t frame, const void* dev_src,
                           void* hip_stream);
 
+/* Playback of a series longer than device memory holds (Methods: the
+ * sequences were buffered in host memory): the volume's frames serve as a
+ * ring of slots and the series stays in host memory.  Enqueues the upload of
+ * one frame [channels][nz][ny][nx] from host_src into slot `slot`:
+ *   1. host_src -> dev_staging on copy_stream (an asynchronous DMA when
+ *      host_src is pinned, e.g. hipHostMalloc or a pinned torch tensor;
+ *      pageable memory works but the copy then blocks the caller);
+ *   2. relayout dev_staging -> the slot, as vr_upload_frame, on a stream of
+ *      the volume's own, after the copy and after the work already enqueued
+ *      on render_stream (renders that may still read the slot).
+ * With staging_bytes of two frames the calls alternate between the halves,
+ * so that each copy follows the previous one without waiting for its
+ * relayout; with one frame a copy waits for the previous relayout.
+ * Before rendering from the slot, call vr_stream_ready on the render stream.
+ * Playback with K slots: at step t, stream frame t + K - 1 into slot
+ * (t + K - 1) mod K, then vr_stream_ready(slot t mod K) and render frame t:
+ * the copy of the later frame overlaps the render of the earlier one.
+ * dev_staging (device, >= channels * nz * ny * nx * bytes per voxel) is reused
+ * safely by later calls on the same copy stream.  The two streams must
+ * differ.  The ordering covers work on render_stream only (not served
+ * tickets).  Calls on one volume serialise.  Returns after enqueueing. */
+vr_status vr_stream_frame(vr_volume* vol, int32_t slot, const void* host_src,
+                          void* dev_staging, uint64_t staging_bytes, void* copy_stream,
+                          void* render_stream);
+
+/* Make render_stream wait until the last vr_stream_frame into `slot` has
+ * landed (no wait if the slot was never streamed). */
+vr_status vr_stream_ready(vr_volume* vol, int32_t slot, void* render_stream);
+
 /* Unregister a volume and return its bytes to the budget.  VR_ERR_BUSY while
  * a served ticket that reads it is pending or running. */
 vr_status vr_destroy_volume(vr_volume* vol);

@@ -21,7 +21,7 @@ __all__ = [
     "vr_last_error", "vr_debug_sample", "Context", "Volume", "VR_U8", "VR_U16",
     "VR_FP32", "VR_FP16", "VR_ORTHO", "VR_PERSPECTIVE", "vr_denoise_workspace_bytes",
     "vr_remove_background", "vr_mrf_denoise", "gaussian_weights", "remove_background",
-    "mrf_denoise",
+    "mrf_denoise", "vr_stream_frame", "vr_stream_ready",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvr.so")
@@ -113,6 +113,8 @@ def lib():
             "vr_create_volume": [P, C.POINTER(vr_volume_desc), P, C.c_uint64,
                                  C.POINTER(C.c_void_p)],
             "vr_upload_frame": [P, C.c_int32, P, P],
+            "vr_stream_frame": [P, C.c_int32, P, P, C.c_uint64, P, P],
+            "vr_stream_ready": [P, C.c_int32, P],
             "vr_destroy_volume": [P],
             "vr_set_transfer": [P, C.c_int32, C.POINTER(vr_transfer)],
             "vr_render": [P, C.POINTER(vr_render_req), P],
@@ -321,6 +323,18 @@ def mrf_denoise(ctx, vol, bits, max_iters, stream=None):
     dst = torch.empty_like(vol)
     info = vr_mrf_denoise(ctx.ptr, grid, max_iters, vol, dst, ws, n, stream)
     return dst, info
+
+
+def vr_stream_frame(vol, slot: int, host_src, dev_staging, staging_bytes: int, copy_stream,
+                    render_stream):
+    """host_src: a (pinned) CPU tensor or an integer address."""
+    src = host_src if isinstance(host_src, int) else host_src.data_ptr()
+    _check(lib().vr_stream_frame(vol, slot, src, _ptr(dev_staging), staging_bytes,
+                                 _stream(copy_stream), _stream(render_stream)))
+
+
+def vr_stream_ready(vol, slot: int, render_stream):
+    _check(lib().vr_stream_ready(vol, slot, _stream(render_stream)))
 
 
 def vr_test_batch_tile(ctx, wave_w=0, wave_h=0):

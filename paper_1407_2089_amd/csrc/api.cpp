@@ -525,10 +525,99 @@ vr_status vr_upload_frame(vr_volume* vol, int32_t frame, const void* dev_src, vo
     return ok();
 }
 
+vr_status vr_stream_frame(vr_volume* vol, int32_t slot, const void* host_src,
+                          void* dev_staging, uint64_t staging_bytes, void* copy_stream,
+                          void* render_stream) {
+    if (!vol) return fail(VR_ERR_INVALID_ARG, "volume is NULL");
+    if (slot < 0 || slot >= vol->desc.frames)
+        return fail(VR_ERR_INVALID_ARG, "slot %d outside 0..%d", slot, vol->desc.frames - 1);
+    if (!host_src || !dev_staging) return fail(VR_ERR_INVALID_ARG, "source or staging is NULL");
+    const vr_volume_desc& d = vol->desc;
+    const uint64_t raw = (uint64_t)d.nx * d.ny * d.nz * d.channels * (d.dtype == VR_U16 ? 2 : 1);
+    if (staging_bytes < raw)
+        return fail(VR_ERR_INVALID_ARG, "staging of %llu bytes, %llu needed",
+                    (unsigned long long)staging_bytes, (unsigned long long)raw);
+    if (copy_stream == render_stream)
+        return fail(VR_ERR_INVALID_ARG, "copy and render streams must differ");
+    if (vol->ctx->device < 0) return fail(VR_ERR_UNSUPPORTED, "validation-only context");
+    DeviceGuard dg(vol->ctx->device);
+    std::lock_guard<std::mutex> lk(vol->stream_mu);
+    hipError_t e;
+    if (!vol->relayout_stream) {
+        if ((e = hipStreamCreateWithFlags(&vol->relayout_stream, hipStreamNonBlocking)) !=
+                hipSuccess ||
+            (e = hipEventCreateWithFlags(&vol->ev_before, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "stream set-up");
+        for (int h = 0; h < 2; ++h)
+            if ((e = hipEventCreateWithFlags(&vol->ev_copied[h], hipEventDisableTiming)) !=
+                    hipSuccess ||
+                (e = hipEventCreateWithFlags(&vol->ev_free[h], hipEventDisableTiming)) !=
+                    hipSuccess)
+                return hip_fail(e, "stream set-up");
+        vol->ev_loaded.assign((size_t)d.frames, nullptr);
+    }
+    if (!vol->ev_loaded[slot] &&
+        (e = hipEventCreateWithFlags(&vol->ev_loaded[slot], hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "stream event");
+    const hipStream_t cs = (hipStream_t)copy_stream, rs = (hipStream_t)render_stream;
+    const hipStream_t ls = vol->relayout_stream;
+    // Two frames of staging: alternate halves, so that a copy need not wait
+    // for the previous frame's relayout.
+    const int halves = staging_bytes >= 2 * raw ? 2 : 1;
+    const int h = halves == 2 ? vol->next_half : 0;
+    uint8_t* stage = (uint8_t*)dev_staging + (uint64_t)h * raw;
+    // the copy waits until the relayout that last read this half is done
+    if (vol->half_used[h] && (e = hipStreamWaitEvent(cs, vol->ev_free[h], 0)) != hipSuccess)
+        return hip_fail(e, "stream ordering");
+    if ((e = hipMemcpyAsync(stage, host_src, raw, hipMemcpyHostToDevice, cs)) != hipSuccess ||
+        (e = hipEventRecord(vol->ev_copied[h], cs)) != hipSuccess)
+        return hip_fail(e, "host to device copy");
+    // the relayout writes the slot: it waits for the copy and for the renders
+    // already enqueued (they may still read the slot)
+    if ((e = hipEventRecord(vol->ev_before, rs)) != hipSuccess ||
+        (e = hipStreamWaitEvent(ls, vol->ev_before, 0)) != hipSuccess ||
+        (e = hipStreamWaitEvent(ls, vol->ev_copied[h], 0)) != hipSuccess)
+        return hip_fail(e, "stream ordering");
+    e = launch_relayout(vol->geom, d.channels, d.dtype == VR_U16, d.bits, stage,
+                        vol->storage + (uint64_t)slot * vol->geom.frame_bytes, ls);
+    if (e != hipSuccess) return hip_fail(e, "relayout launch");
+    if ((e = hipEventRecord(vol->ev_free[h], ls)) != hipSuccess ||
+        (e = hipEventRecord(vol->ev_loaded[slot], ls)) != hipSuccess)
+        return hip_fail(e, "stream ordering");
+    vol->half_used[h] = true;
+    vol->next_half = halves == 2 ? 1 - h : 0;
+    return ok();
+}
+
+vr_status vr_stream_ready(vr_volume* vol, int32_t slot, void* render_stream) {
+    if (!vol) return fail(VR_ERR_INVALID_ARG, "volume is NULL");
+    if (slot < 0 || slot >= vol->desc.frames)
+        return fail(VR_ERR_INVALID_ARG, "slot %d outside 0..%d", slot, vol->desc.frames - 1);
+    if (vol->ctx->device < 0) return fail(VR_ERR_UNSUPPORTED, "validation-only context");
+    DeviceGuard dg(vol->ctx->device);
+    std::lock_guard<std::mutex> lk(vol->stream_mu);
+    if (vol->ev_loaded.empty() || !vol->ev_loaded[slot]) return ok();  // never streamed
+    const hipError_t e = hipStreamWaitEvent((hipStream_t)render_stream, vol->ev_loaded[slot], 0);
+    if (e != hipSuccess) return hip_fail(e, "stream ordering");
+    return ok();
+}
+
 vr_status vr_destroy_volume(vr_volume* vol) {
     if (!vol) return fail(VR_ERR_INVALID_ARG, "volume is NULL");
     if (vol->in_flight.load() != 0)
         return fail(VR_ERR_BUSY, "%d served tickets still read this volume", vol->in_flight.load());
+    if (vol->relayout_stream) {
+        DeviceGuard dg(vol->ctx->device);
+        (void)hipStreamSynchronize(vol->relayout_stream);
+        (void)hipEventDestroy(vol->ev_before);
+        for (int h = 0; h < 2; ++h) {
+            (void)hipEventDestroy(vol->ev_copied[h]);
+            (void)hipEventDestroy(vol->ev_free[h]);
+        }
+        for (hipEvent_t ev : vol->ev_loaded)
+            if (ev) (void)hipEventDestroy(ev);
+        (void)hipStreamDestroy(vol->relayout_stream);
+    }
     vr_ctx* ctx = vol->ctx;
     ctx->used.fetch_sub(vol->bytes);
     ctx->volumes.fetch_sub(1);

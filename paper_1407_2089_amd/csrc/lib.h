@@ -71,6 +71,17 @@ struct vr_volume {
     std::mutex tf_mu;
     vr_transfer tf[vr::kMaxChannels]{};
     std::atomic<int> in_flight{0};  // served tickets that read this volume
+    // vr_stream_frame / vr_stream_ready: the render stream's work before an
+    // upload, and per slot the end of its last upload (events are re-recorded;
+    // a wait takes the record that precedes it).
+    std::mutex stream_mu;
+    hipStream_t relayout_stream = nullptr;  // created by the first upload
+    hipEvent_t ev_before = nullptr;
+    hipEvent_t ev_copied[2] = {nullptr, nullptr};  // per staging half: copy landed
+    hipEvent_t ev_free[2] = {nullptr, nullptr};    // per staging half: relayout read it
+    bool half_used[2] = {false, false};
+    int next_half = 0;
+    std::vector<hipEvent_t> ev_loaded;   // per slot, created by its first upload
 };
 
 struct vr_ctx {

@@ -14,7 +14,8 @@ import numpy as np
 from . import synth
 from . import (VR_FP16, VR_FP32, VR_U8, VR_U16, Volume, gaussian_weights, make_grid,
                make_lowpass, make_request, vr_denoise_workspace_bytes, vr_mrf_denoise, vr_poll,
-               vr_release, vr_remove_background, vr_render, vr_render_batch, vr_submit)
+               vr_release, vr_remove_background, vr_render, vr_render_batch, vr_stream_frame,
+               vr_stream_ready, vr_submit)
 
 SIZES_BATCH = [(960, 540), (1280, 720), (1600, 900), (1920, 1080)]
 SIZES_SERVE = [(960, 540), (1920, 1080), (2560, 1440), (3840, 2160)]
@@ -208,6 +209,84 @@ def precision(ctx, frames=48, seed=3, reps=2):
                      "eff_GBps": total * 32 / dt / 1e9, "samples_per_series": total}
     vol.destroy()
     return res
+
+
+# ---------------------------------------------------------------- streaming
+
+PCIE_GBS = 64.0   # PCIe 5.0 x16, one direction (published link rate)
+
+
+def streaming(ctx, frames=48, slots=3, seed=3, reps=2):
+    """Playback of the precision series (4-channel uint8 1024x1024x48, 48
+    frames = 9.66 GB) kept in pinned host memory, through a ring of `slots`
+    device frames: each step streams a later frame in while the current one
+    renders (stereo 1920x1080)."""
+    import torch
+    log("streaming: generating series into pinned host memory")
+    dims, ser, tfs, cams = precision_setup(ctx, frames, seed)
+    first = ser.frame(0)
+    host = torch.empty((frames,) + tuple(first.shape), dtype=first.dtype, pin_memory=True)
+    for t in range(frames):
+        host[t].copy_(ser.frame(t) if t else first)
+    frame_bytes = host[0].numel() * host.element_size()
+    vol = Volume(ctx, dims, 4, slots, VR_U8, 8)
+    for c, tf in enumerate(tfs):
+        vol.set_transfer(c, tf)
+    staging = torch.empty(2 * frame_bytes, dtype=torch.uint8, device="cuda")  # two halves
+    copy = torch.cuda.Stream()
+    stream = torch.cuda.current_stream()
+    W, H = 1920, 1080
+    out = torch.empty((2, H, W, 4), dtype=torch.float32, device="cuda")
+
+    def play():
+        for t in range(min(slots - 1, frames)):
+            vr_stream_frame(vol.ptr, t, host[t], staging, 2 * frame_bytes, copy, stream)
+        for t in range(frames):
+            nxt = t + slots - 1
+            if nxt < frames:
+                vr_stream_frame(vol.ptr, nxt % slots, host[nxt], staging, 2 * frame_bytes,
+                                copy, stream)
+            vr_stream_ready(vol.ptr, t % slots, stream)
+            vr_render(ctx.ptr, make_request(vol.ptr, t % slots, cams[t], W, H, True, 1.0,
+                                            0.99, out), stream)
+        torch.cuda.synchronize()
+
+    play()
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        play()
+        times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    # the copy alone: pinned host -> device, one frame at a time
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(copy):
+        a.record(copy)
+        for t in range(8):
+            staging[:frame_bytes].copy_(host[t].view(torch.uint8).reshape(-1),
+                                        non_blocking=True)
+        b.record(copy)
+    torch.cuda.synchronize()
+    copy_gbs = 8 * frame_bytes / (a.elapsed_time(b) * 1e-3) / 1e9
+    # the renders alone (frames already resident in the slots)
+    a.record(stream)
+    for t in range(frames):
+        vr_render(ctx.ptr, make_request(vol.ptr, t % slots, cams[t], W, H, True, 1.0, 0.99,
+                                        out), stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    render_ms = a.elapsed_time(b) / frames
+    vol.destroy()
+    fps = frames / dt
+    return {"workload": f"streaming: 4ch u8 1024x1024x48, {frames} frames in pinned host memory "
+                        f"({frames * frame_bytes / 1e9:.2f} GB), {slots} device slots, stereo "
+                        "1920x1080 per frame",
+            "frame_bytes": frame_bytes, "stereo_fps": fps, "ms_per_frame": 1e3 / fps,
+            "h2d_GBps": fps * frame_bytes / 1e9, "copy_only_GBps": copy_gbs,
+            "render_only_ms": render_ms,
+            "roofline": {"bound": "pcie", "achieved": fps * frame_bytes / 1e9,
+                         "peak": PCIE_GBS, "unit": "GB/s",
+                         "frac": fps * frame_bytes / 1e9 / PCIE_GBS}}
 
 
 # ------------------------------------------------------------------ denoise

@@ -25,7 +25,8 @@ def declared_symbols(header="vr.h"):
 def test_library_exports_every_declared_symbol():
     L = vr.lib()
     names = declared_symbols()
-    assert "vr_render" in names and "vr_submit" in names and len(names) == 14
+    assert "vr_render" in names and "vr_submit" in names and len(names) == 16
+    assert "vr_stream_frame" in names and "vr_stream_ready" in names
     dn = declared_symbols("vr_denoise.h")
     assert dn == ["vr_denoise_workspace_bytes", "vr_mrf_denoise", "vr_remove_background"]
     for n in names + declared_symbols("vr_test.h") + dn:
@@ -406,3 +407,18 @@ def test_mrf_validation(vctx):
     expect(vr.VR_ERR_INVALID_ARG, vr.vr_mrf_denoise, vctx, g, 10, BASE, BASE + 8192,
            BASE + 65536, n - 1)
     expect(vr.VR_ERR_INVALID_ARG, vr.vr_mrf_denoise, vctx, g, 10, BASE, None, BASE + 65536, n)
+
+
+def test_stream_frame_validation(vvol):
+    ctx, v = vvol
+    raw = 64 * 48 * 20 * 2 * 2   # desc(): 64 x 48 x 20, 2 channels, uint16
+    host = C.create_string_buffer(16)
+    hp = C.addressof(host)
+    expect(vr.VR_ERR_UNSUPPORTED, vr.vr_stream_frame, v, 1, hp, BASE, raw, 1, 2)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_stream_frame, v, 2, hp, BASE, raw, 1, 2)   # slot
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_stream_frame, v, -1, hp, BASE, raw, 1, 2)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_stream_frame, v, 0, hp, BASE, raw - 1, 1, 2)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_stream_frame, v, 0, hp, None, raw, 1, 2)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_stream_frame, v, 0, hp, BASE, raw, 3, 3)   # same stream
+    expect(vr.VR_ERR_UNSUPPORTED, vr.vr_stream_ready, v, 1, 2)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_stream_ready, v, 5, 2)
