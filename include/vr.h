@@ -74,15 +74,18 @@ typedef struct {
     float origin[3];    /* world position of voxel (0, 0, 0)                 */
     int32_t brick[3];   /* brick edge per axis, each 4, 8, 16 or 32; all 0
                            selects the library default for the voxel word
-                           (all channels of a voxel, 1, 2, 4 or 8 bytes):
-                           16 x 16 x 8 for 1-byte, 8 x 16 x 8 for 2- and
-                           4-byte, 8 x 8 x 8 for 8-byte words.  Fixed at
+                           (all channels of a voxel, 1, 2, 4, 8 or 16
+                           bytes: channels rounded up to 1, 2, 4 or 8, times
+                           the voxel width): 16 x 16 x 8 for 1-byte,
+                           8 x 16 x 8 for 2- and 4-byte, 8 x 8 x 8 for 8-
+                           and 16-byte words.  Fixed at
                            creation.  With row_pairs the defaults are
                            16 x 16 x 16, 8 x 32 x 8 and 4 x 16 x 16 for 1-, 2-
                            and 4-byte words.                                  */
     int32_t row_pairs;  /* 0: default layout.  1: store each brick row next to
                            the row after it (voxel words of 1, 2 or 4 bytes:
-                           not 3 or 4 channels of uint16), so the four taps of
+                           up to 4 channels of uint8 or 2 of uint16), so the
+                           four taps of
                            a sample in one brick plane are consecutive words:
                            a sample takes two 16-byte loads instead of four
                            8-byte ones (4-byte words), two 8-byte loads instead

@@ -30,8 +30,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#define ORC_MAX_CHANNELS 8
+
 typedef struct {
-    int32_t nx, ny, nz, channels;
+    int32_t nx, ny, nz, channels; /* channels 1 .. ORC_MAX_CHANNELS */
     int32_t bytes_per_voxel; /* 1 = uint8, 2 = uint16                         */
     int32_t bits;            /* full scale is 2^bits - 1 (8, 12 or 16)       */
     double spacing[3];       /* world units per voxel along x, y, z           */
@@ -140,7 +142,8 @@ int orc_sample_points(const orc_volume* v, const double* pts, int64_t n, double*
  * that the viewer's lighting takes the gradient from.  g is [channels][3]. */
 int orc_gradient(const orc_volume* v, const double p[3], double* g)
 {
-    double hi[4], lo[4];
+    if (v->channels < 1 || v->channels > ORC_MAX_CHANNELS) return -1;
+    double hi[ORC_MAX_CHANNELS], lo[ORC_MAX_CHANNELS];
     for (int a = 0; a < 3; ++a) {
         double q[3] = {p[0], p[1], p[2]};
         q[a] = p[a] + 1.0;
@@ -189,7 +192,9 @@ static void tap_range(const orc_volume* v, int c, const double p[3], double* mn,
 int orc_shade(const orc_volume* v, const orc_view* view, const double p[3], double* shade,
               double* margin)
 {
-    double g[12], l[3] = {view->light_dir[0], view->light_dir[1], view->light_dir[2]};
+    if (v->channels < 1 || v->channels > ORC_MAX_CHANNELS) return -1;
+    double g[3 * ORC_MAX_CHANNELS];
+    double l[3] = {view->light_dir[0], view->light_dir[1], view->light_dir[2]};
     double ln = sqrt(l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
     for (int a = 0; a < 3; ++a) l[a] /= ln;
     orc_gradient(v, p, g);
@@ -418,7 +423,8 @@ static void render_pixel(const job_t* jb, int64_t slot)
         int prev_in = fabs(A - tau) <= eps;
         if (prev_in) band_add(blo, bhi, bk, out, 0);
 
-        double field[4], shade[4], smargin[4], lit_err;
+        double field[ORC_MAX_CHANNELS], shade[ORC_MAX_CHANNELS], smargin[ORC_MAX_CHANNELS];
+        double lit_err;
         for (int k = 0;; ++k) {
             double t = t_enter + (k + 0.5) * view->step;
             if (!(t < t_exit)) break;
@@ -487,6 +493,7 @@ int orc_render(const orc_volume* vol, const orc_transfer* tf, const orc_camera* 
         || !band_lo || !band_hi || !band_k || !lit_margin)
         return -1;
     if (view->width <= 0 || view->height <= 0 || !(view->step > 0.0)) return -1;
+    if (vol->channels < 1 || vol->channels > ORC_MAX_CHANNELS) return -1;
     if (view->lit && !(view->light_dir[0] != 0.0 || view->light_dir[1] != 0.0
                        || view->light_dir[2] != 0.0))
         return -1;

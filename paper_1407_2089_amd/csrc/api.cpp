@@ -66,7 +66,7 @@ static void brick_edges(const vr_volume_desc& d, int b[3]) {
         return;
     }
     b[0] = w == 1 ? 16 : 8;
-    b[1] = w == 8 ? 8 : 16;
+    b[1] = w >= 8 ? 8 : 16;
     b[2] = 8;
 }
 
@@ -97,7 +97,7 @@ vr_status check_desc(const vr_volume_desc* d) {
         return fail(VR_ERR_INVALID_ARG, "dimensions %d x %d x %d outside 1..8192", d->nx, d->ny,
                     d->nz);
     if (d->channels < 1 || d->channels > kMaxChannels)
-        return fail(VR_ERR_INVALID_ARG, "channels = %d outside 1..4", d->channels);
+        return fail(VR_ERR_INVALID_ARG, "channels = %d outside 1..%d", d->channels, kMaxChannels);
     if (d->frames < 1) return fail(VR_ERR_INVALID_ARG, "frames = %d < 1", d->frames);
     if (d->dtype == VR_U8) {
         if (d->bits != 8) return fail(VR_ERR_INVALID_ARG, "uint8 volumes need bits = 8");
@@ -115,7 +115,8 @@ vr_status check_desc(const vr_volume_desc* d) {
         return fail(VR_ERR_INVALID_ARG, "row_pairs = %d is neither 0 nor 1", d->row_pairs);
     if (d->row_pairs && word_bytes(d->channels, d->dtype == VR_U16) > 4)
         return fail(VR_ERR_INVALID_ARG,
-                    "row pairs need voxel words of at most 4 bytes (not 3 or 4 uint16 channels)");
+                    "row pairs need voxel words of at most 4 bytes (at most 4 uint8 or 2 uint16 "
+                    "channels)");
     const bool dflt = d->brick[0] == 0 && d->brick[1] == 0 && d->brick[2] == 0;
     if (!dflt)
         for (int a = 0; a < 3; ++a)
@@ -278,8 +279,7 @@ static Transparent make_transparent(const ReqParams& P, uint32_t full) {
         t.tmax[c] = (uint32_t)m;
     }
     if (any && !useful) t.ok = 0;
-    t.tmax2[0] = t.tmax[0] | t.tmax[1] << 16;
-    t.tmax2[1] = t.tmax[2] | t.tmax[3] << 16;
+    for (int q = 0; q < kMaxChannels / 2; ++q) t.tmax2[q] = t.tmax[2 * q] | t.tmax[2 * q + 1] << 16;
     auto lane = [&](int c) { return (std::min(t.tmax[c], 255u) << 8) | 255u; };
     t.byte_hi = lane(1) | lane(3) << 16;
     t.byte_lo = lane(0) | lane(2) << 16;

@@ -116,8 +116,9 @@ BatchSlot* batch_slot_for(vr_ctx* ctx, hipStream_t stream, vr_status* st) {
     return s;
 }
 
-static vr_status graph_for(BatchSlot* s, uint32_t mask, int blocks, hipGraphExec_t* out) {
-    const uint64_t key = (uint64_t)mask << 32 | (uint32_t)blocks;
+static vr_status graph_for(BatchSlot* s, uint64_t mask, int blocks, hipGraphExec_t* out) {
+    // variants present (48 bits) and the grid size (a power of two <= 2^17)
+    const uint64_t key = mask << 16 | (uint64_t)(31 - __builtin_clz((unsigned)blocks));
     auto it = s->graphs.find(key);
     if (it != s->graphs.end()) {
         *out = it->second.second;
@@ -300,7 +301,7 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
     }
     BatchWork* w = s->h_work;
     std::memset(w->group, 0, sizeof w->group);
-    uint32_t mask = 0;
+    uint64_t mask = 0;
     int64_t items = 0;
     for (int q = 0; q < n; ++q) {
         const ReqParams& P = params[order[q]];
@@ -315,7 +316,7 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
         if (items > (1 << 30)) return fail(VR_ERR_INVALID_ARG, "batch has too many tiles");
         g.n_req += 1;
         g.n_items = (int32_t)items;
-        if (items > 0) mask |= 1u << P.variant;
+        if (items > 0) mask |= 1ull << P.variant;
     }
     if (mask == 0) return VR_OK;
     w->tile = ts;

@@ -37,7 +37,7 @@ hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_ski
 // Launch the batch kernels of the variants set in `mask`, `blocks`
 // single-wave blocks each.
 hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
-                        const int32_t* dev_prefix, uint32_t mask, int blocks, hipStream_t s);
+                        const int32_t* dev_prefix, uint64_t mask, int blocks, hipStream_t s);
 hipError_t launch_debug_sample(const ReqParams& P, const float* pts, int n, float* out,
                                hipStream_t s);
 

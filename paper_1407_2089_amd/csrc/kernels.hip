@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* 
         const int i = (int)((bx << g.shift[0]) + lx) - 1;
         const int j = (int)((by << g.shift[1]) + ly) - 1;
         const int k = (int)((bz << g.shift[2]) + lz) - 1;
-        uint32_t ch[4] = {0u, 0u, 0u, 0u};
+        uint32_t ch[kMaxChannels] = {};
         if (i >= 0 && j >= 0 && k >= 0 && i < g.n[0] && j < g.n[1] && k < g.n[2]) {
             const size_t plane = (size_t)g.n[0] * g.n[1];
             const size_t vol = plane * g.n[2];
@@ -59,11 +59,15 @@ __global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* 
         if constexpr (!U16) {
             if constexpr (C == 1) word = (T)ch[0];
             else if constexpr (C == 2) word = (T)(ch[0] | (ch[1] << 8));
-            else word = (T)(ch[0] | (ch[1] << 8) | (ch[2] << 16) | (ch[3] << 24));
+            else if constexpr (C <= 4) word = (T)(ch[0] | (ch[1] << 8) | (ch[2] << 16) | (ch[3] << 24));
+            else word = make_uint2(ch[0] | (ch[1] << 8) | (ch[2] << 16) | (ch[3] << 24),
+                                   ch[4] | (ch[5] << 8));
         } else {
             if constexpr (C == 1) word = (T)ch[0];
             else if constexpr (C == 2) word = (T)(ch[0] | (ch[1] << 16));
-            else word = make_uint2(ch[0] | (ch[1] << 16), ch[2] | (ch[3] << 16));
+            else if constexpr (C <= 4) word = make_uint2(ch[0] | (ch[1] << 16), ch[2] | (ch[3] << 16));
+            else word = make_uint4(ch[0] | (ch[1] << 16), ch[2] | (ch[3] << 16),
+                                   ch[4] | (ch[5] << 16), 0u);
         }
         out[w] = word;
     }
@@ -186,8 +190,9 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
                            dst, maxval, words);                                          \
         return hipGetLastError();                                                        \
     }
-    VR_RL(1, false) VR_RL(2, false) VR_RL(3, false) VR_RL(4, false)
-    VR_RL(1, true) VR_RL(2, true) VR_RL(3, true) VR_RL(4, true)
+    VR_RL(1, false) VR_RL(2, false) VR_RL(3, false) VR_RL(4, false) VR_RL(5, false)
+    VR_RL(6, false) VR_RL(1, true) VR_RL(2, true) VR_RL(3, true) VR_RL(4, true)
+    VR_RL(5, true) VR_RL(6, true)
 #undef VR_RL
     return hipErrorInvalidValue;
 }
@@ -226,10 +231,10 @@ hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_ski
 }
 
 hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
-                        const int32_t* dev_prefix, uint32_t mask, int blocks, hipStream_t s) {
+                        const int32_t* dev_prefix, uint64_t mask, int blocks, hipStream_t s) {
     if (blocks <= 0) return hipErrorInvalidValue;
     for (int v = 0; v < kVariants; ++v) {
-        if (!(mask & (1u << v))) continue;
+        if (!(mask & (1ull << v))) continue;
         if (!kBatch[v]) return hipErrorInvalidValue;
         hipLaunchKernelGGL(kBatch[v], dim3(blocks), dim3(kWave), 0, s, dev_work, dev_reqs,
                            dev_prefix);

@@ -25,6 +25,18 @@ template <> struct WordT<1, true> { using T = uint16_t; };
 template <> struct WordT<2, true> { using T = uint32_t; };
 template <> struct WordT<3, true> { using T = uint2; };
 template <> struct WordT<4, true> { using T = uint2; };
+template <> struct WordT<5, false> { using T = uint2; };
+template <> struct WordT<6, false> { using T = uint2; };
+template <> struct WordT<5, true> { using T = uint4; };
+template <> struct WordT<6, true> { using T = uint4; };
+
+// 32-bit part q of a stored word (channels 4q .. 4q + 3 of uint8 words,
+// 2q .. 2q + 1 of uint16 words).
+template <typename T> __device__ __forceinline__ uint32_t part(T w, int q) {
+    if constexpr (sizeof(T) <= 4) return (uint32_t)w;
+    else if constexpr (sizeof(T) == 8) return q == 0 ? w.x : w.y;
+    else return q == 0 ? w.x : q == 1 ? w.y : q == 2 ? w.z : w.w;
+}
 
 // Raw channel values of one stored word, as float.
 template <int C, bool U16, typename T>
@@ -33,22 +45,15 @@ __device__ __forceinline__ void unpack_f32(T w, float (&x)[C]) {
         if constexpr (C == 1) {
             x[0] = (float)(uint32_t)w;
         } else {
-            uint32_t u = (uint32_t)w;
 #pragma unroll
-            for (int c = 0; c < C; ++c) x[c] = (float)((u >> (8 * c)) & 0xffu);
+            for (int c = 0; c < C; ++c) x[c] = (float)((part(w, c >> 2) >> (8 * (c & 3))) & 0xffu);
         }
     } else {
         if constexpr (C == 1) {
             x[0] = (float)(uint32_t)w;
-        } else if constexpr (C == 2) {
-            uint32_t u = (uint32_t)w;
-            x[0] = (float)(u & 0xffffu);
-            x[1] = (float)(u >> 16);
         } else {
-            x[0] = (float)(w.x & 0xffffu);
-            x[1] = (float)(w.x >> 16);
-            x[2] = (float)(w.y & 0xffffu);
-            if constexpr (C == 4) x[3] = (float)(w.y >> 16);
+#pragma unroll
+            for (int c = 0; c < C; ++c) x[c] = (float)((part(w, c >> 1) >> (16 * (c & 1))) & 0xffffu);
         }
     }
 }
@@ -82,18 +87,17 @@ __device__ __forceinline__ void unpack_f16(T w, half2_t (&h)[(C + 1) / 2]) {
         if constexpr (C == 1) {
             h[0] = half2_t{(_Float16)(uint16_t)w, (_Float16)0.0f};
         } else {
-            h[0] = bytes_to_half2((uint32_t)w, 0x04010400u);  // bytes 0, 1
-            if constexpr (C > 2) h[1] = bytes_to_half2((uint32_t)w, 0x04030402u);  // 2, 3
+#pragma unroll
+            for (int q = 0; q < (C + 1) / 2; ++q)  // bytes 0, 1 or 2, 3 of part q / 2
+                h[q] = bytes_to_half2(part(w, q >> 1), (q & 1) ? 0x04030402u : 0x04010400u);
         }
     } else {
         if constexpr (C == 1) {
             const uint16_t v = (uint16_t)w < kHalfMax ? (uint16_t)w : kHalfMax;
             h[0] = half2_t{(_Float16)v, (_Float16)0.0f};
-        } else if constexpr (C == 2) {
-            h[0] = u16x2_to_half2((uint32_t)w);
         } else {
-            h[0] = u16x2_to_half2(w.x);
-            h[1] = u16x2_to_half2(w.y);
+#pragma unroll
+            for (int q = 0; q < (C + 1) / 2; ++q) h[q] = u16x2_to_half2(part(w, q));
         }
     }
 }
@@ -124,6 +128,12 @@ template <> __device__ __forceinline__ uint2 load_word<uint2>(__amdgpu_buffer_rs
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     u32x2 w = __builtin_amdgcn_raw_buffer_load_b64(r, (int)v, (int)s, 0);
     return make_uint2(w.x, w.y);
+}
+template <> __device__ __forceinline__ uint4 load_word<uint4>(__amdgpu_buffer_rsrc_t r,
+                                                             uint32_t v, uint32_t s) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 w = __builtin_amdgcn_raw_buffer_load_b128(r, (int)v, (int)s, 0);
+    return make_uint4(w.x, w.y, w.z, w.w);
 }
 
 // Four consecutive words (the row-pair layout's taps of one plane, which
@@ -250,11 +260,14 @@ __device__ __forceinline__ half2_t lerp(half2_t a, half2_t b, half2_t f) {
     return f * (b - a) + a;
 }
 
-// Trilinear field (raw units) of every channel from landed taps.
-template <int C, bool U16, bool F16, typename T>
+// Trilinear field (raw units) of every channel from landed taps.  kLerp
+// keeps the lerp tree for any channel count: it returns a constant field
+// exactly (a + f (a - a) = a), which the weighted sum does not (its FP32
+// weights sum to 1 only up to rounding).
+template <int C, bool U16, bool F16, bool kLerp = false, typename T>
 __device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
     const float fx = t.fx, fy = t.fy, fz = t.fz;
-    if constexpr (!F16 && C >= 3) {
+    if constexpr (!F16 && C >= 3 && !kLerp) {
         // Many channels: the eight trilinear weights once, then one 8-term
         // weighted sum per channel.
         const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
@@ -329,11 +342,10 @@ __device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
 template <int C, bool U16, typename T>
 __device__ __forceinline__ u16x2_t pair16(T w, int q) {
     if constexpr (U16) {
-        if constexpr (C == 2) return __builtin_bit_cast(u16x2_t, (uint32_t)w);
-        else return __builtin_bit_cast(u16x2_t, q == 0 ? w.x : w.y);
+        return __builtin_bit_cast(u16x2_t, part(w, q));
     } else {
-        const uint32_t sel = q == 0 ? 0x0c010c00u : 0x0c030c02u;  // zero-extend 2 bytes
-        return __builtin_bit_cast(u16x2_t, __builtin_amdgcn_perm(0u, (uint32_t)w, sel));
+        const uint32_t sel = (q & 1) ? 0x0c030c02u : 0x0c010c00u;  // zero-extend 2 bytes
+        return __builtin_bit_cast(u16x2_t, __builtin_amdgcn_perm(0u, part(w, q >> 1), sel));
     }
 }
 
@@ -348,7 +360,7 @@ __device__ __forceinline__ bool transparent(const Taps<T>& t, const Transparent&
             max(max(max((uint32_t)t.w000, (uint32_t)t.w100), max((uint32_t)t.w010, (uint32_t)t.w110)),
                 max(max((uint32_t)t.w001, (uint32_t)t.w101), max((uint32_t)t.w011, (uint32_t)t.w111)));
         return m <= z.tmax[0];
-    } else if constexpr (!U16 && C >= 3) {
+    } else if constexpr (!U16 && (C == 3 || C == 4)) {
         // Four uint8 channels: the odd channels are the high bytes of the
         // word's 16-bit lanes, the even ones become so after a shift by 8 in
         // each lane; a lane max compared with (t << 8 | 255) tests the high
@@ -399,10 +411,10 @@ __device__ __forceinline__ void sample(const BrickGeom& g, const Sampler& S, flo
 }
 
 template <int V> struct Variant {
-    static constexpr int C = (V & 3) + 1;
-    static constexpr bool U16 = (V & 4) != 0;
-    static constexpr bool F16 = (V & 8) != 0;
-    static constexpr bool PAIRS = (V & 16) != 0;
+    static constexpr int C = variant_channels(V);
+    static constexpr bool U16 = variant_u16(V);
+    static constexpr bool F16 = variant_fp16(V);
+    static constexpr bool PAIRS = variant_pairs(V);
 };
 
 // One pixel of one eye: returns nothing, writes RGBA (and the sample count).
@@ -410,7 +422,9 @@ template <int V> struct Variant {
 // Lambert shade of every channel at stored-coordinate point q: the gradient
 // of each channel's trilinear field by central differences over one voxel per
 // axis (six FP32 samples, also under FP16 sampling: FP16 lerps would turn a
-// small gradient's direction), the normal against it, one directional light.
+// small gradient's direction; always the lerp tree, so that a flat
+// neighbourhood has exactly zero gradient and takes ambient + diffuse), the
+// normal against it, one directional light.
 template <int C, bool U16, bool PAIRS, typename Word>
 __device__ __forceinline__ void shade_at(const ReqParams& P, const Sampler& S, const float (&q)[3],
                                          float (&shade)[C]) {
@@ -418,12 +432,12 @@ __device__ __forceinline__ void shade_at(const ReqParams& P, const Sampler& S, c
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float hi[C], lo[C];
-        interpolate<C, U16, false>(fetch<Word, PAIRS>(P.g, S, a == 0 ? q[0] + 1.0f : q[0],
-                                                      a == 1 ? q[1] + 1.0f : q[1],
-                                                      a == 2 ? q[2] + 1.0f : q[2]), hi);
-        interpolate<C, U16, false>(fetch<Word, PAIRS>(P.g, S, a == 0 ? q[0] - 1.0f : q[0],
-                                                      a == 1 ? q[1] - 1.0f : q[1],
-                                                      a == 2 ? q[2] - 1.0f : q[2]), lo);
+        interpolate<C, U16, false, true>(fetch<Word, PAIRS>(P.g, S, a == 0 ? q[0] + 1.0f : q[0],
+                                                            a == 1 ? q[1] + 1.0f : q[1],
+                                                            a == 2 ? q[2] + 1.0f : q[2]), hi);
+        interpolate<C, U16, false, true>(fetch<Word, PAIRS>(P.g, S, a == 0 ? q[0] - 1.0f : q[0],
+                                                            a == 1 ? q[1] - 1.0f : q[1],
+                                                            a == 2 ? q[2] - 1.0f : q[2]), lo);
 #pragma unroll
         for (int c = 0; c < C; ++c) g[a][c] = (hi[c] - lo[c]) * P.light.gscale[a];
     }

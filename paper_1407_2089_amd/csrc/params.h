@@ -10,28 +10,32 @@
 
 namespace vr {
 
-constexpr int kMaxChannels = 4;
+constexpr int kMaxChannels = 6;   // the viewer's six channel colours
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kBlockThreads = 256;
 
-// Data variant of a request: channels (1..4), voxel width, sample precision
-// and storage layout.  Index = (channels - 1) + 4 u16 + 8 fp16 + 16 pairs.
-constexpr int kVariants = 32;
+// Data variant of a request: channels (1..6), voxel width, sample precision
+// and storage layout.  Index = (channels - 1) + 6 u16 + 12 fp16 + 24 pairs.
+constexpr int kVariants = 48;
 inline constexpr int variant_index(int channels, bool u16, bool fp16, bool pairs) {
-    return (channels - 1) + (u16 ? 4 : 0) + (fp16 ? 8 : 0) + (pairs ? 16 : 0);
+    return (channels - 1) + (u16 ? 6 : 0) + (fp16 ? 12 : 0) + (pairs ? 24 : 0);
 }
+inline constexpr int variant_channels(int v) { return v % 6 + 1; }
+inline constexpr bool variant_u16(int v) { return (v / 6) % 2 != 0; }
+inline constexpr bool variant_fp16(int v) { return (v / 12) % 2 != 0; }
+inline constexpr bool variant_pairs(int v) { return v >= 24; }
 
 // Bytes of one stored voxel word: all channels of a voxel side by side, the
-// channel count rounded up to 1, 2 or 4.
+// channel count rounded up to 1, 2, 4 or 8.
 inline constexpr int word_bytes(int channels, bool u16) {
-    return (channels == 1 ? 1 : channels == 2 ? 2 : 4) * (u16 ? 2 : 1);
+    return (channels == 1 ? 1 : channels == 2 ? 2 : channels <= 4 ? 4 : 8) * (u16 ? 2 : 1);
 }
 
 // The row-pair layout exists for 1-, 2- and 4-byte words: a plane's four
 // taps are then two aligned 2-byte loads, one 8-byte or one 16-byte load.
-// (For 8-byte words they already take two 16-byte loads without pairs.)
+// (8- and 16-byte words already take 16-byte loads without pairs.)
 inline constexpr bool variant_exists(int v) {
-    return !(v & 16) || word_bytes((v & 3) + 1, (v & 4) != 0) <= 4;
+    return !variant_pairs(v) || word_bytes(variant_channels(v), variant_u16(v)) <= 4;
 }
 
 // Brick-major layout of one frame.  Stored coordinates s = i + 1 run over
@@ -84,8 +88,8 @@ struct Light {
 // leaves the pixel bitwise unchanged.  ok = 0 when some channel can never be
 // shown transparent that way (then no sample is).
 struct Transparent {
-    uint32_t tmax2[2];   // (tmax[2q] | tmax[2q + 1] << 16), 16-bit lanes
-    uint32_t tmax[4];    // per channel, 0 .. 65535
+    uint32_t tmax2[3];   // (tmax[2q] | tmax[2q + 1] << 16), 16-bit lanes
+    uint32_t tmax[6];    // per channel, 0 .. 65535
     // 4 uint8 channels (c0 | c1 << 8 | c2 << 16 | c3 << 24) read as 16-bit
     // lanes: a lane (hi << 8 | lo) is at most (t << 8 | 255) exactly when its
     // high byte is at most t.  byte_hi tests c1, c3 on the words themselves,

@@ -314,9 +314,11 @@ class DeviceSeries:
                                     rng.uniform(0, nz, k)])
             self.tubes.append((catmull_rom(ctrl, per_unit=1.0), rng.uniform(1500, 3500) * self.scale))
         self.small = []
-        for c in (2, 3):
-            n = max(1, n_cells * (4 if c == 2 else 20) // 4)
-            rad = 2.0 if c == 2 else 1.0
+        # channels 2-5: nuclei (radius 2), puncta (1), large bodies (3), small
+        # puncta (1.5); drawn in this order so that fewer channels draw the
+        # same objects
+        for c, (per, rad) in zip((2, 3, 4, 5), ((4, 2.0), (20, 1.0), (1, 3.0), (10, 1.5))):
+            n = max(1, n_cells * per // 4)
             self.small.append([(np.array([rng.uniform(0, nx), rng.uniform(0, ny),
                                           rng.uniform(0, nz)]), rad,
                                 rng.uniform(1200, 3000) * self.scale) for _ in range(n)])

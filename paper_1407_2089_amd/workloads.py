@@ -19,7 +19,10 @@ from . import (VR_FP16, VR_FP32, VR_U8, VR_U16, Volume, gaussian_weights, make_g
 
 SIZES_BATCH = [(960, 540), (1280, 720), (1600, 900), (1920, 1080)]
 SIZES_SERVE = [(960, 540), (1920, 1080), (2560, 1440), (3840, 2160)]
-PALETTE = [(0.0, 1.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.4, 1.0), (1.0, 1.0, 0.0)]
+# six channel colours (the viewer offers six): green, red, blue, yellow,
+# cyan, magenta
+PALETTE = [(0.0, 1.0, 0.0), (1.0, 0.0, 0.0), (0.0, 0.4, 1.0), (1.0, 1.0, 0.0),
+           (0.0, 1.0, 1.0), (1.0, 0.0, 1.0)]
 
 
 def log(msg):
@@ -33,7 +36,7 @@ def default_tfs(channels):
 
 def pairs_allowed(channels, bits):
     """Row pairs exist for voxel words of at most 4 bytes."""
-    return channels <= 2 or bits <= 8
+    return channels <= 2 or (channels <= 4 and bits <= 8)
 
 
 def load_series(ctx, series, frames, tfs, stream=None, row_pairs=False):

@@ -39,16 +39,21 @@ def desc(nx=64, ny=48, nz=20, ch=2, frames=3, dtype=vr.VR_U16, bits=12, brick=(0
                              (C.c_float * 3)(0, 0, 0), (C.c_int32 * 3)(*brick), row_pairs)
 
 
+WORD = {1: 1, 2: 2, 3: 4, 4: 4, 5: 8, 6: 8}   # bytes per voxel word of uint8 channels
+
+
 @pytest.mark.parametrize("dims,ch,dtype,brick", [
     ((64, 48, 20), 2, vr.VR_U16, (16, 16, 16)),
     ((1, 1, 1), 1, vr.VR_U8, (4, 4, 4)),
     ((100, 37, 9), 3, vr.VR_U8, (8, 16, 4)),
     ((512, 512, 64), 4, vr.VR_U16, (32, 32, 8)),
+    ((40, 30, 20), 5, vr.VR_U8, (8, 8, 8)),
+    ((40, 30, 20), 6, vr.VR_U16, (4, 8, 16)),
 ])
 def test_storage_bytes_follow_brick_layout(dims, ch, dtype, brick):
     d = desc(*dims, ch=ch, frames=3, dtype=dtype, bits=8 if dtype == vr.VR_U8 else 16,
              brick=brick)
-    word = {1: 1, 2: 2, 3: 4, 4: 4}[ch] * (1 if dtype == vr.VR_U8 else 2)
+    word = WORD[ch] * (1 if dtype == vr.VR_U8 else 2)
     nb = [math.ceil((n + 1) / b) for n, b in zip(dims, brick)]
     per_brick = (brick[0] + 1) * (brick[1] + 1) * (brick[2] + 1)
     frame = nb[0] * nb[1] * nb[2] * per_brick * word
@@ -69,7 +74,7 @@ def test_storage_bytes_of_the_row_pair_layout(dims, ch, dtype, brick):
     """Row pairs: a brick plane holds By pairs of rows, 2 (Bx + 1) words each."""
     d = desc(*dims, ch=ch, frames=2, dtype=dtype, bits=8 if dtype == vr.VR_U8 else 16,
              brick=brick, row_pairs=1)
-    word = {1: 1, 2: 2, 3: 4, 4: 4}[ch] * (1 if dtype == vr.VR_U8 else 2)
+    word = WORD[ch] * (1 if dtype == vr.VR_U8 else 2)
     if brick == (0, 0, 0):
         brick = {1: (16, 16, 16), 2: (8, 32, 8), 4: (4, 16, 16)}[word]
     nb = [math.ceil((n + 1) / b) for n, b in zip(dims, brick)]
@@ -80,7 +85,8 @@ def test_storage_bytes_of_the_row_pair_layout(dims, ch, dtype, brick):
 
 
 @pytest.mark.parametrize("ch,dtype,bits,row_pairs", [
-    (2, vr.VR_U16, 12, 2), (4, vr.VR_U8, 8, -1), (3, vr.VR_U16, 16, 1), (4, vr.VR_U16, 12, 1)])
+    (2, vr.VR_U16, 12, 2), (4, vr.VR_U8, 8, -1), (3, vr.VR_U16, 16, 1), (4, vr.VR_U16, 12, 1),
+    (5, vr.VR_U8, 8, 1), (6, vr.VR_U16, 12, 1)])
 def test_row_pairs_need_words_of_at_most_4_bytes_and_a_flag(ch, dtype, bits, row_pairs):
     with pytest.raises(vr.VrError):
         vr.vr_volume_storage_bytes(desc(ch=ch, dtype=dtype, bits=bits, row_pairs=row_pairs))
@@ -89,14 +95,15 @@ def test_row_pairs_need_words_of_at_most_4_bytes_and_a_flag(ch, dtype, bits, row
 @pytest.mark.parametrize("ch,dtype,bits,brick", [
     (1, vr.VR_U8, 8, (16, 16, 8)), (2, vr.VR_U8, 8, (8, 16, 8)), (1, vr.VR_U16, 12, (8, 16, 8)),
     (2, vr.VR_U16, 12, (8, 16, 8)), (4, vr.VR_U8, 8, (8, 16, 8)), (3, vr.VR_U8, 8, (8, 16, 8)),
-    (3, vr.VR_U16, 16, (8, 8, 8)), (4, vr.VR_U16, 16, (8, 8, 8))])
+    (3, vr.VR_U16, 16, (8, 8, 8)), (4, vr.VR_U16, 16, (8, 8, 8)), (5, vr.VR_U8, 8, (8, 8, 8)),
+    (6, vr.VR_U8, 8, (8, 8, 8)), (5, vr.VR_U16, 12, (8, 8, 8)), (6, vr.VR_U16, 16, (8, 8, 8))])
 def test_default_brick_depends_on_word_size(ch, dtype, bits, brick):
     assert vr.vr_volume_storage_bytes(desc(ch=ch, dtype=dtype, bits=bits, brick=(0, 0, 0))) == \
         vr.vr_volume_storage_bytes(desc(ch=ch, dtype=dtype, bits=bits, brick=brick))
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nx", 0), ("nz", 9000), ("channels", 0), ("channels", 5), ("frames", 0), ("dtype", 3),
+    ("nx", 0), ("nz", 9000), ("channels", 0), ("channels", 7), ("frames", 0), ("dtype", 3),
     ("bits", 7),
 ])
 def test_invalid_descriptions(field, value):

@@ -35,13 +35,14 @@ def log(msg):
 
 
 def mixed_scenes(seed=21):
-    """Volumes of every channel count and voxel type, different shapes, three
-    of them in the row-pair layout."""
+    """Volumes of every channel count (1-6) and voxel type, different shapes,
+    three of them in the row-pair layout."""
     rng = np.random.default_rng(seed)
     out = []
     specs = [(1, np.uint8, 8, False), (2, np.uint16, 12, False), (3, np.uint8, 8, False),
              (4, np.uint16, 16, False), (2, np.uint8, 8, False), (1, np.uint16, 12, False),
-             (2, np.uint16, 12, True), (4, np.uint8, 8, True), (1, np.uint8, 8, True)]
+             (2, np.uint16, 12, True), (4, np.uint8, 8, True), (1, np.uint8, 8, True),
+             (6, np.uint8, 8, False), (5, np.uint16, 12, False)]
     for q, (ch, dt, bits, pairs) in enumerate(specs):
         dims = (int(rng.integers(20, 70)), int(rng.integers(20, 70)), int(rng.integers(8, 40)))
         vol = synth.cells_and_vessels(dims, ch, bits, seed + q, n_cells=6, n_tubes=2)

@@ -48,7 +48,8 @@ def assert_same_bits(a, b):
 
 
 CASES = [(1, np.uint8, 8), (2, np.uint8, 8), (3, np.uint8, 8), (4, np.uint8, 8),
-         (1, np.uint16, 12), (2, np.uint16, 12), (3, np.uint16, 16), (4, np.uint16, 16)]
+         (1, np.uint16, 12), (2, np.uint16, 12), (3, np.uint16, 16), (4, np.uint16, 16),
+         (5, np.uint8, 8), (6, np.uint8, 8), (5, np.uint16, 12), (6, np.uint16, 16)]
 
 
 @pytest.mark.parametrize("precision", [vr.VR_FP32, vr.VR_FP16])

@@ -60,7 +60,7 @@ VARIANTS = [(1, np.uint8, 8, False), (2, np.uint8, 8, False), (3, np.uint8, 8, F
             (4, np.uint8, 8, False), (1, np.uint16, 12, False), (2, np.uint16, 12, False),
             (3, np.uint16, 12, False), (4, np.uint16, 16, False), (1, np.uint8, 8, True),
             (2, np.uint8, 8, True), (4, np.uint8, 8, True), (1, np.uint16, 16, True),
-            (2, np.uint16, 12, True)]
+            (2, np.uint16, 12, True), (5, np.uint8, 8, False), (6, np.uint16, 12, False)]
 
 
 @pytest.mark.parametrize("precision", [vr.VR_FP32, vr.VR_FP16])
@@ -200,3 +200,23 @@ def test_lit_requests_in_batches_and_serving_equal_alone(ctx):
         assert torch.equal(o, ro) and torch.equal(s, rs)
     for v, _ in vols:
         v.destroy()
+
+
+@pytest.mark.parametrize("ch", [3, 4, 6])
+def test_lit_flat_plateaus_have_no_gradient(ctx, ch):
+    # A saturated cube per channel: inside it every gradient sample reads
+    # equal voxels, so the gradient is exactly zero and the shade is
+    # ambient + diffuse (the FP32 weighted-sum interpolation of many channels
+    # would leave rounding noise there, with a random normal).
+    nx, ny, nz = 30, 26, 20
+    rng = np.random.default_rng(ch)
+    vol = rng.integers(0, 30, size=(ch, nz, ny, nx)).astype(np.uint8)
+    for c in range(ch):
+        vol[c, 4 + c:16, 5:20, 6 + c:24] = 255
+    tfs = [TF(0.3, 0.9, 0.0, 0.3, tuple(float(x) for x in rng.uniform(0.2, 1.0, 3)))
+           for _ in range(ch)]
+    cam = synth.orbit_camera((nx, ny, nz), 40.0, 30.0, 40.0)
+    sc = Scene("plateau", vol, 8, tfs, cam, 64, 48, True, 0.7, 0.99)
+    sc.light = Light((0.3, -0.4, 0.9), 0.2, 0.8)
+    rgba, smp = gpu.render(ctx, sc)
+    gpu.compare(rgba, smp, orc.render_all(sc), TOL32)

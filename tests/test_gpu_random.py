@@ -35,7 +35,7 @@ def ctx():
 def random_case(seed):
     rng = np.random.default_rng(10_000 + seed)
     nx, ny, nz = (int(rng.integers(1, 41)) for _ in range(3))
-    ch = int(rng.integers(1, 5))
+    ch = int(rng.integers(1, 7))
     u16 = bool(rng.integers(0, 2))
     bits = int(rng.integers(9, 17)) if u16 else 8
     dtype = np.uint16 if u16 else np.uint8
@@ -51,7 +51,7 @@ def random_case(seed):
                 -((i - cx) ** 2 + (j - cy) ** 2 + (k - cz) ** 2) / (2 * s * s))
         vol[c] += rng.uniform(0, 0.08 * full, size=(nz, ny, nx))
     vol = np.clip(np.rint(vol), 0, full).astype(dtype)
-    word = {1: 1, 2: 2, 3: 4, 4: 4}[ch] * (2 if u16 else 1)
+    word = {1: 1, 2: 2, 3: 4, 4: 4, 5: 8, 6: 8}[ch] * (2 if u16 else 1)
     pairs = word <= 4 and bool(rng.integers(0, 2))
     brick = (0, 0, 0) if rng.integers(0, 3) == 0 else tuple(int(rng.choice(EDGES)) for _ in range(3))
     spacing = tuple(float(x) for x in rng.uniform(0.5, 2.0, 3))

@@ -73,7 +73,8 @@ SAMPLER_CASES = [(1, np.uint8, 8, False), (2, np.uint8, 8, False), (3, np.uint8,
                  (3, np.uint16, 12, False), (4, np.uint16, 16, False),
                  (3, np.uint8, 8, True), (4, np.uint8, 8, True), (2, np.uint16, 12, True),
                  (2, np.uint16, 16, True), (1, np.uint8, 8, True), (2, np.uint8, 8, True),
-                 (1, np.uint16, 16, True)]
+                 (1, np.uint16, 16, True), (5, np.uint8, 8, False), (6, np.uint8, 8, False),
+                 (5, np.uint16, 12, False), (6, np.uint16, 16, False)]
 
 
 @pytest.mark.parametrize("ch,dtype,bits,row_pairs", SAMPLER_CASES)
