@@ -411,6 +411,87 @@ __global__ __launch_bounds__(kThreads) void mrf_step(const T* __restrict__ cur,
     block_sum(ss, changed, partial + 2 * blockIdx.x);
 }
 
+// The same iteration for rows of a multiple of 4 voxels at 4-voxel-aligned
+// addresses: a lane takes 4 consecutive voxels with one 4-wide load per
+// neighbour row (and one voxel to each side), a quarter of the load
+// instructions of the one-voxel form (measured: 0.141 -> 0.129 ms per step
+// on 1024 x 1024 x 64; taking two rows per block iteration was slower).
+template <typename T> struct Quad4 {
+    typedef T V4 __attribute__((ext_vector_type(4)));
+    V4 c, a, b, e, f, o;
+    int left, right;
+};
+
+template <typename T>
+__device__ __forceinline__ Quad4<T> quad_load(const T* __restrict__ cur, const T* __restrict__ orig,
+                                             const Dims& d, int r, int x) {
+    typedef typename Quad4<T>::V4 V4;
+    const int y = r % d.ny, z = r / d.ny;
+    const size_t base = (size_t)r * d.nx, plane = (size_t)d.nx * d.ny;
+    const T* c0 = cur + base;
+    Quad4<T> q;
+    q.c = *reinterpret_cast<const V4*>(c0 + x);
+    q.a = *reinterpret_cast<const V4*>(c0 - (y > 0 ? d.nx : 0) + x);
+    q.b = *reinterpret_cast<const V4*>(c0 + (y < d.ny - 1 ? d.nx : 0) + x);
+    q.e = *reinterpret_cast<const V4*>(c0 - (z > 0 ? plane : 0) + x);
+    q.f = *reinterpret_cast<const V4*>(c0 + (z < d.nz - 1 ? plane : 0) + x);
+    q.o = *reinterpret_cast<const V4*>(orig + base + x);
+    // a neighbour outside the row (or volume) is the voxel itself: sgn(0) = 0
+    q.left = x > 0 ? (int)c0[x - 1] : (int)q.c.x;
+    q.right = x + 4 < d.nx ? (int)c0[x + 4] : (int)q.c.w;
+    return q;
+}
+
+template <typename T>
+__device__ __forceinline__ void quad_step(const Quad4<T>& q, T* __restrict__ out, int delta,
+                                          int full, unsigned long long& ss,
+                                          unsigned long long& changed) {
+    typedef typename Quad4<T>::V4 V4;
+    const int cc[4] = {(int)q.c.x, (int)q.c.y, (int)q.c.z, (int)q.c.w};
+    const int ll[4] = {q.left, (int)q.c.x, (int)q.c.y, (int)q.c.z};
+    const int rr[4] = {(int)q.c.y, (int)q.c.z, (int)q.c.w, q.right};
+    const int aa[4] = {(int)q.a.x, (int)q.a.y, (int)q.a.z, (int)q.a.w};
+    const int bb[4] = {(int)q.b.x, (int)q.b.y, (int)q.b.z, (int)q.b.w};
+    const int ee[4] = {(int)q.e.x, (int)q.e.y, (int)q.e.z, (int)q.e.w};
+    const int ff[4] = {(int)q.f.x, (int)q.f.y, (int)q.f.z, (int)q.f.w};
+    const int oo[4] = {(int)q.o.x, (int)q.o.y, (int)q.o.z, (int)q.o.w};
+    int v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int sum = sgn(ll[u] - cc[u]) + sgn(rr[u] - cc[u]) + sgn(aa[u] - cc[u]) +
+                        sgn(bb[u] - cc[u]) + sgn(ee[u] - cc[u]) + sgn(ff[u] - cc[u]);
+        v[u] = min(max(cc[u] + delta * sgn(sum), 0), full);
+        const long long dv = (long long)v[u] - (long long)oo[u];
+        ss += (unsigned long long)(dv * dv);
+        changed += v[u] != cc[u];
+    }
+    V4 w;
+    w.x = (T)v[0];
+    w.y = (T)v[1];
+    w.z = (T)v[2];
+    w.w = (T)v[3];
+    *reinterpret_cast<V4*>(out) = w;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void mrf_step_vec(const T* __restrict__ cur,
+                                                         const T* __restrict__ orig,
+                                                         T* __restrict__ nxt, Dims d, int delta,
+                                                         int full,
+                                                         unsigned long long* __restrict__ partial) {
+    unsigned long long ss = 0, changed = 0;
+    const int rows = d.ny * d.nz;
+    const int nq = d.nx >> 2;
+    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+        for (int qx = threadIdx.x; qx < nq; qx += kThreads) {
+            const int x = 4 * qx;
+            quad_step(quad_load(cur, orig, d, r, x), nxt + (size_t)r * d.nx + x, delta, full, ss,
+                      changed);
+        }
+    }
+    block_sum(ss, changed, partial + 2 * blockIdx.x);
+}
+
 // sums[0..1] = the totals of n block partials (one block).
 __global__ __launch_bounds__(kThreads) void reduce_partials(
     const unsigned long long* __restrict__ partial, int n, unsigned long long* sums) {
@@ -546,8 +627,13 @@ vr_status run_mrf(const vr_grid& g, int max_iters, const T* src, T* dst, uint8_t
     if (delta > 0) {
         while (kept < max_iters) {
             T* out = (kept % 2 == 0) ? dst : spare;
-            hipLaunchKernelGGL(mrf_step<T>, dim3(sblocks), dim3(kThreads), 0, s, cur, src, out,
-                               d, delta, full, partial);
+            const uintptr_t al = 4 * sizeof(T) - 1;
+            if (g.nx % 4 == 0 && !(((uintptr_t)cur | (uintptr_t)src | (uintptr_t)out) & al))
+                hipLaunchKernelGGL(mrf_step_vec<T>, dim3(sblocks), dim3(kThreads), 0, s, cur, src,
+                                   out, d, delta, full, partial);
+            else
+                hipLaunchKernelGGL(mrf_step<T>, dim3(sblocks), dim3(kThreads), 0, s, cur, src,
+                                   out, d, delta, full, partial);
             hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s,
                                (const unsigned long long*)partial, sblocks, sums);
             if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "mrf step launch");

@@ -99,7 +99,9 @@ def test_background_removal_repeats_on_one_workspace(ctx):
         assert np.array_equal(to_host(o, np.uint16), exp)
 
 
-MRF_SHAPES = [(1, 1, 1), (2, 2, 2), (1, 9, 40), (9, 33, 70), (40, 45, 130)]
+# rows of a multiple of 4 voxels take the 4-wide kernel (x = 40, 96, 4), the
+# others the one-voxel kernel
+MRF_SHAPES = [(1, 1, 1), (2, 2, 2), (1, 9, 40), (9, 33, 70), (40, 45, 130), (7, 13, 96), (3, 5, 4)]
 
 
 @pytest.mark.parametrize("dtype,bits", [(np.uint8, 8), (np.uint16, 12)])
