@@ -150,6 +150,39 @@ def denoise_cpu_baseline(crop=(256, 256, 64)):
             "mrf_voxel_steps_per_s": v.size * (iters + 1) / t_mrf, "mrf_iterations": iters}
 
 
+def montage_cpu_baseline(src, cam, tfs, W, H, target_s=10.0):
+    """The oracle on seeded single rays of the montage view, each rendered on
+    its ray's crop of the volume (the montage is too large to copy whole):
+    one thread, about target_s seconds of oracle time."""
+    import numpy as np
+
+    import oracle
+    from paper_1407_2089_amd import workloads
+    rng = np.random.default_rng(12345)
+    otf = [oracle.Transfer(t.lo, t.hi, t.curve, t.alpha_mul, t.rgb, t.visible) for t in tfs]
+    ocam = oracle.Camera(cam.projection, cam.center, cam.forward, cam.up, cam.fov_y,
+                         cam.ortho_height, cam.eye_separation, cam.convergence)
+    dims = (src.shape[3], src.shape[2], src.shape[1])
+    samples, rays, spent = 0, 0, 0.0
+    while spent < target_s:
+        pix = int(rng.integers(W * H))
+        eye = -1 if rng.integers(0, 2) == 0 else 1
+        box = workloads.ray_crop(cam, W, H, eye, pix % W, pix // W, dims)
+        if box is None:
+            continue
+        lo, hi = box
+        crop = src[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()
+        ov = oracle.Volume(crop, 8, (1.0, 1.0, 1.0), tuple(float(x) for x in lo))
+        t0 = time.perf_counter()
+        r = oracle.render(ov, otf, ocam, W, H, eye, 1.0, 0.99, pixels=[pix], nthreads=1)
+        spent += time.perf_counter() - t0
+        samples += int(r["samples"].sum())
+        rays += 1
+    return {"value": samples / spent, "unit": "ray-samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{rays} seeded rays of the stereo view that meet the volume, each on its "
+                      f"ray's crop, FP64, one thread, {spent:.1f} s"}
+
+
 def tiny(args):
     """Launch-bound small case: 1-channel u8 64x64x32, ortho mono 256x256."""
     import numpy as np
@@ -195,7 +228,7 @@ def main():
     ap.add_argument("--mode", choices=["render", "copy"], default="render",
                     help="copy: a plain 1 GiB device copy, to calibrate HBM byte counters")
     ap.add_argument("--workload", choices=["realistic", "tiny", "batch", "serve", "precision",
-                                           "layout", "denoise", "stream"],
+                                           "layout", "denoise", "stream", "montage"],
                     default="realistic",
                     help="realistic (default): one stereo 1920x1080 frame per step; batch: 64 "
                          "mixed requests, batched vs plain launches; serve: Poisson arrivals "
@@ -254,6 +287,8 @@ def main():
             res = workloads.layout_sweep(ctx)
         elif args.workload == "stream":
             res = workloads.streaming(ctx)
+        elif args.workload == "montage":
+            res = workloads.montage(ctx, cpu=None if args.no_cpu else montage_cpu_baseline)
         elif args.workload == "denoise":
             res = workloads.denoise(ctx)
             if not args.no_cpu:

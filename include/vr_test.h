@@ -36,6 +36,14 @@ vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h);
  * are the same either way.  on = 1 (the default) restores the skip. */
 vr_status vr_test_clear_skip(vr_ctx* ctx, int32_t on);
 
+/* on = 1 makes volumes created afterwards on this context use the
+ * large-volume addressing (64-bit byte offsets, FP64 ray set-up and sample
+ * positions) that volumes with an axis above 8192 voxels or a frame of 2^31
+ * stored words or 4 GiB and more always use, so that path can be compared
+ * with the oracle on small volumes; such volumes refuse row pairs.  on = 0
+ * (the default) restores the choice by size. */
+vr_status vr_test_large_addressing(vr_ctx* ctx, int32_t on);
+
 /* Transparent-sample threshold of one channel with floor lo and ceiling hi
  * on bits-bit data: the folded transfer-function constants the kernels use
  * (u = clamp(raw * scale + bias, 0, 1)) and the largest raw tap value tmax

@@ -133,6 +133,7 @@ def lib():
             "vr_test_plain_tile": [P, C.c_int32, C.c_int32],
             "vr_test_block_map": [C.c_int32, C.c_void_p],
             "vr_test_clear_skip": [P, C.c_int32],
+            "vr_test_large_addressing": [P, C.c_int32],
             "vr_test_transparent_max": [C.c_float, C.c_float, C.c_int32, C.POINTER(C.c_float),
                                         C.POINTER(C.c_float), C.POINTER(C.c_int32)],
         }
@@ -347,6 +348,10 @@ def vr_test_plain_tile(ctx, wave_w=0, wave_h=0):
 
 def vr_test_clear_skip(ctx, on: bool):
     _check(lib().vr_test_clear_skip(ctx, int(bool(on))))
+
+
+def vr_test_large_addressing(ctx, on: bool):
+    _check(lib().vr_test_large_addressing(ctx, int(bool(on))))
 
 
 def vr_test_transparent_max(lo: float, hi: float, bits: int):

@@ -91,11 +91,18 @@ BrickGeom make_geom(const vr_volume_desc& d) {
     return g;
 }
 
+bool needs_large(const vr_volume_desc& d, const BrickGeom& g) {
+    const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
+    return d.nx > kFloatAxis || d.ny > kFloatAxis || d.nz > kFloatAxis || words >= (1ull << 31) ||
+           g.frame_bytes >= (1ull << 32);
+}
+
 vr_status check_desc(const vr_volume_desc* d) {
     if (!d) return fail(VR_ERR_INVALID_ARG, "volume description is NULL");
-    if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > 8192 || d->ny > 8192 || d->nz > 8192)
-        return fail(VR_ERR_INVALID_ARG, "dimensions %d x %d x %d outside 1..8192", d->nx, d->ny,
-                    d->nz);
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1 || d->nx > kMaxAxis || d->ny > kMaxAxis ||
+        d->nz > kMaxAxis)
+        return fail(VR_ERR_INVALID_ARG, "dimensions %d x %d x %d outside 1..%d", d->nx, d->ny,
+                    d->nz, kMaxAxis);
     if (d->channels < 1 || d->channels > kMaxChannels)
         return fail(VR_ERR_INVALID_ARG, "channels = %d outside 1..%d", d->channels, kMaxChannels);
     if (d->frames < 1) return fail(VR_ERR_INVALID_ARG, "frames = %d < 1", d->frames);
@@ -124,11 +131,17 @@ vr_status check_desc(const vr_volume_desc* d) {
                 return fail(VR_ERR_INVALID_ARG, "brick[%d] = %d is not 4, 8, 16 or 32", a,
                             d->brick[a]);
     const BrickGeom g = make_geom(*d);
-    const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
-    if (words >= (1ull << 31) || g.frame_bytes >= (1ull << 32))
+    const uint64_t bricks = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2];
+    uint64_t total = 0;
+    if (bricks >= (1ull << 32) || g.frame_bytes >= (1ull << 44) ||
+        __builtin_mul_overflow(g.frame_bytes, (uint64_t)d->frames, &total))
+        return fail(VR_ERR_INVALID_ARG, "one frame needs %llu bricks, %llu bytes (limits 2^32, 2^44)",
+                    (unsigned long long)bricks, (unsigned long long)g.frame_bytes);
+    if (d->row_pairs && needs_large(*d, g))
         return fail(VR_ERR_INVALID_ARG,
-                    "one frame needs %llu stored voxels, %llu bytes (limits 2^31, 2^32)",
-                    (unsigned long long)words, (unsigned long long)g.frame_bytes);
+                    "row pairs need axes of at most %d voxels and frames below 2^31 stored voxels "
+                    "and 4 GiB",
+                    kFloatAxis);
     return VR_OK;
 }
 
@@ -300,6 +313,10 @@ extern "C" vr_status vr_test_transparent_max(float lo, float hi, int32_t bits, f
     return ok();
 }
 
+void set_clamp_d64(const BrickGeom& g, ReqParams* P) {
+    for (int a = 0; a < 3; ++a) P->d64.clamp_hi[a] = std::nextafter((double)(g.n[a] + 1), 0.0);
+}
+
 // Per-eye ray basis in double, rounded once to float.  Perspective: origin is
 // the eye e_s = center + s (sep / 2) r; the unnormalised direction to pixel
 // (sx, sy) is conv f - s (sep / 2) r + sx w r + sy h u.  Orthographic: the
@@ -312,7 +329,8 @@ void make_params(const vr_render_req& r, const vr_transfer* tf_in, ReqParams* P)
     P->vox = v.storage + (uint64_t)r.frame * v.geom.frame_bytes;
     P->channels = d.channels;
     P->variant = variant_index(d.channels, d.dtype == VR_U16, r.precision == VR_FP16,
-                               v.geom.pairs != 0);
+                               v.geom.pairs != 0, v.large);
+    set_clamp_d64(v.geom, P);
 
     const double full = std::ldexp(1.0, d.bits) - 1.0;
     for (int c = 0; c < d.channels; ++c) {
@@ -340,6 +358,7 @@ void make_params(const vr_render_req& r, const vr_transfer* tf_in, ReqParams* P)
     const double c[3] = {r.cam.center[0], r.cam.center[1], r.cam.center[2]};
     const double W = r.width > 0 ? r.width : 1, H = r.height > 0 ? r.height : 1;
     P->eyes = r.stereo ? 2 : 1;
+    auto& D = P->d64;
     if (r.cam.projection == VR_PERSPECTIVE) {
         const double conv = r.cam.convergence;
         const double h = conv * std::tan(0.5 * (double)r.cam.fov_y);
@@ -349,29 +368,42 @@ void make_params(const vr_render_req& r, const vr_transfer* tf_in, ReqParams* P)
             const double s = r.stereo ? (e == 0 ? -1.0 : 1.0) : 0.0;
             for (int a = 0; a < 3; ++a) {
                 const double eye = c[a] + s * half_sep * rt[a];
-                P->o0[e][a] = (float)((eye - org[a]) / sp[a]);
-                P->base[e][a] = (float)(conv * f[a] - s * half_sep * rt[a]);
+                D.o0[e][a] = (eye - org[a]) / sp[a];
+                D.base[e][a] = conv * f[a] - s * half_sep * rt[a];
             }
         }
         for (int a = 0; a < 3; ++a) {
-            P->ou[a] = P->ov[a] = 0.0f;
-            P->du[a] = (float)(w * rt[a]);
-            P->dv[a] = (float)(h * u[a]);
+            D.ou[a] = D.ov[a] = 0.0;
+            D.du[a] = w * rt[a];
+            D.dv[a] = h * u[a];
         }
-        P->tmin = 0.0f;
+        D.tmin = 0.0;
     } else {
         const double h = 0.5 * (double)r.cam.ortho_height;
         const double w = h * W / H;
         for (int a = 0; a < 3; ++a) {
-            P->o0[0][a] = P->o0[1][a] = (float)((c[a] - org[a]) / sp[a]);
-            P->ou[a] = (float)(w * rt[a] / sp[a]);
-            P->ov[a] = (float)(h * u[a] / sp[a]);
-            P->base[0][a] = P->base[1][a] = (float)f[a];
-            P->du[a] = P->dv[a] = 0.0f;
+            D.o0[0][a] = D.o0[1][a] = (c[a] - org[a]) / sp[a];
+            D.ou[a] = w * rt[a] / sp[a];
+            D.ov[a] = h * u[a] / sp[a];
+            D.base[0][a] = D.base[1][a] = f[a];
+            D.du[a] = D.dv[a] = 0.0;
         }
-        P->tmin = -std::numeric_limits<float>::infinity();
+        D.tmin = -std::numeric_limits<double>::infinity();
     }
-    for (int a = 0; a < 3; ++a) P->inv_sp[a] = (float)(1.0 / sp[a]);
+    for (int a = 0; a < 3; ++a) D.inv_sp[a] = 1.0 / sp[a];
+    // The FP32 basis is the FP64 one rounded once.
+    for (int a = 0; a < 3; ++a) {
+        for (int e = 0; e < 2; ++e) {
+            P->o0[e][a] = (float)D.o0[e][a];
+            P->base[e][a] = (float)D.base[e][a];
+        }
+        P->ou[a] = (float)D.ou[a];
+        P->ov[a] = (float)D.ov[a];
+        P->du[a] = (float)D.du[a];
+        P->dv[a] = (float)D.dv[a];
+        P->inv_sp[a] = (float)D.inv_sp[a];
+    }
+    P->tmin = (float)D.tmin;
     if (r.light.enabled) {
         double l[3] = {r.light.direction[0], r.light.direction[1], r.light.direction[2]};
         normalise(l);
@@ -385,12 +417,15 @@ void make_params(const vr_render_req& r, const vr_transfer* tf_in, ReqParams* P)
         P->light.on = 1;
     }
     P->step = r.step;
+    D.step = (double)r.step;
     P->tau = r.term_alpha;
     const double bga = r.background[3];
     for (int q = 0; q < 3; ++q) P->bg[q] = (float)(bga * (double)r.background[q]);
     P->bg[3] = r.background[3];
     P->sx_scale = (float)(2.0 / W);
     P->sy_scale = (float)(2.0 / H);
+    D.sx_scale = 2.0 / W;
+    D.sy_scale = 2.0 / H;
     P->width = r.width;
     P->height = r.height;
     P->out = r.out_rgba;
@@ -491,6 +526,9 @@ vr_status vr_create_volume(vr_ctx* ctx, const vr_volume_desc* desc, void* dev_st
     if (storage_bytes < need)
         return fail(VR_ERR_OUT_OF_MEMORY, "storage holds %llu bytes, the volume needs %llu",
                     (unsigned long long)storage_bytes, (unsigned long long)need);
+    const bool large = needs_large(*desc, g) || ctx->force_large;
+    if (large && desc->row_pairs)
+        return fail(VR_ERR_INVALID_ARG, "row pairs are not available with large-volume addressing");
     uint64_t used = ctx->used.load();
     do {
         if (used + need > ctx->budget)
@@ -502,6 +540,7 @@ vr_status vr_create_volume(vr_ctx* ctx, const vr_volume_desc* desc, void* dev_st
     v->ctx = ctx;
     v->desc = *desc;
     v->geom = g;
+    v->large = large;
     v->storage = (uint8_t*)dev_storage;
     v->bytes = need;
     for (int c = 0; c < kMaxChannels; ++c) default_transfer(&v->tf[c]);
@@ -667,7 +706,8 @@ vr_status vr_debug_sample(vr_volume* vol, int32_t frame, const float* pts, int32
     P.vox = vol->storage + (uint64_t)frame * vol->geom.frame_bytes;
     P.channels = vol->desc.channels;
     P.variant = variant_index(vol->desc.channels, vol->desc.dtype == VR_U16, false,
-                              vol->geom.pairs != 0);
+                              vol->geom.pairs != 0, vol->large);
+    set_clamp_d64(vol->geom, &P);
     DeviceGuard dg(vol->ctx->device);
     hipError_t e = launch_debug_sample(P, pts, n, out, (hipStream_t)hip_stream);
     if (e != hipSuccess) return hip_fail(e, "debug sample launch");

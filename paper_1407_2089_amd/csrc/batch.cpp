@@ -157,10 +157,10 @@ static const TileShape kCandidates[] = {{8, 8}, {16, 4}, {4, 16}, {32, 2}, {64, 
 // Shape class: the set of data variants in the batch and the order of
 // magnitude of its ray count.
 static uint64_t shape_class(const ReqParams* params, int n) {
-    uint32_t variants = 0;
+    uint64_t variants = 0;  // below 2^48: batched variants only
     double rays = 0.0;
     for (int q = 0; q < n; ++q) {
-        variants |= 1u << params[q].variant;
+        variants |= 1ull << params[q].variant;
         rays += (double)params[q].eyes * params[q].width * params[q].height;
     }
     const int mag = rays > 1.0 ? (int)std::floor(std::log2(rays)) : 0;
@@ -235,20 +235,24 @@ static vr_status tune(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
 vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
                         bool allow_tuning) {
     if (n <= 0) return VR_OK;
-    // Lit requests take plain launches on the slot's stream (the batch
-    // kernels are unlit); the rest form the batch.
+    // Lit requests and large volumes take plain launches on the slot's stream
+    // (the batch kernels are unlit and 32-bit addressed); the rest form the
+    // batch.
+    const auto plain = [](const ReqParams& P) {
+        return P.light.on != 0 || variant_large(P.variant);
+    };
     std::vector<ReqParams> unlit;
-    bool any_lit = false;
-    for (int q = 0; q < n && !any_lit; ++q) any_lit = params[q].light.on != 0;
-    if (any_lit) {
+    bool any_plain = false;
+    for (int q = 0; q < n && !any_plain; ++q) any_plain = plain(params[q]);
+    if (any_plain) {
         for (int q = 0; q < n; ++q) {
-            if (!params[q].light.on) {
+            if (!plain(params[q])) {
                 unlit.push_back(params[q]);
                 continue;
             }
             const hipError_t e = launch_render(params[q], ctx->plain_tile, ctx->clear_skip,
                                                s->stream);
-            if (e != hipSuccess) return hip_fail(e, "lit render launch");
+            if (e != hipSuccess) return hip_fail(e, "render launch");
         }
         params = unlit.data();
         n = (int)unlit.size();
@@ -324,7 +328,7 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
     // up to a power of two (a few captured graphs cover all batch sizes),
     // capped so that a block takes a handful of items of a large batch.
     int64_t most = 0;
-    for (int v = 0; v < kVariants; ++v) most = std::max<int64_t>(most, w->group[v].n_items);
+    for (int v = 0; v < kBatchVariants; ++v) most = std::max<int64_t>(most, w->group[v].n_items);
     int blocks = kWave;
     while (blocks < most && blocks < kBatchBlocksMax) blocks *= 2;
     if ((e = hipMemcpyAsync(s->d_reqs, s->h_reqs, sizeof(ReqParams) * (size_t)n,
@@ -383,6 +387,12 @@ extern "C" vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wav
 extern "C" vr_status vr_test_clear_skip(vr_ctx* ctx, int32_t on) {
     if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
     ctx->clear_skip = on != 0;
+    return ok();
+}
+
+extern "C" vr_status vr_test_large_addressing(vr_ctx* ctx, int32_t on) {
+    if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    ctx->force_large = on != 0;
     return ok();
 }
 

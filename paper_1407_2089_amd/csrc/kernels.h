@@ -25,7 +25,7 @@ struct BatchGroup {
 // dispatcher balances the load as blocks finish, with no shared counter.
 struct BatchWork {
     TileShape tile;
-    BatchGroup group[kVariants];
+    BatchGroup group[kBatchVariants];
 };
 
 hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,

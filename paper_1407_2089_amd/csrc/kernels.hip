@@ -149,15 +149,15 @@ typedef void (*batch_fn)(const BatchWork*, const ReqParams*, const int32_t*);
 
 // Kernel tables indexed by variant, null where the variant does not exist.
 template <int V> constexpr batch_fn batch_entry() {
-    if constexpr (variant_exists(V)) return batch_kernel<V>;
+    if constexpr (variant_exists(V) && !variant_large(V)) return batch_kernel<V>;
     else return nullptr;
 }
 template <int... V>
-constexpr std::array<batch_fn, kVariants> batch_table(std::integer_sequence<int, V...>) {
+constexpr std::array<batch_fn, kBatchVariants> batch_table(std::integer_sequence<int, V...>) {
     return {{batch_entry<V>()...}};
 }
-static const std::array<batch_fn, kVariants> kBatch =
-    batch_table(std::make_integer_sequence<int, kVariants>{});
+static const std::array<batch_fn, kBatchVariants> kBatch =
+    batch_table(std::make_integer_sequence<int, kBatchVariants>{});
 
 // ------------------------------------------------------------ test hook
 template <int V>
@@ -167,10 +167,18 @@ __global__ __launch_bounds__(256) void debug_sample_kernel(ReqParams P, const fl
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float x[C];
-    const Sampler S = make_sampler(P.vox, P.g);
-    sample<C, Variant<V>::U16, Variant<V>::F16, Variant<V>::PAIRS>(P.g, S, pts[3 * i],
-                                                                    pts[3 * i + 1],
-                                                                    pts[3 * i + 2], x);
+    if constexpr (Variant<V>::LARGE) {
+        using T = typename WordT<C, Variant<V>::U16>::T;
+        const SamplerL S = make_sampler_large(P);
+        interpolate<C, Variant<V>::U16, Variant<V>::F16>(
+            fetch<T, false>(P.g, S, (double)pts[3 * i] + 1.0, (double)pts[3 * i + 1] + 1.0,
+                            (double)pts[3 * i + 2] + 1.0), x);
+    } else {
+        const Sampler S = make_sampler(P.vox, P.g);
+        sample<C, Variant<V>::U16, Variant<V>::F16, Variant<V>::PAIRS>(P.g, S, pts[3 * i],
+                                                                        pts[3 * i + 1],
+                                                                        pts[3 * i + 2], x);
+    }
 #pragma unroll
     for (int c = 0; c < C; ++c) out[(size_t)i * C + c] = x[c];
 }
@@ -233,7 +241,8 @@ hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_ski
 hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
                         const int32_t* dev_prefix, uint64_t mask, int blocks, hipStream_t s) {
     if (blocks <= 0) return hipErrorInvalidValue;
-    for (int v = 0; v < kVariants; ++v) {
+    if (mask >> kBatchVariants) return hipErrorInvalidValue;
+    for (int v = 0; v < kBatchVariants; ++v) {
         if (!(mask & (1ull << v))) continue;
         if (!kBatch[v]) return hipErrorInvalidValue;
         hipLaunchKernelGGL(kBatch[v], dim3(blocks), dim3(kWave), 0, s, dev_work, dev_reqs,

@@ -70,6 +70,7 @@ struct vr_volume {
     uint64_t bytes = 0;
     std::mutex tf_mu;
     vr_transfer tf[vr::kMaxChannels]{};
+    bool large = false;             // large-volume addressing (64-bit, FP64 positions)
     std::atomic<int> in_flight{0};  // served tickets that read this volume
     // vr_stream_frame / vr_stream_ready: the render stream's work before an
     // upload, and per slot the end of its last upload (events are re-recorded;
@@ -100,6 +101,7 @@ struct vr_ctx {
     vr::TileShape batch_tile{8, 8};
     vr::TileShape plain_tile{8, 8};  // wave tile of vr_render launches
     bool clear_skip = true;  // vr_render leaves out transparent samples' arithmetic
+    bool force_large = false;  // new volumes take large-volume addressing (test hook)
     std::map<uint64_t, vr::TileShape> tuned;
     vr::Scheduler* server = nullptr;  // created by the first vr_submit (server.cpp)
     std::mutex server_mu;
@@ -111,6 +113,11 @@ namespace vr {
 vr_status check_desc(const vr_volume_desc* d);
 vr_status check_request(const vr_ctx* ctx, const vr_render_req* r);
 BrickGeom make_geom(const vr_volume_desc& d);
+// True when the volume needs large-volume addressing: an axis above
+// kFloatAxis voxels, or a frame of 2^31 stored words or 4 GiB and more.
+bool needs_large(const vr_volume_desc& d, const BrickGeom& g);
+// Clamp bounds of the FP64 sample positions (large variants).
+void set_clamp_d64(const BrickGeom& g, ReqParams* P);
 // Fills the device parameters of a request from the volume's current transfer
 // functions (or from `tf` when given).
 void make_params(const vr_render_req& r, const vr_transfer* tf, ReqParams* P);

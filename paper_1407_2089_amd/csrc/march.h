@@ -8,6 +8,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "params.h"
 
 namespace vr {
@@ -189,6 +191,43 @@ __device__ __forceinline__ Sampler make_sampler(const uint8_t* vox, const BrickG
     return S;
 }
 
+// Large volumes (an axis above 8192 voxels, or a frame of 2^31 words or
+// 4 GiB and more): plain global loads at 64-bit addresses, sample positions
+// in FP64.
+struct SamplerL {
+    const uint8_t* vox;
+    double hi[3];       // largest double below n + 1 per axis (clamp bound)
+    uint32_t row_b;     // bytes per brick row
+    uint32_t plane_b;   // bytes per brick plane
+    uint32_t diag_b;    // row_b + plane_b
+};
+
+__device__ __forceinline__ SamplerL make_sampler_large(const ReqParams& P) {
+    SamplerL S;
+    S.vox = P.vox;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) S.hi[a] = P.d64.clamp_hi[a];
+    S.row_b = (uint32_t)(P.g.row * P.g.word);
+    S.plane_b = (uint32_t)(P.g.plane * P.g.word);
+    S.diag_b = S.row_b + S.plane_b;
+    return S;
+}
+
+#define VR_GLOBAL __attribute__((address_space(1)))
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+template <typename T> __device__ __forceinline__ T load_global(const uint8_t* p) {
+    if constexpr (sizeof(T) <= 4) {
+        return *(const VR_GLOBAL T*)p;
+    } else if constexpr (sizeof(T) == 8) {
+        const u32x2_t w = *(const VR_GLOBAL u32x2_t*)p;
+        return make_uint2(w.x, w.y);
+    } else {
+        const u32x4_t w = *(const VR_GLOBAL u32x4_t*)p;
+        return make_uint4(w.x, w.y, w.z, w.w);
+    }
+}
+
 // The 2x2x2 taps around one sample point, in flight or landed.
 template <typename T> struct Taps {
     T w000, w100, w010, w110, w001, w101, w011, w111;
@@ -253,6 +292,56 @@ __device__ __forceinline__ Taps<T> fetch(const BrickGeom& g, const Sampler& S, f
     t.w011 = load_word<T>(S.rsrc, o, S.diag_b);
     t.w111 = load_word<T>(S.rsrc, o + W, S.diag_b);
     return t;
+}
+
+// Large-volume fetch: the same taps, with the point, its clamp into
+// [0, n + 1) and its floor in FP64 (a stored coordinate up to 16385 keeps
+// 2^-38 voxel resolution) and the byte offset in 64 bits.  The brick index
+// fits 32 bits (a frame holds fewer than 2^32 bricks, checked at volume
+// creation), and so does the in-brick word index.  The fraction in [0, 1) is
+// rounded to FP32 for the interpolation weights.
+template <typename T, bool PAIRS>
+__device__ __forceinline__ Taps<T> fetch(const BrickGeom& g, const SamplerL& S, double qx,
+                                         double qy, double qz) {
+    static_assert(!PAIRS, "large volumes have no row-pair layout");
+    Taps<T> t;
+    const double p[3] = {qx, qy, qz};
+    float f[3];
+    uint32_t s[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double q = __builtin_fmin(__builtin_fmax(p[a], 0.0), S.hi[a]);
+        const double fl = __builtin_floor(q);
+        s[a] = (uint32_t)fl;
+        f[a] = (float)(q - fl);
+    }
+    t.fx = f[0];
+    t.fy = f[1];
+    t.fz = f[2];
+    const uint32_t bx = s[0] >> g.shift[0], lx = s[0] & ((1u << g.shift[0]) - 1u);
+    const uint32_t by = s[1] >> g.shift[1], ly = s[1] & ((1u << g.shift[1]) - 1u);
+    const uint32_t bz = s[2] >> g.shift[2], lz = s[2] & ((1u << g.shift[2]) - 1u);
+    const uint32_t brick = (bz * (uint32_t)g.nb[1] + by) * (uint32_t)g.nb[0] + bx;
+    const uint32_t local = lz * (uint32_t)g.plane + ly * (uint32_t)g.row + lx;
+    constexpr uint32_t W = sizeof(T);
+    const uint8_t* b = S.vox + ((uint64_t)brick * (uint32_t)g.brick + local) * W;
+    const uint8_t* r = b + S.row_b;
+    const uint8_t* z = b + S.plane_b;
+    const uint8_t* rz = b + S.diag_b;
+    t.w000 = load_global<T>(b);
+    t.w100 = load_global<T>(b + W);
+    t.w010 = load_global<T>(r);
+    t.w110 = load_global<T>(r + W);
+    t.w001 = load_global<T>(z);
+    t.w101 = load_global<T>(z + W);
+    t.w011 = load_global<T>(rz);
+    t.w111 = load_global<T>(rz + W);
+    return t;
+}
+
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) {
+    return __builtin_fma(a, b, c);
 }
 
 __device__ __forceinline__ float lerp(float a, float b, float f) { return fmaf(f, b - a, a); }
@@ -415,7 +504,16 @@ template <int V> struct Variant {
     static constexpr bool U16 = variant_u16(V);
     static constexpr bool F16 = variant_fp16(V);
     static constexpr bool PAIRS = variant_pairs(V);
+    static constexpr bool LARGE = variant_large(V);
+    // Position type: FP64 for large volumes.
+    using R = typename std::conditional<LARGE, double, float>::type;
+    using Smp = typename std::conditional<LARGE, SamplerL, Sampler>::type;
 };
+
+template <bool LARGE> __device__ __forceinline__ auto sampler_for(const ReqParams& P) {
+    if constexpr (LARGE) return make_sampler_large(P);
+    else return make_sampler(P.vox, P.g);
+}
 
 // One pixel of one eye: returns nothing, writes RGBA (and the sample count).
 // `valid` false lanes take part in the wave's loop structure but do no work.
@@ -425,19 +523,20 @@ template <int V> struct Variant {
 // small gradient's direction; always the lerp tree, so that a flat
 // neighbourhood has exactly zero gradient and takes ambient + diffuse), the
 // normal against it, one directional light.
-template <int C, bool U16, bool PAIRS, typename Word>
-__device__ __forceinline__ void shade_at(const ReqParams& P, const Sampler& S, const float (&q)[3],
+template <int C, bool U16, bool PAIRS, typename Word, typename Smp, typename R>
+__device__ __forceinline__ void shade_at(const ReqParams& P, const Smp& S, const R (&q)[3],
                                          float (&shade)[C]) {
     float g[3][C];
+    const R one = 1;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         float hi[C], lo[C];
-        interpolate<C, U16, false, true>(fetch<Word, PAIRS>(P.g, S, a == 0 ? q[0] + 1.0f : q[0],
-                                                            a == 1 ? q[1] + 1.0f : q[1],
-                                                            a == 2 ? q[2] + 1.0f : q[2]), hi);
-        interpolate<C, U16, false, true>(fetch<Word, PAIRS>(P.g, S, a == 0 ? q[0] - 1.0f : q[0],
-                                                            a == 1 ? q[1] - 1.0f : q[1],
-                                                            a == 2 ? q[2] - 1.0f : q[2]), lo);
+        interpolate<C, U16, false, true>(fetch<Word, PAIRS>(P.g, S, a == 0 ? q[0] + one : q[0],
+                                                            a == 1 ? q[1] + one : q[1],
+                                                            a == 2 ? q[2] + one : q[2]), hi);
+        interpolate<C, U16, false, true>(fetch<Word, PAIRS>(P.g, S, a == 0 ? q[0] - one : q[0],
+                                                            a == 1 ? q[1] - one : q[1],
+                                                            a == 2 ? q[2] - one : q[2]), lo);
 #pragma unroll
         for (int c = 0; c < C; ++c) g[a][c] = (hi[c] - lo[c]) * P.light.gscale[a];
     }
@@ -454,18 +553,15 @@ __device__ __forceinline__ void shade_at(const ReqParams& P, const Sampler& S, c
     }
 }
 
-template <int V, bool kClear = true, bool kLit = false>
-__device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px, int py,
-                                             bool valid) {
-    constexpr int C = Variant<V>::C;
-    constexpr bool U16 = Variant<V>::U16;
-    constexpr bool F16 = Variant<V>::F16;
-    constexpr bool PAIRS = Variant<V>::PAIRS;
-
+// Ray of one pixel in index space: direction d (index units per unit of t),
+// entry point pe in stored coordinates (index-space position + 1) and sample
+// count n (0 for a ray that misses the box or an invalid lane).
+__device__ __forceinline__ void pixel_ray(const ReqParams& P, int eye, int px, int py, bool valid,
+                                          float (&d)[3], float (&pe)[3], int& n) {
     const float sx = fmaf((float)px + 0.5f, P.sx_scale, -1.0f);
     const float sy = fmaf(-((float)py + 0.5f), P.sy_scale, 1.0f);
 
-    float p0[3], d[3];
+    float p0[3];
     float w[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -494,25 +590,82 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
             hit = hit && (p0[a] >= -1.0f) && (p0[a] <= hi);
         }
     }
-    int n = 0;
+    n = 0;
     if (hit && t_in < t_out) {
         const float span = (t_out - t_in) / P.step - 0.5f;
         const float c = ceilf(span);
         n = c <= 0.0f ? 0 : (c >= (float)kMaxSamples ? kMaxSamples : (int)c);
     }
-
-    // Entry point in stored coordinates (index-space position + 1).
-    float pe[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) pe[a] = fmaf(n > 0 ? t_in : 0.0f, d[a], p0[a]) + 1.0f;
+}
+
+// The same ray in FP64 from the request's FP64 basis (large volumes).
+__device__ __forceinline__ void pixel_ray(const ReqParams& P, int eye, int px, int py, bool valid,
+                                          double (&d)[3], double (&pe)[3], int& n) {
+    const auto& D = P.d64;
+    const double sx = __builtin_fma((double)px + 0.5, D.sx_scale, -1.0);
+    const double sy = __builtin_fma(-((double)py + 0.5), D.sy_scale, 1.0);
+    double p0[3], w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double o = eye ? D.o0[1][a] : D.o0[0][a];
+        const double bse = eye ? D.base[1][a] : D.base[0][a];
+        p0[a] = __builtin_fma(sy, D.ov[a], __builtin_fma(sx, D.ou[a], o));
+        w[a] = __builtin_fma(sy, D.dv[a], __builtin_fma(sx, D.du[a], bse));
+    }
+    const double inv_len =
+        1.0 / __builtin_sqrt(__builtin_fma(w[0], w[0], __builtin_fma(w[1], w[1], w[2] * w[2])));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = w[a] * inv_len * D.inv_sp[a];
+    double t_in = D.tmin, t_out = __builtin_inf();
+    bool hit = valid;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double hi = (double)P.g.n[a];
+        if (d[a] != 0.0) {
+            const double inv = 1.0 / d[a];
+            const double t1 = (-1.0 - p0[a]) * inv;
+            const double t2 = (hi - p0[a]) * inv;
+            t_in = __builtin_fmax(t_in, __builtin_fmin(t1, t2));
+            t_out = __builtin_fmin(t_out, __builtin_fmax(t1, t2));
+        } else {
+            hit = hit && (p0[a] >= -1.0) && (p0[a] <= hi);
+        }
+    }
+    n = 0;
+    if (hit && t_in < t_out) {
+        const double c = __builtin_ceil((t_out - t_in) / D.step - 0.5);
+        n = c <= 0.0 ? 0 : (c >= (double)kMaxSamples ? kMaxSamples : (int)c);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) pe[a] = __builtin_fma(n > 0 ? t_in : 0.0, d[a], p0[a]) + 1.0;
+}
+
+template <int V, bool kClear = true, bool kLit = false>
+__device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px, int py,
+                                             bool valid) {
+    constexpr int C = Variant<V>::C;
+    constexpr bool U16 = Variant<V>::U16;
+    constexpr bool F16 = Variant<V>::F16;
+    constexpr bool PAIRS = Variant<V>::PAIRS;
+    constexpr bool LARGE = Variant<V>::LARGE;
+    using R = typename Variant<V>::R;
+
+    R d[3], pe[3];
+    int n;
+    pixel_ray(P, eye, px, py, valid, d, pe, n);
 
     // Transfer-function coefficients (wave-uniform).
     ChanTF tf[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) tf[c] = P.tf[c];
 
-    const Sampler S = make_sampler(P.vox, P.g);
-    const float half_step = 0.5f * P.step;
+    const typename Variant<V>::Smp S = sampler_for<LARGE>(P);
+    R step;
+    if constexpr (LARGE) step = P.d64.step;
+    else step = P.step;
+    const R half_step = (R)0.5 * step;
     const float tau = P.tau;
     float Cr = 0.0f, Cg = 0.0f, Cb = 0.0f, A = 0.0f;
     int k = 0;
@@ -535,9 +688,9 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         interpolate<C, U16, F16>(t, x);
         float shade[C];
         if constexpr (kLit) {
-            const float sj = fmaf((float)j, P.step, half_step);
-            const float q[3] = {fmaf(sj, d[0], pe[0]), fmaf(sj, d[1], pe[1]),
-                                fmaf(sj, d[2], pe[2])};
+            const R sj = fma_r((R)j, step, half_step);
+            const R q[3] = {fma_r(sj, d[0], pe[0]), fma_r(sj, d[1], pe[1]),
+                            fma_r(sj, d[2], pe[2])};
             shade_at<C, U16, PAIRS, Word>(P, S, q, shade);
         }
         float amax = 0.0f, r = 0.0f, gg = 0.0f, bb = 0.0f;
@@ -560,9 +713,9 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         A = A + wgt;
     };
     auto fetch_at = [&](int j) -> Taps<Word> {
-        const float sj = fmaf((float)j, P.step, half_step);
-        return fetch<Word, PAIRS>(P.g, S, fmaf(sj, d[0], pe[0]), fmaf(sj, d[1], pe[1]),
-                                  fmaf(sj, d[2], pe[2]));
+        const R sj = fma_r((R)j, step, half_step);
+        return fetch<Word, PAIRS>(P.g, S, fma_r(sj, d[0], pe[0]), fma_r(sj, d[1], pe[1]),
+                                  fma_r(sj, d[2], pe[2]));
     };
     if (n > 0) {
         // Software pipeline over pairs of samples: the taps of the next

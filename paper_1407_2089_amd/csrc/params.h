@@ -15,15 +15,27 @@ constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kBlockThreads = 256;
 
 // Data variant of a request: channels (1..6), voxel width, sample precision
-// and storage layout.  Index = (channels - 1) + 6 u16 + 12 fp16 + 24 pairs.
-constexpr int kVariants = 48;
-inline constexpr int variant_index(int channels, bool u16, bool fp16, bool pairs) {
-    return (channels - 1) + (u16 ? 6 : 0) + (fp16 ? 12 : 0) + (pairs ? 24 : 0);
+// and storage layout.  Index = (channels - 1) + 6 u16 + 12 fp16 + 24 pairs,
+// or + 48 for a large volume (an axis above 8192 voxels or a frame of 2^31
+// words or 4 GiB and more: 64-bit addresses and FP64 ray positions; never
+// row pairs).
+constexpr int kVariants = 72;
+inline constexpr int variant_index(int channels, bool u16, bool fp16, bool pairs,
+                                   bool large = false) {
+    return (channels - 1) + (u16 ? 6 : 0) + (fp16 ? 12 : 0) + (large ? 48 : pairs ? 24 : 0);
 }
 inline constexpr int variant_channels(int v) { return v % 6 + 1; }
 inline constexpr bool variant_u16(int v) { return (v / 6) % 2 != 0; }
 inline constexpr bool variant_fp16(int v) { return (v / 12) % 2 != 0; }
-inline constexpr bool variant_pairs(int v) { return v >= 24; }
+inline constexpr bool variant_pairs(int v) { return v >= 24 && v < 48; }
+inline constexpr bool variant_large(int v) { return v >= 48; }
+// Variants that the batched launch serves (large ones take plain launches).
+constexpr int kBatchVariants = 48;
+
+// Axes up to kMaxAxis voxels; above kFloatAxis the FP32 sample position no
+// longer resolves a thousandth of a voxel and the large variants take over.
+constexpr int kFloatAxis = 8192;
+constexpr int kMaxAxis = 16384;
 
 // Bytes of one stored voxel word: all channels of a voxel side by side, the
 // channel count rounded up to 1, 2, 4 or 8.
@@ -123,6 +135,13 @@ struct ReqParams {
     int32_t pad_;
     float* out;             // [eyes][H][W][4]
     int32_t* samples;       // [eyes][H][W] or null
+    // Large variants: the same ray basis in FP64, and the clamp bound of
+    // stored coordinates (largest double below n + 1 per axis).
+    struct {
+        double o0[2][3], ou[3], ov[3], base[2][3], du[3], dv[3], inv_sp[3];
+        double tmin, step, sx_scale, sy_scale;
+        double clamp_hi[3];
+    } d64;
 };
 
 // Work decomposition: one item = one wave's pixel tile of one eye of one

@@ -404,3 +404,32 @@ def realistic_scene(seed=2, width=1920, height=1080, dims=(512, 512, 64)):
 
 
 SCENES = {"tiny": tiny_scene, "realistic": realistic_scene}
+
+
+def montage(dims, channels, seed, tile=(1024, 1024), distinct=3, device="cuda", log=None):
+    """Seeded stand-in for a stitched confocal montage, [C][Z][Y][X] uint8 on
+    the GPU: a grid of tile-sized fields cut from `distinct` generated 8-bit
+    frames (DeviceSeries, full depth), tile (gx, gy) taking frame
+    (gx + 2 gy) mod distinct, mirrored in x on odd columns and in y on odd
+    rows, the last row and column cropped to the montage's edge.  `log`, if
+    given, is called with a line per generated frame."""
+    import torch
+    nx, ny, nz = dims
+    tx, ty = tile
+    tiles = []
+    for k in range(distinct):
+        tiles.append(DeviceSeries((tx, ty, nz), channels, 8, seed + 101 * k,
+                                  device=device).frame(0))
+        if log is not None:
+            log(f"montage tile frame {k + 1} of {distinct} generated")
+    out = torch.empty((channels, nz, ny, nx), dtype=torch.uint8, device=device)
+    for gy in range((ny + ty - 1) // ty):
+        for gx in range((nx + tx - 1) // tx):
+            t = tiles[(gx + 2 * gy) % distinct]
+            if gx % 2:
+                t = t.flip(3)
+            if gy % 2:
+                t = t.flip(2)
+            w, h = min(tx, nx - gx * tx), min(ty, ny - gy * ty)
+            out[:, :, gy * ty:gy * ty + h, gx * tx:gx * tx + w] = t[:, :, :h, :w]
+    return out

@@ -562,3 +562,116 @@ def serving(ctx, total_gb=150.0, seconds=10.0, warm=1.0,
     for v in vols:
         v.destroy()
     return results
+
+
+# ------------------------------------------------------------------ montage
+
+MONTAGE_DIMS = (10173, 3858, 74)   # stitched SVZ montage, 5 channels, 8 bit
+MONTAGE_CHANNELS = 5
+
+
+def montage_setup(ctx, seed=3):
+    """The five-channel uint8 montage resident in HBM (large-volume
+    addressing: 2.9 G voxels per channel, 23 GB of bricks) with the default
+    transfer functions; returns (volume, source tensor, tfs)."""
+    log("montage: generating 10173x3858x74x5 uint8")
+    src = synth.montage(MONTAGE_DIMS, MONTAGE_CHANNELS, seed, log=log)
+    tfs = [synth.TF(20.0 / 255.0, 200.0 / 255.0, 0.0, 1.0, PALETTE[c])
+           for c in range(MONTAGE_CHANNELS)]
+    vol = Volume(ctx, MONTAGE_DIMS, MONTAGE_CHANNELS, 1, VR_U8, 8)
+    vol.upload(0, src)
+    for c, tf in enumerate(tfs):
+        vol.set_transfer(c, tf)
+    return vol, src, tfs
+
+
+def ray_crop(cam, W, H, eye, px, py, dims, margin=3):
+    """Index-space box [lo, hi) holding the part of pixel (px, py)'s ray that
+    lies in the volume's extended box [-1, n] per axis, widened by `margin`
+    voxels and clipped to the grid (unit spacing, origin 0); None if the ray
+    misses.  Rendering that crop (origin moved to lo) gives the ray the same
+    samples as the whole volume, so single pixels of a volume too large to
+    copy whole can be checked on their own."""
+    f = np.array(cam.forward, float)
+    f /= np.linalg.norm(f)
+    rt = np.cross(f, np.array(cam.up, float))
+    rt /= np.linalg.norm(rt)
+    u = np.cross(rt, f)
+    sx = (px + 0.5) * 2.0 / W - 1.0
+    sy = 1.0 - (py + 0.5) * 2.0 / H
+    c = np.array(cam.center, float)
+    if cam.projection == "perspective":
+        h = cam.convergence * np.tan(0.5 * cam.fov_y)
+        w = h * W / H
+        s = float(eye)
+        o = c + s * 0.5 * cam.eye_separation * rt
+        d = cam.convergence * f - s * 0.5 * cam.eye_separation * rt + sx * w * rt + sy * h * u
+        t0 = 0.0
+    else:
+        h = 0.5 * cam.ortho_height
+        w = h * W / H
+        o = c + sx * w * rt + sy * h * u
+        d = f
+        t0 = -np.inf
+    t1 = np.inf
+    n = np.array(dims, float)
+    for a in range(3):
+        if d[a] != 0.0:
+            ta, tb = (-1.0 - o[a]) / d[a], (n[a] - o[a]) / d[a]
+            t0, t1 = max(t0, min(ta, tb)), min(t1, max(ta, tb))
+        elif not -1.0 <= o[a] <= n[a]:
+            return None
+    if not t0 < t1:
+        return None
+    p0, p1 = o + t0 * d, o + t1 * d
+    lo = np.maximum(np.floor(np.minimum(p0, p1)) - margin, 0).astype(int)
+    hi = np.minimum(np.ceil(np.maximum(p0, p1)) + margin + 1, n).astype(int)
+    return lo, hi
+
+
+def montage_camera():
+    return synth.orbit_camera(MONTAGE_DIMS, 30.0, 55.0, 40.0, 0.6)
+
+
+def montage(ctx, reps=10, W=1920, H=1080, cpu=None):
+    """Stereo 1920x1080 views of the montage (perspective, elevation 55
+    degrees, the montage's long side filling the view).  `cpu`, if given, is
+    called as cpu(src, cam, tfs, W, H) while the source is still on the GPU
+    and its result is returned as cpu_baseline."""
+    import torch
+    vol, src, tfs = montage_setup(ctx)
+    cam = montage_camera()
+    base = cpu(src, cam, tfs, W, H) if cpu is not None else None
+    del src
+    stream = torch.cuda.current_stream()
+    out = torch.empty((2, H, W, 4), dtype=torch.float32, device="cuda")
+    smp = torch.empty((2, H, W), dtype=torch.int32, device="cuda")
+    req = make_request(vol.ptr, 0, cam, W, H, True, 1.0, 0.99, out, out_samples=smp)
+    vr_render(ctx.ptr, req, stream)
+    torch.cuda.synchronize()
+    samples = int(smp.to(torch.int64).sum().item())
+    req = make_request(vol.ptr, 0, cam, W, H, True, 1.0, 0.99, out)
+    for _ in range(2):
+        vr_render(ctx.ptr, req, stream)
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        vr_render(ctx.ptr, req, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    ms = float(np.median(times))
+    word = 8   # five uint8 channels per voxel word
+    eff = samples * 8 * word / (ms * 1e-3) / 1e9
+    frame_bytes = vol.bytes
+    vol.destroy()
+    return {"workload": "montage: 5ch u8 10173x3858x74 (one frame, 14.5 GB of voxels, "
+                        f"{frame_bytes / 1e9:.1f} GB of bricks), stereo {W}x{H}, step 1.0, "
+                        "tau 0.99, perspective elevation 55 deg",
+            "frame_bytes": frame_bytes, "samples": samples, "ms_per_step": ms,
+            "value": samples / (ms * 1e-3), "unit": "ray-samples/s",
+            "roofline": {"bound": "hbm", "achieved": eff, "peak": 8000.0, "unit": "GB/s",
+                         "frac": eff / 8000.0,
+                         "note": "effective bytes: 8 taps x 8-byte words per sample"},
+            "cpu_baseline": base}

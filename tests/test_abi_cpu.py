@@ -103,7 +103,7 @@ def test_default_brick_depends_on_word_size(ch, dtype, bits, brick):
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nx", 0), ("nz", 9000), ("channels", 0), ("channels", 7), ("frames", 0), ("dtype", 3),
+    ("nx", 0), ("nz", 16385), ("channels", 0), ("channels", 7), ("frames", 0), ("dtype", 3),
     ("bits", 7),
 ])
 def test_invalid_descriptions(field, value):
@@ -121,9 +121,30 @@ def test_invalid_spacing_bits_and_brick():
         with pytest.raises(vr.VrError) as e:
             vr.vr_volume_storage_bytes(d)
         assert e.value.status == vr.VR_ERR_INVALID_ARG
-    big = desc(8192, 8192, 64, ch=1, frames=1, dtype=vr.VR_U8, bits=8)
-    with pytest.raises(vr.VrError, match="2\\^31"):
-        vr.vr_volume_storage_bytes(big)
+
+
+def test_large_volume_limits():
+    # a frame of 2^31 words or more, 4 GiB or more, or an axis above 8192
+    # voxels takes the large-volume addressing: accepted, sized as any other
+    for dims, ch, dt in (((8192, 8192, 64), 1, vr.VR_U8), ((1024, 1024, 800), 2, vr.VR_U16),
+                         ((16384, 3, 2), 1, vr.VR_U8), ((10173, 3858, 74), 5, vr.VR_U8)):
+        d = desc(*dims, ch=ch, frames=2, dtype=dt, bits=8 if dt == vr.VR_U8 else 16)
+        word = WORD[ch] * (1 if dt == vr.VR_U8 else 2)
+        assert vr.vr_volume_storage_bytes(d) >= 2 * word * dims[0] * dims[1] * dims[2]
+    # ... but not in the row-pair layout, and not beyond 16384 voxels per axis
+    for d in (desc(8192, 8192, 64, ch=1, frames=1, dtype=vr.VR_U8, bits=8, row_pairs=1),
+              desc(8193, 4, 4, ch=2, frames=1, dtype=vr.VR_U16, bits=12, row_pairs=1)):
+        with pytest.raises(vr.VrError, match="row pairs") as e:
+            vr.vr_volume_storage_bytes(d)
+        assert e.value.status == vr.VR_ERR_INVALID_ARG
+    for dims in ((16385, 4, 4), (4, 16385, 4), (4, 4, 16385)):
+        with pytest.raises(vr.VrError, match="1..16384") as e:
+            vr.vr_volume_storage_bytes(desc(*dims))
+        assert e.value.status == vr.VR_ERR_INVALID_ARG
+    # storage of every frame must fit 64 bits
+    with pytest.raises(vr.VrError, match="bricks"):
+        vr.vr_volume_storage_bytes(desc(16384, 16384, 16384, ch=6, frames=1 << 30,
+                                        dtype=vr.VR_U16, bits=16))
 
 
 @pytest.fixture
@@ -181,6 +202,27 @@ def expect(status, fn, *a):
         fn(*a)
     assert e.value.status == status, str(e.value)
     return str(e.value)
+
+
+def test_large_addressing_hook(vctx):
+    # forced large-volume addressing refuses row pairs; without it they work;
+    # a large volume's requests pass validation like any other
+    d = desc(frames=1, row_pairs=1)
+    n = vr.vr_volume_storage_bytes(d)
+    vr.vr_test_large_addressing(vctx, True)
+    try:
+        msg = expect(vr.VR_ERR_INVALID_ARG, vr.vr_create_volume, vctx, d, FAKE, n)
+        assert "row pairs" in msg
+        v = vr.vr_create_volume(vctx, desc(frames=1), FAKE, n * 4)
+        expect(vr.VR_ERR_UNSUPPORTED, vr.vr_render, vctx, good_request(v))
+        vr.vr_destroy_volume(v)
+    finally:
+        vr.vr_test_large_addressing(vctx, False)
+    vr.vr_destroy_volume(vr.vr_create_volume(vctx, d, FAKE, n))
+    big = desc(16384, 8, 8, ch=6, frames=1, dtype=vr.VR_U16, bits=16)
+    v = vr.vr_create_volume(vctx, big, FAKE, vr.vr_volume_storage_bytes(big))
+    expect(vr.VR_ERR_UNSUPPORTED, vr.vr_render, vctx, good_request(v))
+    vr.vr_destroy_volume(v)
 
 
 def test_valid_request_reaches_the_device_check(vvol):
