@@ -81,15 +81,18 @@ __global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* 
 // full (same output bits; kept to test and time the transparent-sample skip).
 // Tiles of an eye run super-tile by super-tile (row-major over super-tiles of
 // kSuperW x kSuperH tiles, row-major inside each); the grid covers whole
-// super-tiles, and lanes past the image edge are invalid.  kLit: lit by the
-// request's directional light.
+// super-tiles, and lanes past the image edge are invalid.  A stereo pair's
+// two eyes take consecutive blocks per tile (the eyes' rays of one tile
+// meet nearly the same bricks, so the second often finds them in L2;
+// measured 2 % faster on a 36 GB montage, 1.4 % on a 230 MB frame).  kLit:
+// lit by the request's directional light.
 template <int V, bool kClear, bool kLit>
 __global__ __launch_bounds__(kWave) void render_kernel(ReqParams P, TileShape ts, int supers_x,
                                                        int per_eye) {
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int eye = b / per_eye;
+    const int eye = P.eyes == 2 ? (b & 1) : 0;
     int tx, ty;
-    tile_at(b - eye * per_eye, supers_x, tx, ty);
+    tile_at(P.eyes == 2 ? (b >> 1) : b, supers_x, tx, ty);
     const int lane = threadIdx.x;
     const int px = tx * ts.wave_w + lane % ts.wave_w;
     const int py = ty * ts.wave_h + lane / ts.wave_w;
@@ -114,12 +117,12 @@ __device__ __forceinline__ int find_req(const int32_t* __restrict__ prefix, int 
 
 template <int V>
 __device__ __forceinline__ void batch_tile(const ReqParams& P, const TileShape& ts, int local) {
-    // A request's items are its eyes' tiles in super-tile order.
+    // A request's items are its tiles in super-tile order, both eyes of a
+    // stereo tile in consecutive items.
     const int supers_x = (int)supers_across(P.width, ts);
-    const int per_eye = (int)tiles_per_eye(P.width, P.height, ts);
-    const int eye = local / per_eye;
+    const int eye = P.eyes == 2 ? (local & 1) : 0;
     int tx, ty;
-    tile_at(local - eye * per_eye, supers_x, tx, ty);
+    tile_at(P.eyes == 2 ? (local >> 1) : local, supers_x, tx, ty);
     const int lane = threadIdx.x & (kWave - 1);
     const int px = tx * ts.wave_w + lane % ts.wave_w;
     const int py = ty * ts.wave_h + lane / ts.wave_w;
