@@ -65,8 +65,13 @@ typedef enum { VR_ORTHO = 0, VR_PERSPECTIVE = 1 } vr_projection;
  * as the transfer-function description states, 4095 for 12-bit, 65535 for
  * 16-bit. */
 typedef struct {
-    int32_t nx, ny, nz; /* >= 1 each, <= 8192                                */
-    int32_t channels;   /* 1..4                                              */
+    int32_t nx, ny, nz; /* >= 1 each, <= 16384.  A volume with an axis above
+                           8192, or a frame of 2^31 stored words or 4 GiB
+                           and more, is large: its kernels address taps with
+                           64-bit offsets and step rays in FP64 (at most
+                           2^32 bricks and 2^44 bytes per frame), and it
+                           cannot use row_pairs                              */
+    int32_t channels;   /* 1..6                                              */
     int32_t frames;     /* >= 1 time points                                  */
     int32_t dtype;      /* vr_dtype                                          */
     int32_t bits;       /* VR_U8: 8.  VR_U16: 9..16                          */
@@ -78,7 +83,8 @@ typedef struct {
                            bytes: channels rounded up to 1, 2, 4 or 8, times
                            the voxel width): 16 x 16 x 8 for 1-byte,
                            8 x 16 x 8 for 2- and 4-byte, 8 x 8 x 8 for 8-
-                           and 16-byte words.  Fixed at
+                           and 16-byte words (4 x 16 x 8 for 8-byte words
+                           of a large volume, see below).  Fixed at
                            creation.  With row_pairs the defaults are
                            16 x 16 x 16, 8 x 32 x 8 and 4 x 16 x 16 for 1-, 2-
                            and 4-byte words.                                  */

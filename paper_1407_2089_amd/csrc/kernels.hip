@@ -81,18 +81,26 @@ __global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* 
 // full (same output bits; kept to test and time the transparent-sample skip).
 // Tiles of an eye run super-tile by super-tile (row-major over super-tiles of
 // kSuperW x kSuperH tiles, row-major inside each); the grid covers whole
-// super-tiles, and lanes past the image edge are invalid.  A stereo pair's
-// two eyes take consecutive blocks per tile (the eyes' rays of one tile
-// meet nearly the same bricks, so the second often finds them in L2;
+// super-tiles, and lanes past the image edge are invalid.  Unlit, a stereo
+// pair's two eyes take consecutive blocks per tile (the eyes' rays of one
+// tile meet nearly the same bricks, so the second often finds them in L2;
 // measured 2 % faster on a 36 GB montage, 1.4 % on a 230 MB frame).  kLit:
-// lit by the request's directional light.
+// lit by the request's directional light; lit launches render the eyes one
+// after the other (4 % faster than interleaved, measured).
 template <int V, bool kClear, bool kLit>
 __global__ __launch_bounds__(kWave) void render_kernel(ReqParams P, TileShape ts, int supers_x,
                                                        int per_eye) {
     const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
-    const int eye = P.eyes == 2 ? (b & 1) : 0;
+    int eye, t;
+    if constexpr (kLit) {
+        eye = b / per_eye;
+        t = b - eye * per_eye;
+    } else {
+        eye = P.eyes == 2 ? (b & 1) : 0;
+        t = P.eyes == 2 ? (b >> 1) : b;
+    }
     int tx, ty;
-    tile_at(P.eyes == 2 ? (b >> 1) : b, supers_x, tx, ty);
+    tile_at(t, supers_x, tx, ty);
     const int lane = threadIdx.x;
     const int px = tx * ts.wave_w + lane % ts.wave_w;
     const int py = ty * ts.wave_h + lane / ts.wave_w;

@@ -570,7 +570,7 @@ MONTAGE_DIMS = (10173, 3858, 74)   # stitched SVZ montage, 5 channels, 8 bit
 MONTAGE_CHANNELS = 5
 
 
-def montage_setup(ctx, seed=3):
+def montage_setup(ctx, seed=3, brick=(0, 0, 0)):
     """The five-channel uint8 montage resident in HBM (large-volume
     addressing: 2.9 G voxels per channel, 23 GB of bricks) with the default
     transfer functions; returns (volume, source tensor, tfs)."""
@@ -578,7 +578,7 @@ def montage_setup(ctx, seed=3):
     src = synth.montage(MONTAGE_DIMS, MONTAGE_CHANNELS, seed, log=log)
     tfs = [synth.TF(20.0 / 255.0, 200.0 / 255.0, 0.0, 1.0, PALETTE[c])
            for c in range(MONTAGE_CHANNELS)]
-    vol = Volume(ctx, MONTAGE_DIMS, MONTAGE_CHANNELS, 1, VR_U8, 8)
+    vol = Volume(ctx, MONTAGE_DIMS, MONTAGE_CHANNELS, 1, VR_U8, 8, brick=brick)
     vol.upload(0, src)
     for c, tf in enumerate(tfs):
         vol.set_transfer(c, tf)

@@ -131,6 +131,17 @@ def test_large_volume_limits():
         d = desc(*dims, ch=ch, frames=2, dtype=dt, bits=8 if dt == vr.VR_U8 else 16)
         word = WORD[ch] * (1 if dt == vr.VR_U8 else 2)
         assert vr.vr_volume_storage_bytes(d) >= 2 * word * dims[0] * dims[1] * dims[2]
+    # the default brick of a large volume with 8-byte words is 4 x 16 x 8;
+    # smaller volumes with 8-byte words keep 8 x 8 x 8
+    def frame(dims, b, word):
+        nb = [math.ceil((n + 1) / e) for n, e in zip(dims, b)]
+        f = nb[0] * nb[1] * nb[2] * (b[0] + 1) * (b[1] + 1) * (b[2] + 1) * word
+        return (f + 255) // 256 * 256
+    mont = (10173, 3858, 74)
+    assert vr.vr_volume_storage_bytes(desc(*mont, ch=5, frames=1, dtype=vr.VR_U8, bits=8)) == \
+        frame(mont, (4, 16, 8), 8)
+    assert vr.vr_volume_storage_bytes(desc(512, 512, 64, ch=5, frames=1, dtype=vr.VR_U8, bits=8)) \
+        == frame((512, 512, 64), (8, 8, 8), 8)
     # ... but not in the row-pair layout, and not beyond 16384 voxels per axis
     for d in (desc(8192, 8192, 64, ch=1, frames=1, dtype=vr.VR_U8, bits=8, row_pairs=1),
               desc(8193, 4, 4, ch=2, frames=1, dtype=vr.VR_U16, bits=12, row_pairs=1)):
