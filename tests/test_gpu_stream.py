@@ -60,10 +60,20 @@ def render_all(ctx, vol, frames, slots, cams, W, H, stream, host=None, staging=N
     return outs, smps
 
 
-@pytest.mark.parametrize("ch,bits,pairs,slots,halves", [(2, 12, True, 2, 1), (2, 12, True, 2, 2),
-                                                       (4, 8, False, 3, 2), (1, 8, True, 2, 1),
-                                                       (3, 16, False, 4, 2)])
-def test_streamed_playback_equals_resident(ctx, ch, bits, pairs, slots, halves):
+@pytest.mark.parametrize("ch,bits,pairs,slots,halves,large", [
+    (2, 12, True, 2, 1, False), (2, 12, True, 2, 2, False), (4, 8, False, 3, 2, False),
+    (1, 8, True, 2, 1, False), (3, 16, False, 4, 2, False), (5, 8, False, 3, 2, True)])
+def test_streamed_playback_equals_resident(ctx, ch, bits, pairs, slots, halves, large):
+    # large: both volumes take the large-volume addressing (test hook)
+    import torch
+    vr.vr_test_large_addressing(ctx.ptr, large)
+    try:
+        _streamed_playback(ctx, ch, bits, pairs, slots, halves)
+    finally:
+        vr.vr_test_large_addressing(ctx.ptr, False)
+
+
+def _streamed_playback(ctx, ch, bits, pairs, slots, halves):
     import torch
     dims, F = (96, 80, 40), 7
     W, H = 160, 120
