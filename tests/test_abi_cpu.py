@@ -343,12 +343,12 @@ def test_block_map_is_a_permutation_that_deals_super_tiles_to_xcds():
         assert np.array_equal(np.sort(m), np.arange(n)), n
     n = 8 * R * 2 + 5
     m = vr.vr_test_block_map(n)
-    # Round 0: XCD x takes positions R x .. R x + R - 1 as its blocks 0..R-1.
+    # First deal of runs: XCD x takes positions R x .. R x + R - 1 as its blocks 0..R-1.
     for xcd in range(8):
         blocks = np.arange(xcd, 8 * R * 8, 8)[:R]
         assert list(m[blocks]) == list(range(R * xcd, R * xcd + R))
     assert list(m[8 * R * 2:]) == list(range(8 * R * 2, n))  # the tail keeps its order
-    # Work spread: every XCD holds positions from every round of 8 runs.
+    # Work spread: every XCD holds positions from every deal of 8 runs.
     m = vr.vr_test_block_map(8 * R * 10)
     for xcd in range(8):
         rounds = set((m[np.arange(xcd, 8 * R * 10, 8)] // (8 * R)).tolist())
