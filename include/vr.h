@@ -69,8 +69,7 @@ typedef struct {
                            8192, or a frame of 2^31 stored words or 4 GiB
                            and more, is large: its kernels address taps with
                            64-bit offsets and step rays in FP64 (at most
-                           2^32 bricks and 2^44 bytes per frame), and it
-                           cannot use row_pairs                              */
+                           2^32 bricks and 2^44 bytes per frame)             */
     int32_t channels;   /* 1..6                                              */
     int32_t frames;     /* >= 1 time points                                  */
     int32_t dtype;      /* vr_dtype                                          */
@@ -90,7 +89,10 @@ typedef struct {
                            and 4-byte words.                                  */
     int32_t row_pairs;  /* 0: default layout.  1: store each brick row next to
                            the row after it (voxel words of 1, 2 or 4 bytes:
-                           up to 4 channels of uint8 or 2 of uint16), so the
+                           up to 4 channels of uint8 or 2 of uint16; in a
+                           large volume also 8-byte words, whose plane taps
+                           then take two 16-byte loads; vr_create_volume
+                           refuses 8-byte pairs otherwise), so the
                            four taps of
                            a sample in one brick plane are consecutive words:
                            a sample takes two 16-byte loads instead of four

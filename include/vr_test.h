@@ -40,8 +40,8 @@ vr_status vr_test_clear_skip(vr_ctx* ctx, int32_t on);
  * large-volume addressing (64-bit byte offsets, FP64 ray set-up and sample
  * positions) that volumes with an axis above 8192 voxels or a frame of 2^31
  * stored words or 4 GiB and more always use, so that path can be compared
- * with the oracle on small volumes; such volumes refuse row pairs.  on = 0
- * (the default) restores the choice by size. */
+ * with the oracle on small volumes (row pairs of 8-byte words included).
+ * on = 0 (the default) restores the choice by size. */
 vr_status vr_test_large_addressing(vr_ctx* ctx, int32_t on);
 
 /* Transparent-sample threshold of one channel with floor lo and ceiling hi

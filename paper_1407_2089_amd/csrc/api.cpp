@@ -138,10 +138,10 @@ vr_status check_desc(const vr_volume_desc* d) {
     if (!finite3(d->origin)) return fail(VR_ERR_INVALID_ARG, "origin must be finite");
     if (d->row_pairs != 0 && d->row_pairs != 1)
         return fail(VR_ERR_INVALID_ARG, "row_pairs = %d is neither 0 nor 1", d->row_pairs);
-    if (d->row_pairs && word_bytes(d->channels, d->dtype == VR_U16) > 4)
+    if (d->row_pairs && word_bytes(d->channels, d->dtype == VR_U16) > max_pair_word(true))
         return fail(VR_ERR_INVALID_ARG,
-                    "row pairs need voxel words of at most 4 bytes (at most 4 uint8 or 2 uint16 "
-                    "channels)");
+                    "row pairs need voxel words of at most 8 bytes (at most 6 uint8 or 4 uint16 "
+                    "channels; 8-byte words only in large volumes)");
     const bool dflt = d->brick[0] == 0 && d->brick[1] == 0 && d->brick[2] == 0;
     if (!dflt)
         for (int a = 0; a < 3; ++a)
@@ -155,11 +155,6 @@ vr_status check_desc(const vr_volume_desc* d) {
         __builtin_mul_overflow(g.frame_bytes, (uint64_t)d->frames, &total))
         return fail(VR_ERR_INVALID_ARG, "one frame needs %llu bricks, %llu bytes (limits 2^32, 2^44)",
                     (unsigned long long)bricks, (unsigned long long)g.frame_bytes);
-    if (d->row_pairs && needs_large(*d, g))
-        return fail(VR_ERR_INVALID_ARG,
-                    "row pairs need axes of at most %d voxels and frames below 2^31 stored voxels "
-                    "and 4 GiB",
-                    kFloatAxis);
     return VR_OK;
 }
 
@@ -545,8 +540,12 @@ vr_status vr_create_volume(vr_ctx* ctx, const vr_volume_desc* desc, void* dev_st
         return fail(VR_ERR_OUT_OF_MEMORY, "storage holds %llu bytes, the volume needs %llu",
                     (unsigned long long)storage_bytes, (unsigned long long)need);
     const bool large = needs_large(*desc, g) || ctx->force_large;
-    if (large && desc->row_pairs)
-        return fail(VR_ERR_INVALID_ARG, "row pairs are not available with large-volume addressing");
+    if (desc->row_pairs &&
+        word_bytes(desc->channels, desc->dtype == VR_U16) > max_pair_word(large))
+        return fail(VR_ERR_INVALID_ARG,
+                    "row pairs of 8-byte voxel words need a large volume (an axis above %d "
+                    "voxels, or a frame of 2^31 stored voxels or 4 GiB)",
+                    kFloatAxis);
     uint64_t used = ctx->used.load();
     do {
         if (used + need > ctx->budget)

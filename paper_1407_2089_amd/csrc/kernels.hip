@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void debug_sample_kernel(ReqParams P, const fl
         using T = typename WordT<C, Variant<V>::U16>::T;
         const SamplerL S = make_sampler_large(P);
         interpolate<C, Variant<V>::U16, Variant<V>::F16>(
-            fetch<T, false>(P.g, S, (double)pts[3 * i] + 1.0, (double)pts[3 * i + 1] + 1.0,
+            fetch<T, Variant<V>::PAIRS>(P.g, S, (double)pts[3 * i] + 1.0, (double)pts[3 * i + 1] + 1.0,
                             (double)pts[3 * i + 2] + 1.0), x);
     } else {
         const Sampler S = make_sampler(P.vox, P.g);

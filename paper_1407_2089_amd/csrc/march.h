@@ -228,6 +228,32 @@ template <typename T> __device__ __forceinline__ T load_global(const uint8_t* p)
     }
 }
 
+// Four consecutive words of the row-pair layout through global loads (the
+// first word has an even index, so the run is 2 W-aligned): two aligned loads
+// of 2 W bytes each.
+template <typename T> __device__ __forceinline__ Quad<T> load_quad_global(const uint8_t* p);
+template <> __device__ __forceinline__ Quad<uint8_t> load_quad_global<uint8_t>(const uint8_t* p) {
+    const uint16_t a = *(const VR_GLOBAL uint16_t*)p;
+    const uint16_t b = *(const VR_GLOBAL uint16_t*)(p + 2);
+    return Quad<uint8_t>{{(uint8_t)a, (uint8_t)(a >> 8), (uint8_t)b, (uint8_t)(b >> 8)}};
+}
+template <> __device__ __forceinline__ Quad<uint16_t> load_quad_global<uint16_t>(const uint8_t* p) {
+    const uint32_t a = *(const VR_GLOBAL uint32_t*)p;
+    const uint32_t b = *(const VR_GLOBAL uint32_t*)(p + 4);
+    return Quad<uint16_t>{{(uint16_t)a, (uint16_t)(a >> 16), (uint16_t)b, (uint16_t)(b >> 16)}};
+}
+template <> __device__ __forceinline__ Quad<uint32_t> load_quad_global<uint32_t>(const uint8_t* p) {
+    const u32x2_t a = *(const VR_GLOBAL u32x2_t*)p;
+    const u32x2_t b = *(const VR_GLOBAL u32x2_t*)(p + 8);
+    return Quad<uint32_t>{{a.x, a.y, b.x, b.y}};
+}
+template <> __device__ __forceinline__ Quad<uint2> load_quad_global<uint2>(const uint8_t* p) {
+    const u32x4_t a = *(const VR_GLOBAL u32x4_t*)p;
+    const u32x4_t b = *(const VR_GLOBAL u32x4_t*)(p + 16);
+    return Quad<uint2>{{make_uint2(a.x, a.y), make_uint2(a.z, a.w), make_uint2(b.x, b.y),
+                        make_uint2(b.z, b.w)}};
+}
+
 // The 2x2x2 taps around one sample point, in flight or landed.
 template <typename T> struct Taps {
     T w000, w100, w010, w110, w001, w101, w011, w111;
@@ -303,7 +329,6 @@ __device__ __forceinline__ Taps<T> fetch(const BrickGeom& g, const Sampler& S, f
 template <typename T, bool PAIRS>
 __device__ __forceinline__ Taps<T> fetch(const BrickGeom& g, const SamplerL& S, double qx,
                                          double qy, double qz) {
-    static_assert(!PAIRS, "large volumes have no row-pair layout");
     Taps<T> t;
     const double p[3] = {qx, qy, qz};
     float f[3];
@@ -322,9 +347,23 @@ __device__ __forceinline__ Taps<T> fetch(const BrickGeom& g, const SamplerL& S, 
     const uint32_t by = s[1] >> g.shift[1], ly = s[1] & ((1u << g.shift[1]) - 1u);
     const uint32_t bz = s[2] >> g.shift[2], lz = s[2] & ((1u << g.shift[2]) - 1u);
     const uint32_t brick = (bz * (uint32_t)g.nb[1] + by) * (uint32_t)g.nb[0] + bx;
-    const uint32_t local = lz * (uint32_t)g.plane + ly * (uint32_t)g.row + lx;
+    const uint32_t local = lz * (uint32_t)g.plane + ly * (uint32_t)g.row + (PAIRS ? lx << 1 : lx);
     constexpr uint32_t W = sizeof(T);
     const uint8_t* b = S.vox + ((uint64_t)brick * (uint32_t)g.brick + local) * W;
+    if constexpr (PAIRS) {
+        // Words (x, y), (x, y + 1), (x + 1, y), (x + 1, y + 1) of each plane.
+        const Quad<T> a = load_quad_global<T>(b);
+        const Quad<T> c = load_quad_global<T>(b + S.plane_b);
+        t.w000 = a.w[0];
+        t.w010 = a.w[1];
+        t.w100 = a.w[2];
+        t.w110 = a.w[3];
+        t.w001 = c.w[0];
+        t.w011 = c.w[1];
+        t.w101 = c.w[2];
+        t.w111 = c.w[3];
+        return t;
+    }
     const uint8_t* r = b + S.row_b;
     const uint8_t* z = b + S.plane_b;
     const uint8_t* rz = b + S.diag_b;

@@ -15,19 +15,19 @@ constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kBlockThreads = 256;
 
 // Data variant of a request: channels (1..6), voxel width, sample precision
-// and storage layout.  Index = (channels - 1) + 6 u16 + 12 fp16 + 24 pairs,
-// or + 48 for a large volume (an axis above 8192 voxels or a frame of 2^31
-// words or 4 GiB and more: 64-bit addresses and FP64 ray positions; never
-// row pairs).
-constexpr int kVariants = 72;
+// and storage layout.  Index = (channels - 1) + 6 u16 + 12 fp16 + 24 pairs
+// + 48 large, where large marks a large volume (an axis above 8192 voxels or
+// a frame of 2^31 words or 4 GiB and more: 64-bit addresses and FP64 ray
+// positions).
+constexpr int kVariants = 96;
 inline constexpr int variant_index(int channels, bool u16, bool fp16, bool pairs,
                                    bool large = false) {
-    return (channels - 1) + (u16 ? 6 : 0) + (fp16 ? 12 : 0) + (large ? 48 : pairs ? 24 : 0);
+    return (channels - 1) + (u16 ? 6 : 0) + (fp16 ? 12 : 0) + (pairs ? 24 : 0) + (large ? 48 : 0);
 }
 inline constexpr int variant_channels(int v) { return v % 6 + 1; }
 inline constexpr bool variant_u16(int v) { return (v / 6) % 2 != 0; }
 inline constexpr bool variant_fp16(int v) { return (v / 12) % 2 != 0; }
-inline constexpr bool variant_pairs(int v) { return v >= 24 && v < 48; }
+inline constexpr bool variant_pairs(int v) { return (v / 24) % 2 != 0; }
 inline constexpr bool variant_large(int v) { return v >= 48; }
 // Variants that the batched launch serves (large ones take plain launches).
 constexpr int kBatchVariants = 48;
@@ -45,9 +45,14 @@ inline constexpr int word_bytes(int channels, bool u16) {
 
 // The row-pair layout exists for 1-, 2- and 4-byte words: a plane's four
 // taps are then two aligned 2-byte loads, one 8-byte or one 16-byte load.
-// (8- and 16-byte words already take 16-byte loads without pairs.)
+// 8-byte words already take 16-byte loads without pairs and lose by pairs on
+// densely sampled frames (cache footprint); only large volumes, usually seen
+// undersampled, where a sample's fabric traffic counts more than its cache
+// footprint, offer pairs of 8-byte words too (a plane's taps: 32 bytes).
+inline constexpr int max_pair_word(bool large) { return large ? 8 : 4; }
 inline constexpr bool variant_exists(int v) {
-    return !variant_pairs(v) || word_bytes(variant_channels(v), variant_u16(v)) <= 4;
+    return !variant_pairs(v) ||
+           word_bytes(variant_channels(v), variant_u16(v)) <= max_pair_word(variant_large(v));
 }
 
 // Brick-major layout of one frame.  Stored coordinates s = i + 1 run over

@@ -85,11 +85,29 @@ def test_storage_bytes_of_the_row_pair_layout(dims, ch, dtype, brick):
 
 
 @pytest.mark.parametrize("ch,dtype,bits,row_pairs", [
-    (2, vr.VR_U16, 12, 2), (4, vr.VR_U8, 8, -1), (3, vr.VR_U16, 16, 1), (4, vr.VR_U16, 12, 1),
-    (5, vr.VR_U8, 8, 1), (6, vr.VR_U16, 12, 1)])
-def test_row_pairs_need_words_of_at_most_4_bytes_and_a_flag(ch, dtype, bits, row_pairs):
+    (2, vr.VR_U16, 12, 2), (4, vr.VR_U8, 8, -1), (5, vr.VR_U16, 16, 1), (6, vr.VR_U16, 12, 1)])
+def test_row_pairs_need_words_of_at_most_8_bytes_and_a_flag(ch, dtype, bits, row_pairs):
     with pytest.raises(vr.VrError):
         vr.vr_volume_storage_bytes(desc(ch=ch, dtype=dtype, bits=bits, row_pairs=row_pairs))
+
+
+@pytest.mark.parametrize("ch,dtype,bits", [(3, vr.VR_U16, 16), (4, vr.VR_U16, 12),
+                                           (5, vr.VR_U8, 8), (6, vr.VR_U8, 8)])
+def test_row_pairs_of_8_byte_words_need_a_large_volume(ch, dtype, bits):
+    ctx = vr.vr_init(-1, 1 << 40)
+    try:
+        d = desc(ch=ch, dtype=dtype, bits=bits, row_pairs=1, frames=1)
+        n = vr.vr_volume_storage_bytes(d)  # sized like any pair layout
+        with pytest.raises(vr.VrError, match="need a large volume") as e:
+            vr.vr_create_volume(ctx, d, FAKE, n)
+        assert e.value.status == vr.VR_ERR_INVALID_ARG
+        vr.vr_test_large_addressing(ctx, True)
+        vr.vr_destroy_volume(vr.vr_create_volume(ctx, d, FAKE, n))
+        vr.vr_test_large_addressing(ctx, False)
+        big = desc(16384, 8, 8, ch=ch, dtype=dtype, bits=bits, row_pairs=1, frames=1)
+        vr.vr_destroy_volume(vr.vr_create_volume(ctx, big, FAKE, vr.vr_volume_storage_bytes(big)))
+    finally:
+        vr.vr_shutdown(ctx)
 
 
 @pytest.mark.parametrize("ch,dtype,bits,brick", [
@@ -142,12 +160,10 @@ def test_large_volume_limits():
         frame(mont, (4, 16, 8), 8)
     assert vr.vr_volume_storage_bytes(desc(512, 512, 64, ch=5, frames=1, dtype=vr.VR_U8, bits=8)) \
         == frame((512, 512, 64), (8, 8, 8), 8)
-    # ... but not in the row-pair layout, and not beyond 16384 voxels per axis
+    # row pairs too; not beyond 16384 voxels per axis
     for d in (desc(8192, 8192, 64, ch=1, frames=1, dtype=vr.VR_U8, bits=8, row_pairs=1),
               desc(8193, 4, 4, ch=2, frames=1, dtype=vr.VR_U16, bits=12, row_pairs=1)):
-        with pytest.raises(vr.VrError, match="row pairs") as e:
-            vr.vr_volume_storage_bytes(d)
-        assert e.value.status == vr.VR_ERR_INVALID_ARG
+        assert vr.vr_volume_storage_bytes(d) > 0
     for dims in ((16385, 4, 4), (4, 16385, 4), (4, 4, 16385)):
         with pytest.raises(vr.VrError, match="1..16384") as e:
             vr.vr_volume_storage_bytes(desc(*dims))
@@ -216,14 +232,13 @@ def expect(status, fn, *a):
 
 
 def test_large_addressing_hook(vctx):
-    # forced large-volume addressing refuses row pairs; without it they work;
-    # a large volume's requests pass validation like any other
+    # forced large-volume addressing takes row pairs as well; a large
+    # volume's requests pass validation like any other
     d = desc(frames=1, row_pairs=1)
     n = vr.vr_volume_storage_bytes(d)
     vr.vr_test_large_addressing(vctx, True)
     try:
-        msg = expect(vr.VR_ERR_INVALID_ARG, vr.vr_create_volume, vctx, d, FAKE, n)
-        assert "row pairs" in msg
+        vr.vr_destroy_volume(vr.vr_create_volume(vctx, d, FAKE, n))
         v = vr.vr_create_volume(vctx, desc(frames=1), FAKE, n * 4)
         expect(vr.VR_ERR_UNSUPPORTED, vr.vr_render, vctx, good_request(v))
         vr.vr_destroy_volume(v)

@@ -42,10 +42,17 @@ def same_bits(a, b):
     return np.array_equal(np.asarray(a).view(np.uint32), np.asarray(b).view(np.uint32))
 
 
-def large_volume(ctx, sc, brick=(0, 0, 0)):
+WORD = {1: 1, 2: 2, 3: 4, 4: 4, 5: 8, 6: 8}   # bytes per voxel word of uint8 channels
+
+
+def word_bytes(ch, dtype):
+    return WORD[ch] * (2 if dtype == np.uint16 else 1)
+
+
+def large_volume(ctx, sc, brick=(0, 0, 0), row_pairs=False):
     vr.vr_test_large_addressing(ctx.ptr, True)
     try:
-        return gpu.make_volume(ctx, sc, brick)
+        return gpu.make_volume(ctx, sc, brick, row_pairs=row_pairs)
     finally:
         vr.vr_test_large_addressing(ctx.ptr, False)
 
@@ -67,10 +74,13 @@ VARIANTS = [(ch, dt, bits, prec) for ch in range(1, 7)
             for prec in (vr.VR_FP32, vr.VR_FP16)]
 
 
+@pytest.mark.parametrize("pairs", [False, True])
 @pytest.mark.parametrize("lit", [False, True])
 @pytest.mark.parametrize("ch,dtype,bits,precision", VARIANTS)
-def test_every_large_variant_matches_the_oracle(ctx, ch, dtype, bits, precision, lit):
-    log(f"large variant ch {ch} {dtype.__name__}-{bits} prec {precision} lit {lit}")
+def test_every_large_variant_matches_the_oracle(ctx, ch, dtype, bits, precision, lit, pairs):
+    if pairs and word_bytes(ch, dtype) > 8:
+        pytest.skip("row pairs exist for voxel words of at most 8 bytes")
+    log(f"large variant ch {ch} {dtype.__name__}-{bits} prec {precision} lit {lit} pairs {pairs}")
     dims = (52, 44, 30)
     data = synth.cells_and_vessels(dims, ch, bits, 60 + ch, n_cells=8, n_tubes=3)
     rng = np.random.default_rng(ch * 10 + bits)
@@ -83,7 +93,7 @@ def test_every_large_variant_matches_the_oracle(ctx, ch, dtype, bits, precision,
     if lit:
         sc.light = Light(tuple(float(x) for x in rng.normal(size=3)), 0.3, 0.7)
     tol = TOL16 if precision == vr.VR_FP16 else TOL32
-    v = large_volume(ctx, sc)
+    v = large_volume(ctx, sc, row_pairs=pairs)
     try:
         rgba, smp = render_both_skips(ctx, sc, precision, v)
     finally:
@@ -95,16 +105,18 @@ def test_every_large_variant_matches_the_oracle(ctx, ch, dtype, bits, precision,
 
 @pytest.mark.parametrize("seed", range(64))
 def test_large_random_configuration_against_the_oracle(ctx, seed):
-    # the seeded random configurations of the 32-bit path (row pairs off);
-    # every fourth one lit
+    # the seeded random configurations of the 32-bit path (their row-pair
+    # choice; 8-byte words take pairs on even seeds); every fourth one lit
     from test_gpu_random import random_case
-    sc, brick, _, precision = random_case(seed)
+    sc, brick, pairs, precision = random_case(seed)
+    if word_bytes(sc.volume.shape[0], sc.volume.dtype) == 8 and seed % 2 == 0:
+        pairs = True
     if seed % 4 == 3:
         rng = np.random.default_rng(1300 + seed)
         sc.light = Light(tuple(float(x) for x in rng.normal(size=3)),
                          float(rng.uniform(0, 1)), float(rng.uniform(0, 1)))
     tol = TOL16 if precision == vr.VR_FP16 else TOL32
-    v = large_volume(ctx, sc, brick)
+    v = large_volume(ctx, sc, brick, row_pairs=pairs)
     try:
         rgba, smp = render_both_skips(ctx, sc, precision, v)
     finally:
@@ -112,13 +124,14 @@ def test_large_random_configuration_against_the_oracle(ctx, seed):
     gpu.compare(rgba, smp, orc.render_all(sc, band_eps=tol), tol)
 
 
-def test_large_sampler_reproduces_a_linear_field(ctx):
+@pytest.mark.parametrize("pairs", [False, True])
+def test_large_sampler_reproduces_a_linear_field(ctx, pairs):
     # trilinear interpolation of a linear field is exact up to FP32 rounding
     import torch
     nx, ny, nz = 37, 29, 23
     vol = scenes.linear_field(nx, ny, nz)
     sc = Scene("lin", vol, 16, [TF()], None, 1, 1, False, 1.0, 1.0)
-    v = large_volume(ctx, sc)
+    v = large_volume(ctx, sc, row_pairs=pairs)
     try:
         rng = np.random.default_rng(5)
         pts = rng.uniform([-1, -1, -1], [nx, ny, nz], size=(4096, 3)).astype(np.float32)
