@@ -14,62 +14,119 @@
 namespace vr {
 
 // ------------------------------------------------------------- relayout
-// One thread per stored word of the frame: gathers the word's channels from
-// the linear [C][Z][Y][X] source (zero outside the grid), clamps them to the
-// declared bit depth and packs them side by side.  In the row-pair layout a
-// word's brick-local row is its pair's row plus the word's parity.
+// One thread per stored position (sx, sy, sz) of the frame, stored
+// coordinate s = voxel index + 1 over [0, nb B] per axis: it reads the
+// voxel's channels from the linear [C][Z][Y][X] source (zero outside the
+// grid; consecutive threads read consecutive x), clamps them to the declared
+// bit depth, packs them into one word and writes every copy of that word.
+// Per axis a position is local s mod B of brick s / B (if that brick
+// exists) and, when s is a nonzero multiple of B, also the high-side halo
+// (local B) of brick s / B - 1; in the row-pair layout a local row ly is the
+// first word of pair row ly (ly < By) and the second of pair row ly - 1
+// (ly >= 1).  Each stored word of the frame is written by exactly one
+// thread.  Grid: x over positions, y and z one block row per position.
+template <int C, bool U16> __device__ __forceinline__ typename WordT<C, U16>::T pack_word(
+    const uint32_t (&ch)[kMaxChannels]) {
+    using T = typename WordT<C, U16>::T;
+    if constexpr (!U16) {
+        if constexpr (C == 1) return (T)ch[0];
+        else if constexpr (C == 2) return (T)(ch[0] | (ch[1] << 8));
+        else if constexpr (C <= 4) return (T)(ch[0] | (ch[1] << 8) | (ch[2] << 16) | (ch[3] << 24));
+        else return make_uint2(ch[0] | (ch[1] << 8) | (ch[2] << 16) | (ch[3] << 24),
+                               ch[4] | (ch[5] << 8));
+    } else {
+        if constexpr (C == 1) return (T)ch[0];
+        else if constexpr (C == 2) return (T)(ch[0] | (ch[1] << 16));
+        else if constexpr (C <= 4) return make_uint2(ch[0] | (ch[1] << 16), ch[2] | (ch[3] << 16));
+        else return make_uint4(ch[0] | (ch[1] << 16), ch[2] | (ch[3] << 16),
+                               ch[4] | (ch[5] << 16), 0u);
+    }
+}
+
+// Copies of stored position s along one axis: (brick, local) pairs.
+struct AxisCopies {
+    uint32_t brick[2], local[2];
+    int n;
+};
+__device__ __forceinline__ AxisCopies axis_copies(uint32_t s, int shift, uint32_t nb) {
+    AxisCopies a;
+    a.n = 0;
+    const uint32_t b = s >> shift, l = s & ((1u << shift) - 1u);
+    if (b < nb) {
+        a.brick[a.n] = b;
+        a.local[a.n] = l;
+        ++a.n;
+    }
+    if (l == 0 && b > 0) {
+        a.brick[a.n] = b - 1;
+        a.local[a.n] = 1u << shift;
+        ++a.n;
+    }
+    return a;
+}
+
+constexpr int kRelayoutThreads = 128;
+
 template <int C, bool U16>
-__global__ __launch_bounds__(256) void relayout_kernel(BrickGeom g, const void* __restrict__ src,
-                                                        uint8_t* __restrict__ dst, uint32_t maxval,
-                                                        uint64_t total_words) {
+__global__ __launch_bounds__(kRelayoutThreads) void relayout_kernel(
+    BrickGeom g, const void* __restrict__ src, uint8_t* __restrict__ dst, uint32_t maxval) {
     using T = typename WordT<C, U16>::T;
     using S = typename std::conditional<U16, uint16_t, uint8_t>::type;
-    const S* in = reinterpret_cast<const S*>(src);
-    T* out = reinterpret_cast<T*>(dst);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total_words; w += stride) {
-        const uint32_t brick = (uint32_t)(w / (uint32_t)g.brick);
-        const uint32_t rem = (uint32_t)(w - (uint64_t)brick * (uint32_t)g.brick);
-        const uint32_t lz = rem / (uint32_t)g.plane;
-        const uint32_t r2 = rem - lz * (uint32_t)g.plane;
-        const uint32_t lr = r2 / (uint32_t)g.row;
-        const uint32_t e = r2 - lr * (uint32_t)g.row;
-        const uint32_t ly = g.pairs ? lr + (e & 1u) : lr;
-        const uint32_t lx = g.pairs ? e >> 1 : e;
-        const uint32_t bx = brick % (uint32_t)g.nb[0];
-        const uint32_t byz = brick / (uint32_t)g.nb[0];
-        const uint32_t by = byz % (uint32_t)g.nb[1];
-        const uint32_t bz = byz / (uint32_t)g.nb[1];
-        // voxel index = stored coordinate - 1
-        const int i = (int)((bx << g.shift[0]) + lx) - 1;
-        const int j = (int)((by << g.shift[1]) + ly) - 1;
-        const int k = (int)((bz << g.shift[2]) + lz) - 1;
-        uint32_t ch[kMaxChannels] = {};
-        if (i >= 0 && j >= 0 && k >= 0 && i < g.n[0] && j < g.n[1] && k < g.n[2]) {
-            const size_t plane = (size_t)g.n[0] * g.n[1];
-            const size_t vol = plane * g.n[2];
-            const size_t base = (size_t)k * plane + (size_t)j * g.n[0] + i;
+    const uint32_t sx = blockIdx.x * kRelayoutThreads + threadIdx.x;
+    const uint32_t sy = blockIdx.y, sz = blockIdx.z;
+    if (sx > ((uint32_t)g.nb[0] << g.shift[0])) return;
+    const int i = (int)sx - 1, j = (int)sy - 1, k = (int)sz - 1;
+    uint32_t ch[kMaxChannels] = {};
+    if (i >= 0 && j >= 0 && k >= 0 && i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+        const S* in = reinterpret_cast<const S*>(src);
+        const size_t plane = (size_t)g.n[0] * g.n[1];
+        const size_t vol = plane * g.n[2];
+        const size_t base = (size_t)k * plane + (size_t)j * g.n[0] + i;
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                uint32_t v = in[(size_t)c * vol + base];
-                ch[c] = v > maxval ? maxval : v;
+        for (int c = 0; c < C; ++c) {
+            const uint32_t v = in[(size_t)c * vol + base];
+            ch[c] = v > maxval ? maxval : v;
+        }
+    }
+    const T word = pack_word<C, U16>(ch);
+    T* out = reinterpret_cast<T*>(dst);
+    const AxisCopies X = axis_copies(sx, g.shift[0], (uint32_t)g.nb[0]);
+    const AxisCopies Y = axis_copies(sy, g.shift[1], (uint32_t)g.nb[1]);
+    const AxisCopies Z = axis_copies(sz, g.shift[2], (uint32_t)g.nb[2]);
+    const uint32_t By = 1u << g.shift[1];
+    for (int zc = 0; zc < Z.n; ++zc) {
+        for (int yc = 0; yc < Y.n; ++yc) {
+            const uint32_t ly = Y.local[yc];
+            // (row, parity) slots of local row ly within the brick plane
+            uint32_t rows[2], par[2];
+            int nr = 0;
+            if (!g.pairs) {
+                rows[0] = ly;
+                par[0] = 0;
+                nr = 1;
+            } else {
+                if (ly < By) {
+                    rows[nr] = ly;
+                    par[nr] = 0;
+                    ++nr;
+                }
+                if (ly >= 1) {
+                    rows[nr] = ly - 1;
+                    par[nr] = 1;
+                    ++nr;
+                }
+            }
+            for (int xc = 0; xc < X.n; ++xc) {
+                const uint64_t brick =
+                    ((uint64_t)Z.brick[zc] * (uint32_t)g.nb[1] + Y.brick[yc]) * (uint32_t)g.nb[0] +
+                    X.brick[xc];
+                for (int r = 0; r < nr; ++r) {
+                    const uint32_t e = g.pairs ? 2u * X.local[xc] + par[r] : X.local[xc];
+                    const uint32_t local = Z.local[zc] * (uint32_t)g.plane + rows[r] * (uint32_t)g.row + e;
+                    out[brick * (uint32_t)g.brick + local] = word;
+                }
             }
         }
-        T word;
-        if constexpr (!U16) {
-            if constexpr (C == 1) word = (T)ch[0];
-            else if constexpr (C == 2) word = (T)(ch[0] | (ch[1] << 8));
-            else if constexpr (C <= 4) word = (T)(ch[0] | (ch[1] << 8) | (ch[2] << 16) | (ch[3] << 24));
-            else word = make_uint2(ch[0] | (ch[1] << 8) | (ch[2] << 16) | (ch[3] << 24),
-                                   ch[4] | (ch[5] << 8));
-        } else {
-            if constexpr (C == 1) word = (T)ch[0];
-            else if constexpr (C == 2) word = (T)(ch[0] | (ch[1] << 16));
-            else if constexpr (C <= 4) word = make_uint2(ch[0] | (ch[1] << 16), ch[2] | (ch[3] << 16));
-            else word = make_uint4(ch[0] | (ch[1] << 16), ch[2] | (ch[3] << 16),
-                                   ch[4] | (ch[5] << 16), 0u);
-        }
-        out[w] = word;
     }
 }
 
@@ -198,16 +255,18 @@ __global__ __launch_bounds__(256) void debug_sample_kernel(ReqParams P, const fl
 
 hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
                            const void* src, uint8_t* dst, hipStream_t s) {
-    const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
+    // stored positions 0 .. nb B per axis
+    const uint32_t NX = ((uint32_t)g.nb[0] << g.shift[0]) + 1u;
+    const uint32_t NY = ((uint32_t)g.nb[1] << g.shift[1]) + 1u;
+    const uint32_t NZ = ((uint32_t)g.nb[2] << g.shift[2]) + 1u;
+    if (NY > 65535u || NZ > 65535u) return hipErrorInvalidValue;
     const uint32_t maxval = (1u << bits) - 1u;
-    uint64_t blocks64 = (words + 255) / 256;
-    const unsigned blocks = (unsigned)(blocks64 > 65536 ? 65536 : blocks64);
-    if (words == 0) return hipSuccess;
-#define VR_RL(C, U)                                                                      \
-    if (channels == C && u16 == U) {                                                     \
-        hipLaunchKernelGGL((relayout_kernel<C, U>), dim3(blocks), dim3(256), 0, s, g, src, \
-                           dst, maxval, words);                                          \
-        return hipGetLastError();                                                        \
+    const dim3 grid((NX + kRelayoutThreads - 1) / kRelayoutThreads, NY, NZ);
+#define VR_RL(C, U)                                                                     \
+    if (channels == C && u16 == U) {                                                    \
+        hipLaunchKernelGGL((relayout_kernel<C, U>), grid, dim3(kRelayoutThreads), 0, s, g, \
+                           src, dst, maxval);                                           \
+        return hipGetLastError();                                                       \
     }
     VR_RL(1, false) VR_RL(2, false) VR_RL(3, false) VR_RL(4, false) VR_RL(5, false)
     VR_RL(6, false) VR_RL(1, true) VR_RL(2, true) VR_RL(3, true) VR_RL(4, true)

@@ -578,8 +578,15 @@ def montage_setup(ctx, seed=3, brick=(0, 0, 0)):
     src = synth.montage(MONTAGE_DIMS, MONTAGE_CHANNELS, seed, log=log)
     tfs = [synth.TF(20.0 / 255.0, 200.0 / 255.0, 0.0, 1.0, PALETTE[c])
            for c in range(MONTAGE_CHANNELS)]
+    import torch
     vol = Volume(ctx, MONTAGE_DIMS, MONTAGE_CHANNELS, 1, VR_U8, 8, brick=brick)
-    vol.upload(0, src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    a.record(stream)
+    vol.upload(0, src, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    vol.relayout_ms = a.elapsed_time(b)
     for c, tf in enumerate(tfs):
         vol.set_transfer(c, tf)
     return vol, src, tfs
@@ -665,11 +672,15 @@ def montage(ctx, reps=10, W=1920, H=1080, cpu=None):
     word = 8   # five uint8 channels per voxel word
     eff = samples * 8 * word / (ms * 1e-3) / 1e9
     frame_bytes = vol.bytes
+    relayout_ms = vol.relayout_ms
     vol.destroy()
     return {"workload": "montage: 5ch u8 10173x3858x74 (one frame, 14.5 GB of voxels, "
                         f"{frame_bytes / 1e9:.1f} GB of bricks), stereo {W}x{H}, step 1.0, "
                         "tau 0.99, perspective elevation 55 deg",
             "frame_bytes": frame_bytes, "samples": samples, "ms_per_step": ms,
+            # upload: read 5 B per voxel, write the bricks
+            "relayout_ms": relayout_ms,
+            "relayout_GBps": (5 * 10173 * 3858 * 74 + frame_bytes) / (relayout_ms * 1e-3) / 1e9,
             "value": samples / (ms * 1e-3), "unit": "ray-samples/s",
             "roofline": {"bound": "hbm", "achieved": eff, "peak": 8000.0, "unit": "GB/s",
                          "frac": eff / 8000.0,
