@@ -14,7 +14,7 @@
 namespace vr {
 
 // ------------------------------------------------------------- relayout
-// One thread per stored position (sx, sy, sz) of the frame, stored
+// Scatter form: one thread per stored position (sx, sy, sz) of the frame, stored
 // coordinate s = voxel index + 1 over [0, nb B] per axis: it reads the
 // voxel's channels from the linear [C][Z][Y][X] source (zero outside the
 // grid; consecutive threads read consecutive x), clamps them to the declared
@@ -65,10 +65,61 @@ __device__ __forceinline__ AxisCopies axis_copies(uint32_t s, int shift, uint32_
     return a;
 }
 
+// Gather form, for bricks at least 8 voxels wide: one thread per stored word
+// (grid-stride), which finds its voxel and gathers the channels; a wave
+// writes 64 consecutive words and reads runs of Bx + 1 voxels.  In the
+// row-pair layout a word's brick-local row is its pair's row plus the word's
+// parity.  (Narrower bricks take the scatter form below: runs of 5 voxels
+// made the gather's reads 2.9x slower on a 4 x 16 x 8 brick frame, while
+// the scatter's short write runs cost it 1.4x on 8 x 16 x 8 bricks of
+// 4-byte words.)
+template <int C, bool U16>
+__global__ __launch_bounds__(256) void relayout_gather_kernel(BrickGeom g, const void* __restrict__ src,
+                                                        uint8_t* __restrict__ dst, uint32_t maxval,
+                                                        uint64_t total_words) {
+    using T = typename WordT<C, U16>::T;
+    using S = typename std::conditional<U16, uint16_t, uint8_t>::type;
+    const S* in = reinterpret_cast<const S*>(src);
+    T* out = reinterpret_cast<T*>(dst);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < total_words; w += stride) {
+        const uint32_t brick = (uint32_t)(w / (uint32_t)g.brick);
+        const uint32_t rem = (uint32_t)(w - (uint64_t)brick * (uint32_t)g.brick);
+        const uint32_t lz = rem / (uint32_t)g.plane;
+        const uint32_t r2 = rem - lz * (uint32_t)g.plane;
+        const uint32_t lr = r2 / (uint32_t)g.row;
+        const uint32_t e = r2 - lr * (uint32_t)g.row;
+        const uint32_t ly = g.pairs ? lr + (e & 1u) : lr;
+        const uint32_t lx = g.pairs ? e >> 1 : e;
+        const uint32_t bx = brick % (uint32_t)g.nb[0];
+        const uint32_t byz = brick / (uint32_t)g.nb[0];
+        const uint32_t by = byz % (uint32_t)g.nb[1];
+        const uint32_t bz = byz / (uint32_t)g.nb[1];
+        // voxel index = stored coordinate - 1
+        const int i = (int)((bx << g.shift[0]) + lx) - 1;
+        const int j = (int)((by << g.shift[1]) + ly) - 1;
+        const int k = (int)((bz << g.shift[2]) + lz) - 1;
+        uint32_t ch[kMaxChannels] = {};
+        if (i >= 0 && j >= 0 && k >= 0 && i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+            const size_t plane = (size_t)g.n[0] * g.n[1];
+            const size_t vol = plane * g.n[2];
+            const size_t base = (size_t)k * plane + (size_t)j * g.n[0] + i;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                uint32_t v = in[(size_t)c * vol + base];
+                ch[c] = v > maxval ? maxval : v;
+            }
+        }
+        const T word = pack_word<C, U16>(ch);
+        out[w] = word;
+    }
+}
+
+
 constexpr int kRelayoutThreads = 128;
 
 template <int C, bool U16>
-__global__ __launch_bounds__(kRelayoutThreads) void relayout_kernel(
+__global__ __launch_bounds__(kRelayoutThreads) void relayout_scatter_kernel(
     BrickGeom g, const void* __restrict__ src, uint8_t* __restrict__ dst, uint32_t maxval) {
     using T = typename WordT<C, U16>::T;
     using S = typename std::conditional<U16, uint16_t, uint8_t>::type;
@@ -262,11 +313,19 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
     if (NY > 65535u || NZ > 65535u) return hipErrorInvalidValue;
     const uint32_t maxval = (1u << bits) - 1u;
     const dim3 grid((NX + kRelayoutThreads - 1) / kRelayoutThreads, NY, NZ);
-#define VR_RL(C, U)                                                                     \
-    if (channels == C && u16 == U) {                                                    \
-        hipLaunchKernelGGL((relayout_kernel<C, U>), grid, dim3(kRelayoutThreads), 0, s, g, \
-                           src, dst, maxval);                                           \
-        return hipGetLastError();                                                       \
+    const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
+    const uint64_t blocks64 = (words + 255) / 256;
+    const unsigned gblocks = (unsigned)(blocks64 > 65536 ? 65536 : blocks64);
+    const bool gather = g.shift[0] >= 3;  // bricks at least 8 voxels wide
+#define VR_RL(C, U)                                                                       \
+    if (channels == C && u16 == U) {                                                      \
+        if (gather)                                                                       \
+            hipLaunchKernelGGL((relayout_gather_kernel<C, U>), dim3(gblocks), dim3(256), 0, s, \
+                               g, src, dst, maxval, words);                               \
+        else                                                                              \
+            hipLaunchKernelGGL((relayout_scatter_kernel<C, U>), grid, dim3(kRelayoutThreads), 0, s, g, \
+                               src, dst, maxval);                                         \
+        return hipGetLastError();                                                         \
     }
     VR_RL(1, false) VR_RL(2, false) VR_RL(3, false) VR_RL(4, false) VR_RL(5, false)
     VR_RL(6, false) VR_RL(1, true) VR_RL(2, true) VR_RL(3, true) VR_RL(4, true)
