@@ -71,9 +71,11 @@ typedef struct {
  * sgn(neighbour - voxel)), clamped to [0, 2^bits - 1]; the result is the last
  * image whose RMS distance to src is at most sigma (tested as
  * sum d^2 <= sigma^2 N in double), stopping early at a fixed point or after
- * max_iters (>= 0) iterations.  Runs on hip_stream and waits on it between
- * iterations (the stopping test reads device sums); returns when dst holds
- * the result.  src and dst must not overlap each other or the workspace. */
+ * max_iters (>= 0) iterations.  Runs on hip_stream and waits on it after
+ * every second iteration (the stopping test reads device sums; the second
+ * iteration of a pair runs before the first is judged, into the workspace,
+ * and is dropped if the first stops); returns when dst holds the result.
+ * src and dst must not overlap each other or the workspace. */
 vr_status vr_mrf_denoise(vr_ctx* ctx, const vr_grid* grid, int32_t max_iters, const void* src,
                          void* dst, void* workspace, uint64_t workspace_bytes, void* hip_stream,
                          vr_mrf_info* info);

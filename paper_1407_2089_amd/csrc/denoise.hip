@@ -624,27 +624,51 @@ vr_status run_mrf(const vr_grid& g, int max_iters, const T* src, T* dst, uint8_t
     const T* cur = src;
     int kept = 0;
     unsigned long long kept_ss = 0;
+    // One iteration: next = step(from) with its sums (squared distance to src,
+    // voxels changed) in sums[2 slot], sums[2 slot + 1].
+    auto step = [&](const T* from, T* next, int slot) {
+        const uintptr_t al = 4 * sizeof(T) - 1;
+        if (g.nx % 4 == 0 && !(((uintptr_t)from | (uintptr_t)src | (uintptr_t)next) & al))
+            hipLaunchKernelGGL(mrf_step_vec<T>, dim3(sblocks), dim3(kThreads), 0, s, from, src,
+                               next, d, delta, full, partial);
+        else
+            hipLaunchKernelGGL(mrf_step<T>, dim3(sblocks), dim3(kThreads), 0, s, from, src, next,
+                               d, delta, full, partial);
+        hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s,
+                           (const unsigned long long*)partial, sblocks, sums + 2 * slot);
+    };
     if (delta > 0) {
-        while (kept < max_iters) {
-            T* out = (kept % 2 == 0) ? dst : spare;
-            const uintptr_t al = 4 * sizeof(T) - 1;
-            if (g.nx % 4 == 0 && !(((uintptr_t)cur | (uintptr_t)src | (uintptr_t)out) & al))
-                hipLaunchKernelGGL(mrf_step_vec<T>, dim3(sblocks), dim3(kThreads), 0, s, cur, src,
-                                   out, d, delta, full, partial);
-            else
-                hipLaunchKernelGGL(mrf_step<T>, dim3(sblocks), dim3(kThreads), 0, s, cur, src,
-                                   out, d, delta, full, partial);
-            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kThreads), 0, s,
-                               (const unsigned long long*)partial, sblocks, sums);
+        // Two iterations per round trip to the host: the second runs before
+        // the first is judged, into a third buffer (the workspace's second
+        // volume), so the last accepted image survives a rejected second
+        // step.  The images kept and the counts are those of one iteration
+        // per round trip.
+        T* const bufs[3] = {dst, spare, (T*)(ws + vb)};
+        bool stop = false;
+        while (!stop && kept < max_iters) {
+            T* out[2];
+            int m = 0;
+            for (T* b : bufs)
+                if (b != cur && m < 2) out[m++] = b;
+            const int run = max_iters - kept >= 2 ? 2 : 1;
+            step(cur, out[0], 0);
+            if (run == 2) step(out[0], out[1], 1);
             if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "mrf step launch");
-            if ((e = hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            unsigned long long hs[4] = {0, 0, 0, 0};
+            if ((e = hipMemcpyAsync(hs, sums, sizeof(unsigned long long) * 2 * run,
+                                    hipMemcpyDeviceToHost, s)) != hipSuccess ||
                 (e = hipStreamSynchronize(s)) != hipSuccess)
                 return hip_fail(e, "mrf step sums");
-            if (h[1] == 0) break;  // fixed point
-            if (!((double)h[0] <= sigma * sigma * (double)n)) break;
-            cur = out;
-            kept += 1;
-            kept_ss = h[0];
+            for (int q = 0; q < run; ++q) {
+                const unsigned long long ss = hs[2 * q], changed = hs[2 * q + 1];
+                if (changed == 0 || !((double)ss <= sigma * sigma * (double)n)) {
+                    stop = true;  // fixed point, or past the noise bound
+                    break;
+                }
+                cur = out[q];
+                kept += 1;
+                kept_ss = ss;
+            }
         }
     }
     if (cur != dst) {

@@ -349,7 +349,13 @@ def denoise(ctx, reps=10, max_iters=500):
     t0 = time.perf_counter()
     info = vr_mrf_denoise(ctx.ptr, grid, max_iters, vol, mrf_dst, ws, ws_bytes, stream)
     wall = time.perf_counter() - t0
-    steps = info.iterations + (1 if info.iterations < max_iters else 0)  # the rejected step too
+    # steps computed: the kept ones, the rejected one and, when that one was
+    # the first of a pair, the pair's second (iterations run two per round
+    # trip to the host)
+    k = info.iterations
+    steps = k
+    if k < max_iters:
+        steps += 1 + (1 if k % 2 == 0 and k + 2 <= max_iters else 0)
     res["mrf"] = {"iterations": info.iterations, "steps_run": steps, "sigma": info.sigma,
                   "delta": info.delta, "rms": info.rms, "wall_ms": wall * 1e3,
                   "ms_per_step": wall * 1e3 / max(steps, 1),
