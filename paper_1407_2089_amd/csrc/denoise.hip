@@ -117,17 +117,20 @@ __global__ __launch_bounds__(kThreads) void lowpass_pass(const T* __restrict__ s
     // (unrolled so that several loads are in flight per thread)
     const int span = kOut + 2 * r;
     if (AXIS == 0) {
-        // a wave loads every fourth line, its lanes consecutive x of it
+        // a wave loads every fourth line, its lanes consecutive x of it, in
+        // three 64-voxel chunks aligned to the tile (x from a0 - 64 to
+        // a0 + 127, which holds a0 - r .. a0 + kOut + r - 1 for r <= 64):
+        // each wave load is one aligned 128-byte run instead of straddling
+        // two; the filter then starts at tile column 64 - r
         const int lane = tid & 63, wave = tid >> 6;
 #pragma unroll 4
         for (int l = wave; l < 64; l += kThreads / 64) {
             if (l >= lines_valid) break;
             const long long lb = base_of_line0 + l * line_stride;
 #pragma unroll
-            for (int row = lane; row < kOut + 2 * (kMaxTaps / 2); row += 64) {
-                if (row >= span) break;
-                const int a = min(max(a0 - r + row, 0), na - 1);
-                tile[l * kPitch + row] = src[lb + a];
+            for (int j = 0; j < 3; ++j) {
+                const int a = min(max(a0 - 64 + lane + 64 * j, 0), na - 1);
+                tile[l * kPitch + lane + 64 * j] = src[lb + a];
             }
         }
     } else {
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void lowpass_pass(const T* __restrict__ s
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
     uint32_t acc[kRun];
-    filter_run(tile + lane * kPitch + wave * kRun, k, acc);
+    filter_run(tile + lane * kPitch + (AXIS == 0 ? 64 - r : 0) + wave * kRun, k, acc);
     if (AXIS == 0) {
         // The lanes hold rows: stage the results in LDS and store them row
         // by row so that consecutive threads write consecutive x.
