@@ -44,8 +44,8 @@ struct Dims {
 constexpr int kOut = (kThreads / 64) * kRun;                // 64 outputs per line
 // A wave's run reads rows wave * kRun .. wave * kRun + padded + kRun - 1
 // (the last chunk's final row against no weight at all).
-constexpr int kRows = kOut + kPadTaps;                      // 208 rows
-constexpr int kPitch = kRows | 1;                            // odd pitch, 209
+constexpr int kRows = kOut + kPadTaps;                      // at most 208 rows
+static_assert(64 * (kRows | 1) * 4 <= 65536, "the largest tile fits a block's LDS");
 
 // acc += w * x with both factors below 2^24 (weights <= 2^16, voxels <= 2^16):
 // one full-rate v_mad_u32_u24 (left to itself the compiler pairs products
@@ -82,8 +82,11 @@ __device__ __forceinline__ void filter_run(const uint32_t* __restrict__ t, const
 // line_base maps a line index to its first element; n_lines lines exist.
 template <typename T, int AXIS>
 __global__ __launch_bounds__(kThreads) void lowpass_pass(const T* __restrict__ src,
-                                                         T* __restrict__ dst, Dims d, Axis1D k) {
-    __shared__ uint32_t tile[64 * kPitch];
+                                                         T* __restrict__ dst, Dims d, Axis1D k,
+                                                         int pitch) {
+    // 64 lines of `pitch` words (dynamic LDS, sized by the host to the
+    // rows this filter reads: more blocks per CU for shorter filters)
+    extern __shared__ uint32_t tile[];
     const int tid = threadIdx.x;
     const int r = (k.taps - 1) >> 1;
     // line geometry: length na along the axis, stride sa; lines indexed by
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void lowpass_pass(const T* __restrict__ s
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const int a = min(max(a0 - 64 + lane + 64 * j, 0), na - 1);
-                tile[l * kPitch + lane + 64 * j] = src[lb + a];
+                tile[l * pitch + lane + 64 * j] = src[lb + a];
             }
         }
     } else {
@@ -140,25 +143,25 @@ __global__ __launch_bounds__(kThreads) void lowpass_pass(const T* __restrict__ s
             const int row = i >> 6, l = i & 63;
             if (l >= lines_valid) continue;
             const int a = min(max(a0 - r + row, 0), na - 1);
-            tile[l * kPitch + row] = src[base_of_line0 + l + a * sa];
+            tile[l * pitch + row] = src[base_of_line0 + l + a * sa];
         }
     }
     __syncthreads();
     const int lane = tid & 63, wave = tid >> 6;
     uint32_t acc[kRun];
-    filter_run(tile + lane * kPitch + (AXIS == 0 ? 64 - r : 0) + wave * kRun, k, acc);
+    filter_run(tile + lane * pitch + (AXIS == 0 ? 64 - r : 0) + wave * kRun, k, acc);
     if (AXIS == 0) {
         // The lanes hold rows: stage the results in LDS and store them row
         // by row so that consecutive threads write consecutive x.
         __syncthreads();
 #pragma unroll
-        for (int m = 0; m < kRun; ++m) tile[lane * kPitch + wave * kRun + m] = acc[m] >> k.shift;
+        for (int m = 0; m < kRun; ++m) tile[lane * pitch + wave * kRun + m] = acc[m] >> k.shift;
         __syncthreads();
         for (int i = tid; i < 64 * kOut; i += kThreads) {
             const int l = i / kOut, o = i - l * kOut;
             const int a = a0 + o;
             if (l < lines_valid && a < na)
-                dst[base_of_line0 + l * line_stride + a] = (T)tile[l * kPitch + o];
+                dst[base_of_line0 + l * line_stride + a] = (T)tile[l * pitch + o];
         }
         return;
     }
@@ -589,12 +592,21 @@ hipError_t enqueue_background(const vr_grid& g, const Axis1D (&ax)[3], const T* 
     const long long bx = (long long)((g.nx + kOut - 1) / kOut) * ((g.ny * g.nz + 63) / 64);
     const long long by = (long long)((g.ny + kOut - 1) / kOut) * tx * g.nz;
     const long long bz = (long long)((g.nz + kOut - 1) / kOut) * tx * g.ny;
-    hipLaunchKernelGGL((lowpass_pass<T, 0>), dim3((unsigned)bx), dim3(kThreads), 0, s, src, t1,
-                       d, ax[0]);
-    hipLaunchKernelGGL((lowpass_pass<T, 1>), dim3((unsigned)by), dim3(kThreads), 0, s,
-                       (const T*)t1, t2, d, ax[1]);
-    hipLaunchKernelGGL((lowpass_pass<T, 2>), dim3((unsigned)bz), dim3(kThreads), 0, s,
-                       (const T*)t2, b, d, ax[2]);
+    // LDS rows per line: y and z read rows 0 .. kOut + padded - 1; x loads
+    // rows 0 .. 191 (aligned chunks) and reads from 64 - r on
+    int pitch[3];
+    for (int a = 0; a < 3; ++a) {
+        const int r = (ax[a].taps - 1) >> 1;
+        const int rows = a == 0 ? std::max(192, 128 - r + ax[a].padded) : kOut + ax[a].padded;
+        pitch[a] = rows | 1;
+    }
+    const auto lds = [&](int a) { return (unsigned)(64 * pitch[a] * sizeof(uint32_t)); };
+    hipLaunchKernelGGL((lowpass_pass<T, 0>), dim3((unsigned)bx), dim3(kThreads), lds(0), s, src,
+                       t1, d, ax[0], pitch[0]);
+    hipLaunchKernelGGL((lowpass_pass<T, 1>), dim3((unsigned)by), dim3(kThreads), lds(1), s,
+                       (const T*)t1, t2, d, ax[1], pitch[1]);
+    hipLaunchKernelGGL((lowpass_pass<T, 2>), dim3((unsigned)bz), dim3(kThreads), lds(2), s,
+                       (const T*)t2, b, d, ax[2], pitch[2]);
     const long long blocks = (long long)((g.nx + kMX - 1) / kMX) * ((g.ny + kMY - 1) / kMY) *
                              ((g.nz + kMZ - 1) / kMZ);
     hipLaunchKernelGGL(subtract_median<T>, dim3((unsigned)blocks), dim3(kThreads), 0, s, src,
