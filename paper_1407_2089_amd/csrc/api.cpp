@@ -102,7 +102,8 @@ static BrickGeom make_geom_with(const vr_volume_desc& d, bool large) {
 }
 
 // Default bricks depend on whether the volume needs large-volume addressing
-// at the regular default (larger bricks never make a large volume small).
+// at the regular default (the large default stores more halo, so such a
+// volume still needs it at the large default).
 BrickGeom make_geom(const vr_volume_desc& d) {
     const BrickGeom g = make_geom_with(d, false);
     const bool dflt = d.brick[0] == 0 && d.brick[1] == 0 && d.brick[2] == 0;
