@@ -488,6 +488,10 @@ __global__ __launch_bounds__(kThreads) void mrf_step_zm(const T* __restrict__ cu
         const int z0 = (int)(rest / d.ny) * kZChunk;
         const int z1 = min(z0 + kZChunk, d.nz);
         const int qx = qc * kThreads + (int)threadIdx.x;
+        // the wave's lanes hold consecutive quads of one row: a lane's x - 1
+        // and x + 4 neighbours are the adjacent lanes' edge voxels (DPP wave
+        // shifts), loaded from memory only by the wave's first and last lane
+        const int lane = (int)threadIdx.x & 63;
         if (qx >= nq) continue;
         const int x = 4 * qx;
         const size_t col = (size_t)y * d.nx + x;
@@ -504,8 +508,13 @@ __global__ __launch_bounds__(kThreads) void mrf_step_zm(const T* __restrict__ cu
             q.a = *reinterpret_cast<const V4*>(c0 - dym);
             q.b = *reinterpret_cast<const V4*>(c0 + dyp);
             q.o = *reinterpret_cast<const V4*>(orig + (size_t)z * plane + col);
-            q.left = x > 0 ? (int)c0[-1] : (int)c.x;
-            q.right = x + 4 < d.nx ? (int)c0[4] : (int)c.w;
+            // wave_shr:1 gives lane i the value of lane i - 1, wave_shl:1 that
+            // of lane i + 1 (lanes past the row's last quad are inactive and
+            // their values unused: that quad's right neighbour is itself)
+            const int from_prev = __builtin_amdgcn_update_dpp(0, (int)c.w, 0x138, 0xf, 0xf, false);
+            const int from_next = __builtin_amdgcn_update_dpp(0, (int)c.x, 0x130, 0xf, 0xf, false);
+            q.left = x == 0 ? (int)c.x : lane == 0 ? (int)c0[-1] : from_prev;
+            q.right = x + 4 >= d.nx ? (int)c.w : lane == 63 ? (int)c0[4] : from_next;
             quad_step(q, nxt + (size_t)z * plane + col, delta, full, ss, changed);
             prev = c;
             c = q.f;
