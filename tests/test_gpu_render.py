@@ -346,3 +346,42 @@ def test_invisible_channel_and_oblique_orthographic_view(ctx):
     rgba2, _ = gpu.render(ctx, Scene("ortho", vol2, 8, tfs, cam, 50, 40, False, 0.5, 0.995,
                                      (0.1, 0.1, 0.1, 1.0)))
     assert np.array_equal(rgba, rgba2)
+
+
+LAYOUTS = [((4, 4, 4), False), ((4, 16, 8), False), ((8, 8, 8), False), ((16, 4, 4), False),
+           ((32, 8, 4), False), ((4, 4, 4), True), ((8, 16, 8), True), ((16, 4, 32), True)]
+
+
+@pytest.mark.parametrize("ch,dtype", [(1, np.uint8), (2, np.uint16), (4, np.uint8), (5, np.uint8),
+                                      (6, np.uint16)])
+def test_relayout_forms_store_the_same_voxels(ctx, ch, dtype):
+    # Bricks 4 voxels wide take the scatter form of the relayout, wider ones
+    # the gather form; with and without row pairs.  Sampling the same points
+    # must give the same values bit for bit in every layout (the taps and
+    # the interpolation arithmetic do not depend on the layout).
+    import torch
+    nx, ny, nz = 37, 29, 23
+    bits = 8 if dtype == np.uint8 else 12
+    vol = scenes.random_volume(90 + ch, (ch, nz, ny, nx), dtype, 1 << bits)
+    rng = np.random.default_rng(ch)
+    n = 4096
+    pts = torch.from_numpy(rng.uniform([-1, -1, -1], [nx, ny, nz], size=(n, 3))
+                           .astype(np.float32)).cuda()
+    word = {1: 1, 2: 2, 3: 4, 4: 4, 5: 8, 6: 8}[ch] * (2 if dtype == np.uint16 else 1)
+    got = []
+    for brick, pairs in LAYOUTS:
+        if pairs and word > 4:
+            continue
+        v = vr.Volume(ctx, (nx, ny, nz), ch, 1, vr.VR_U8 if dtype == np.uint8 else vr.VR_U16,
+                      bits, brick=brick, row_pairs=pairs)
+        try:
+            v.upload(0, gpu.to_device(vol))
+            out = torch.zeros(n * ch, dtype=torch.float32, device="cuda")
+            vr.vr_debug_sample(v.ptr, 0, pts, n, out)
+            torch.cuda.synchronize()
+            got.append(out.cpu().numpy().view(np.uint32))
+        finally:
+            v.destroy()
+    assert len(got) >= 5
+    for g in got[1:]:
+        assert np.array_equal(g, got[0])
