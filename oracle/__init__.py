@@ -76,7 +76,7 @@ def load():
                                   C.c_void_p, C.c_void_p]
         lib.orc_shade.restype = C.c_int
         lib.orc_render.argtypes = [C.POINTER(_Volume), C.POINTER(_Transfer),
-                                   C.POINTER(_Camera), C.POINTER(_View), P,
+                                   C.POINTER(_Camera), C.POINTER(_View), P, P,
                                    C.c_int64, P, P, P, P, P, P, P, P, C.c_int]
         lib.orc_render.restype = C.c_int
         _lib = lib
@@ -180,12 +180,18 @@ def shade(vol: Volume, light, point):
 
 def render(vol: Volume, transfers, cam: Camera, width, height, eye=0, step=1.0,
            term_alpha=1.0, band_eps=1e-3, background=(0, 0, 0, 0), pixels=None,
-           nthreads=None, light=None):
+           nthreads=None, light=None, stop_at=None, members=True):
     """Render one eye (-1 left, 0 mono, +1 right), lit by ``light`` (a
     Light, or None for no lighting).  ``pixels`` is an optional int64 array of
-    linear pixel indices j * width + i.  Returns a dict of float64 / int32
-    numpy arrays keyed rgba, samples, nominal, count_margin, band_lo,
-    band_hi, band_k, lit_margin."""
+    linear pixel indices j * width + i.  ``stop_at`` (optional, one int per
+    rendered pixel): k >= 0 forces that ray to stop after exactly k samples
+    (R_k of the acceptance rule), -1 keeps the termination threshold.
+    Returns a dict of float64 / int32 numpy arrays keyed rgba, samples,
+    nominal, count_margin, band_lo, band_hi, band_k, lit_margin; with
+    ``members`` also band_idx (flat indices, into the rendered pixels, of the
+    pixels whose band is not empty) and band_rgba [len(band_idx)][L][4]:
+    member j of a pixel is R_k for k = band_k[0] + j up to band_k[1] (NaN
+    past its last member)."""
     lib = load()
     if len(transfers) != vol.data.shape[0]:
         raise ValueError("one transfer function per channel is required")
@@ -198,6 +204,12 @@ def render(vol: Volume, transfers, cam: Camera, width, height, eye=0, step=1.0,
         pixels = np.ascontiguousarray(pixels, dtype=np.int64)
         npix = pixels.size
         pix_ptr = pixels.ctypes.data
+    stop_ptr = None
+    if stop_at is not None:
+        stop_at = np.ascontiguousarray(stop_at, dtype=np.int32).reshape(-1)
+        if stop_at.size != npix:
+            raise ValueError("stop_at needs one entry per rendered pixel")
+        stop_ptr = stop_at.ctypes.data
     res = {
         "rgba": np.zeros((npix, 4), np.float64),
         "samples": np.zeros(npix, np.int32),
@@ -211,7 +223,7 @@ def render(vol: Volume, transfers, cam: Camera, width, height, eye=0, step=1.0,
     if nthreads is None:
         nthreads = os.cpu_count() or 1
     cv, cc = vol._c(), cam._c()
-    rc = lib.orc_render(C.byref(cv), tfs, C.byref(cc), C.byref(view), pix_ptr, npix,
+    rc = lib.orc_render(C.byref(cv), tfs, C.byref(cc), C.byref(view), pix_ptr, stop_ptr, npix,
                         res["rgba"].ctypes.data, res["samples"].ctypes.data,
                         res["nominal"].ctypes.data, res["count_margin"].ctypes.data,
                         res["band_lo"].ctypes.data, res["band_hi"].ctypes.data,
@@ -219,7 +231,25 @@ def render(vol: Volume, transfers, cam: Camera, width, height, eye=0, step=1.0,
                         int(nthreads))
     if rc != 0:
         raise ValueError("orc_render rejected its arguments")
+    if members and stop_at is None:
+        # Every member of each non-empty band, by forced stops (the band is a
+        # run of consecutive stop counts: opacity never decreases).
+        bk = res["band_k"]
+        idx = np.flatnonzero(bk[:, 0] >= 0)
+        span = (bk[idx, 1] - bk[idx, 0] + 1) if idx.size else np.zeros(0, np.int64)
+        L = int(span.max()) if idx.size else 0
+        band = np.full((idx.size, L, 4), np.nan)
+        all_pix = (np.arange(npix, dtype=np.int64) if pixels is None else pixels)
+        for j in range(L):
+            sel = np.flatnonzero(span > j)
+            r = render(vol, transfers, cam, width, height, eye, step, term_alpha, band_eps,
+                       background, all_pix[idx[sel]], nthreads, light,
+                       stop_at=bk[idx[sel], 0] + j, members=False)
+            band[sel, j] = r["rgba"]
+        res["band_idx"] = idx
+        res["band_rgba"] = band
     if pixels is None:
         for key in res:
-            res[key] = res[key].reshape((int(height), int(width)) + res[key].shape[1:])
+            if key not in ("band_idx", "band_rgba"):
+                res[key] = res[key].reshape((int(height), int(width)) + res[key].shape[1:])
     return res

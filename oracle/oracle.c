@@ -363,6 +363,7 @@ typedef struct {
     const orc_camera* cam;
     const orc_view* view;
     const int64_t* pixels;
+    const int32_t* stop_at; /* per listed pixel: -1, or the forced stop count */
     int64_t npix;
     orc_result res;
     int64_t next; /* shared work counter */
@@ -410,6 +411,10 @@ static void render_pixel(const job_t* jb, int64_t slot)
     bk[0] = bk[1] = -1;
 
     const double tau = view->term_alpha, eps = view->band_eps;
+    /* A forced stop count k >= 0 gives R_k, the result of the ray stopped
+     * after exactly k samples (or after its last one), whatever its opacity:
+     * the members of the termination band are such results. */
+    const int32_t target = jb->stop_at ? jb->stop_at[slot] : -1;
     int stopped = 0, k_stop = 0, nominal = 0;
     double margin = 1.0, margin_lit = 0.0;
 
@@ -422,6 +427,10 @@ static void render_pixel(const job_t* jb, int64_t slot)
          * decide A >= tau either way, and then stops at the next sample). */
         int prev_in = fabs(A - tau) <= eps;
         if (prev_in) band_add(blo, bhi, bk, out, 0);
+        if (target == 0) {
+            memcpy(rgba, out, sizeof out);
+            stopped = 1;
+        }
 
         double field[ORC_MAX_CHANNELS], shade[ORC_MAX_CHANNELS], smargin[ORC_MAX_CHANNELS];
         double lit_err;
@@ -429,7 +438,7 @@ static void render_pixel(const job_t* jb, int64_t slot)
             double t = t_enter + (k + 0.5) * view->step;
             if (!(t < t_exit)) break;
             nominal = k + 1;
-            if (stopped && A > tau + eps && !prev_in) continue; /* only counting now */
+            if (stopped && A > tau + eps && !prev_in && target < 0) continue; /* only counting now */
             double p[3];
             for (int a = 0; a < 3; ++a) p[a] = p0[a] + t * d[a];
             orc_sample(v, p, field);
@@ -447,7 +456,7 @@ static void render_pixel(const job_t* jb, int64_t slot)
             if (!stopped) {
                 memcpy(rgba, out, sizeof out);
                 k_stop = k + 1;
-                if (A >= tau) stopped = 1;
+                if (target >= 0 ? k + 1 >= target : A >= tau) stopped = 1;
             }
         }
         if (!stopped && k_stop == 0) { /* entered the box but took no sample */
@@ -481,10 +490,14 @@ static void* worker(void* arg)
 
 /* Render the pixels listed in `pixels` (linear index j * width + i), or the
  * whole image in row-major order when `pixels` is NULL (npix must then be
- * width * height).  nthreads <= 1 runs on the calling thread.  Returns 0, or
- * -1 on an invalid argument. */
+ * width * height).  stop_at (NULL, or one entry per rendered pixel): an entry
+ * k >= 0 stops that ray after exactly k samples (after its last sample if it
+ * has fewer) instead of at the termination threshold, which yields the band
+ * member R_k of the acceptance rule; -1 keeps the threshold.  nthreads <= 1
+ * runs on the calling thread.  Returns 0, or -1 on an invalid argument. */
 int orc_render(const orc_volume* vol, const orc_transfer* tf, const orc_camera* cam,
-               const orc_view* view, const int64_t* pixels, int64_t npix,
+               const orc_view* view, const int64_t* pixels, const int32_t* stop_at,
+               int64_t npix,
                double* rgba, int32_t* samples, int32_t* nominal, double* count_margin,
                double* band_lo, double* band_hi, int32_t* band_k, double* lit_margin,
                int nthreads)
@@ -505,6 +518,7 @@ int orc_render(const orc_volume* vol, const orc_transfer* tf, const orc_camera* 
     jb.cam = cam;
     jb.view = view;
     jb.pixels = pixels;
+    jb.stop_at = stop_at;
     jb.npix = npix;
     jb.res.rgba = rgba;
     jb.res.samples = samples;

@@ -174,7 +174,7 @@ def oracle_pixels_on_crops(src, sc, eye, pixels):
         res.append(oracle.render(vol, orc.transfers(sc.tfs), orc.camera(sc.cam), sc.width,
                                  sc.height, eye, sc.step, sc.term_alpha, 1e-3, sc.background,
                                  [int(pix)], 1, None))
-    return {k: np.concatenate([r[k] for r in res]) for k in res[0]}
+    return orc.concat(res)
 
 
 @pytest.fixture(scope="module")

@@ -85,6 +85,69 @@ def test_p2_termination_band_brackets_neighbours():
                                atol=1e-12)
 
 
+def test_p2_band_members_are_the_forced_stops_closed_form():
+    # Each member R_k of the termination band is the ray stopped after exactly
+    # k samples: on the slab, transparent samples until z_a and then
+    # A_k = 1 - (1 - a)^(k - z_a - 1), colour g rgb A_k, for every k of the
+    # band's range, in order.
+    sc = scenes.slab_scene(alpha_mul=1.0, curve=0.0, term_alpha=0.99, z_a=3, z_b=40, nz=44)
+    _, a, stop = scenes.slab_closed_form(sc, 200, 3, 40)
+    r = orc.render(sc, band_eps=4e-3)
+    assert r["band_idx"].size == 64  # every interior ray crosses the band
+    g = (200 / 255 - sc.tfs[0].lo) / (1 - sc.tfs[0].lo)
+    k0, k1 = r["band_k"].reshape(-1, 2)[0]
+    assert k0 <= stop <= k1 and k1 - k0 >= 1
+    for j, k in enumerate(range(k0, k1 + 1)):
+        A = 1 - (1 - a) ** (k - 4)
+        exp = [A * g * c for c in sc.tfs[0].rgb] + [A]
+        np.testing.assert_allclose(r["band_rgba"][:, j], np.broadcast_to(exp, (64, 4)),
+                                   rtol=0, atol=1e-12)
+    assert np.isnan(r["band_rgba"][:, k1 - k0 + 1:]).all()
+    # a forced stop past the last sample gives the full ray
+    full = orc.render(sc, term_alpha=1.0)
+    late = orc.render(sc, stop_at=np.full(64, 10_000), term_alpha=0.99)
+    np.testing.assert_array_equal(late["rgba"], full["rgba"])
+    # and a forced stop at 0 gives the background
+    none = orc.render(sc, stop_at=np.zeros(64), term_alpha=0.99)
+    assert not none["rgba"].any()
+
+
+def test_p2_background_behind_partial_opacity_closed_form():
+    # Slab of opacity 0 < A < 1 over a coloured background:
+    # rgb = A g c + (1 - A) bg_a bg_rgb, alpha = A + (1 - A) bg_a.
+    sc = scenes.slab_scene(dtype=np.uint16, bits=12, v=2500, z_a=5, z_b=8)
+    exp, a, _ = scenes.slab_closed_form(sc, 2500, 5, 8)
+    A = exp[3]
+    assert 0.2 < A < 0.8
+    for bg in ((0.2, 0.5, 0.9, 0.6), (1.0, 0.0, 0.3, 1.0), (0.7, 0.7, 0.1, 0.25)):
+        sc.background = bg
+        r = orc.render(sc)["rgba"].reshape(-1, 4)
+        want = [exp[q] + (1 - A) * bg[3] * bg[q] for q in range(3)] + [A + (1 - A) * bg[3]]
+        np.testing.assert_allclose(r, np.broadcast_to(want, r.shape), rtol=0, atol=1e-12)
+
+
+def test_acceptance_rule_is_per_band_member():
+    # A pixel in the band passes when it is within tol of one member, not
+    # merely inside the componentwise box around all members.
+    import gpu
+    sc = scenes.slab_scene(alpha_mul=1.0, curve=0.0, term_alpha=0.99, z_a=3, z_b=40, nz=44,
+                           rgb=(0.9, 0.1, 0.5))
+    ref = orc.render(sc, band_eps=1e-3)
+    members = ref["band_rgba"][0]
+    members = members[~np.isnan(members[:, 0])]
+    assert len(members) >= 2
+    tol = 1e-3
+    for m in members:  # every member passes, with its own sample count
+        gpu.compare(np.broadcast_to(m, (8, 8, 4)), None, ref, tol)
+    # a point inside the box [min - tol, max + tol] but far from every member:
+    # red from the first member, alpha from the last
+    odd = members[0].copy()
+    odd[3] = members[-1][3]
+    assert np.abs(members - odd).max(-1).min() > tol
+    with pytest.raises(AssertionError):
+        gpu.compare(np.broadcast_to(odd, (8, 8, 4)), None, ref, tol)
+
+
 def test_p2_two_channel_slab_merge_closed_form():
     # Both channels fill the same planes.  The sample's alpha is the larger
     # channel alpha (capped at 1); its colour is the per-component sum of the
