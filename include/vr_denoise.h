@@ -41,6 +41,19 @@ typedef struct {
     int32_t shift;
 } vr_lowpass;
 
+/* Integer weights of the low-pass of eq. (1) as a quantised Gaussian of
+ * width sigma voxels (the paper names a Gaussian filter without weights):
+ * w[i] = round(2^shift g_i / sum_j g_j), g_i = exp(-k^2 / (2 sigma^2)) at
+ * k = i - r for i = 0 .. 2r (ties to even), with the rounding remainder
+ * added to the centre tap w[r] so that the weights sum to exactly 2^shift.
+ * radius r: 0..64, or -1 for min(64, ceil(3 sigma)).  w (host, capacity
+ * entries) receives the 2r + 1 weights and *taps their number.  Pure host
+ * computation.  VR_ERR_INVALID_ARG for sigma <= 0 or not finite, shift
+ * outside 1..16, capacity < 2r + 1, or when the rounded side weights alone
+ * exceed 2^shift (a wide kernel at a small shift). */
+vr_status vr_gaussian_weights(double sigma, int32_t shift, int32_t radius, uint32_t* w,
+                              int32_t capacity, int32_t* taps);
+
 /* Device workspace bytes that the two calls below need for `grid`: two
  * volumes of the voxel type (each rounded up to 256 bytes) plus
  * 1 MiB + 64 KiB + 256 bytes of tables. */

@@ -27,8 +27,24 @@ import math
 
 import numpy as np
 
-__all__ = ["low_pass", "median3", "remove_background", "noise_sigma", "min_gap", "mrf_step",
+__all__ = ["gaussian_weights", "low_pass", "median3", "remove_background", "noise_sigma", "min_gap", "mrf_step",
            "mrf"]
+
+
+def gaussian_weights(sigma, shift, radius=None):
+    """The low-pass kernel of eq. (1) read as a quantised Gaussian: the
+    Gaussian exp(-k^2 / (2 sigma^2)) sampled at the integer offsets
+    k = -r .. r (r = min(64, ceil(3 sigma)) unless given), normalised to sum
+    2^shift, each weight rounded to the nearest integer (ties to even), and
+    whatever the rounding leaves over or takes away put on the centre tap."""
+    r = min(64, math.ceil(3.0 * sigma)) if radius is None else int(radius)
+    k = np.arange(-r, r + 1, dtype=np.float64)
+    g = np.exp(-(k * k) / (2.0 * sigma * sigma))
+    w = np.rint(g / g.sum() * 2.0 ** shift).astype(np.int64)
+    w[r] += (1 << shift) - int(w.sum())
+    if w[r] < 0:
+        raise ValueError("the rounded side weights exceed 2^shift")
+    return [int(x) for x in w]
 
 
 def _pass(vol, weights, shift, axis):

@@ -21,7 +21,7 @@ __all__ = [
     "vr_last_error", "vr_debug_sample", "Context", "Volume", "VR_U8", "VR_U16",
     "VR_FP32", "VR_FP16", "VR_ORTHO", "VR_PERSPECTIVE", "vr_denoise_workspace_bytes",
     "vr_remove_background", "vr_mrf_denoise", "gaussian_weights", "remove_background",
-    "mrf_denoise", "vr_stream_frame", "vr_stream_ready",
+    "mrf_denoise", "vr_stream_frame", "vr_stream_ready", "vr_gaussian_weights",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvr.so")
@@ -124,6 +124,8 @@ def lib():
             "vr_release": [P, C.c_uint64],
             "vr_debug_sample": [P, C.c_int32, P, C.c_int32, P, P],
             "vr_denoise_workspace_bytes": [C.POINTER(vr_grid), C.POINTER(C.c_uint64)],
+            "vr_gaussian_weights": [C.c_double, C.c_int32, C.c_int32, P, C.c_int32,
+                                    C.POINTER(C.c_int32)],
             "vr_remove_background": [P, C.POINTER(vr_grid), C.POINTER(vr_lowpass), P, P, P, P,
                                      C.c_uint64, P],
             "vr_mrf_denoise": [P, C.POINTER(vr_grid), C.c_int32, P, P, P, C.c_uint64, P,
@@ -278,17 +280,19 @@ def vr_mrf_denoise(ctx, grid, max_iters, src, dst, workspace, workspace_bytes, s
     return info
 
 
+def vr_gaussian_weights(sigma: float, shift: int = 14, radius: int = -1):
+    """Quantised Gaussian low-pass weights from the library (a list of ints
+    summing to 2^shift; radius -1: min(64, ceil(3 sigma)))."""
+    buf = (C.c_uint32 * 129)()
+    taps = C.c_int32()
+    _check(lib().vr_gaussian_weights(float(sigma), int(shift), int(radius), buf, 129,
+                                     C.byref(taps)))
+    return [int(buf[i]) for i in range(taps.value)]
+
+
 def gaussian_weights(sigma, shift=14, radius=None):
-    """Integer weights of a sampled Gaussian (radius ceil(3 sigma), at most
-    64) that sum to exactly 2^shift: rounded, the remainder put on the
-    centre tap."""
-    import math
-    r = min(64, int(math.ceil(3.0 * sigma))) if radius is None else int(radius)
-    g = [math.exp(-0.5 * (k / sigma) ** 2) for k in range(-r, r + 1)]
-    tot = sum(g)
-    w = [int(round((1 << shift) * x / tot)) for x in g]
-    w[r] += (1 << shift) - sum(w)
-    return w
+    """vr_gaussian_weights with radius None meaning the library default."""
+    return vr_gaussian_weights(sigma, shift, -1 if radius is None else radius)
 
 
 def _grid_of(vol, bits):

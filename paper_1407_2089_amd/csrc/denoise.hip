@@ -743,6 +743,41 @@ using namespace vr;
 
 extern "C" {
 
+vr_status vr_gaussian_weights(double sigma, int32_t shift, int32_t radius, uint32_t* w,
+                              int32_t capacity, int32_t* taps) {
+    if (!(sigma > 0.0) || !std::isfinite(sigma))
+        return fail(VR_ERR_INVALID_ARG, "sigma must be finite and > 0");
+    if (shift < 1 || shift > 16) return fail(VR_ERR_INVALID_ARG, "shift must be 1..16");
+    if (radius < -1 || radius > 64) return fail(VR_ERR_INVALID_ARG, "radius must be -1..64");
+    if (!w || !taps) return fail(VR_ERR_INVALID_ARG, "NULL output");
+    const int r = radius >= 0 ? radius : (int)std::min(64.0, std::ceil(3.0 * sigma));
+    const int n = 2 * r + 1;
+    if (capacity < n) return fail(VR_ERR_INVALID_ARG, "%d weights need capacity %d", n, n);
+    // Samples of exp(-k^2 / (2 sigma^2)) at k = -r .. r, scaled to 2^shift
+    // and rounded to nearest (ties to even); the rounding remainder goes to
+    // the centre tap so that the sum is exactly 2^shift.
+    double g[129], tot = 0.0;
+    for (int i = 0; i < n; ++i) {
+        const double k = (double)(i - r);
+        g[i] = std::exp(-(k * k) / (2.0 * sigma * sigma));
+        tot += g[i];
+    }
+    const double scale = std::ldexp(1.0, shift);
+    int64_t sum = 0;
+    for (int i = 0; i < n; ++i) {
+        w[i] = (uint32_t)std::nearbyint(scale * g[i] / tot);
+        sum += w[i];
+    }
+    const int64_t centre = (int64_t)w[r] + ((int64_t)1 << shift) - sum;
+    if (centre < 0)
+        return fail(VR_ERR_INVALID_ARG,
+                    "rounded weights exceed 2^%d at sigma %g and radius %d: take a larger shift",
+                    shift, sigma, r);
+    w[r] = (uint32_t)centre;
+    *taps = n;
+    return ok();
+}
+
 vr_status vr_denoise_workspace_bytes(const vr_grid* grid, uint64_t* bytes) {
     vr_status st = check_grid(grid);
     if (st != VR_OK) return st;

@@ -28,7 +28,8 @@ def test_library_exports_every_declared_symbol():
     assert "vr_render" in names and "vr_submit" in names and len(names) == 16
     assert "vr_stream_frame" in names and "vr_stream_ready" in names
     dn = declared_symbols("vr_denoise.h")
-    assert dn == ["vr_denoise_workspace_bytes", "vr_mrf_denoise", "vr_remove_background"]
+    assert dn == ["vr_denoise_workspace_bytes", "vr_gaussian_weights", "vr_mrf_denoise",
+                  "vr_remove_background"]
     for n in names + declared_symbols("vr_test.h") + dn:
         assert hasattr(L, n), n
 
@@ -463,11 +464,27 @@ def test_remove_background_validation(vctx):
     expect(vr.VR_ERR_UNSUPPORTED, lambda: bg_call(vctx, g, ok, dst=BASE + 40 * 30 * 20 * 2))
 
 
-def test_gaussian_weights_sum_to_a_power_of_two():
-    for sigma, shift in [(0.5, 8), (1.0, 14), (2.5, 16), (30.0, 16)]:
-        w = vr.gaussian_weights(sigma, shift)
-        assert sum(w) == 1 << shift and len(w) % 2 == 1 and len(w) <= 129
-        assert w == w[::-1] and max(w) == w[len(w) // 2]
+@pytest.mark.parametrize("sigma,shift,radius", [(0.5, 8, None), (0.6, 3, 2), (0.6, 4, 2),
+                                                (1.0, 8, 3), (1.0, 14, None),
+                                                (2.5, 16, None), (4.0, 16, None),
+                                                (16.0, 16, None), (20.0, 16, None),
+                                                (30.0, 16, None), (7.3, 12, 9)])
+def test_gaussian_weights_match_the_oracle(sigma, shift, radius):
+    # the library's host computation against the oracle's, integer for integer
+    from oracle import denoise as dn
+    assert vr.gaussian_weights(sigma, shift, radius) == dn.gaussian_weights(sigma, shift, radius)
+
+
+def test_gaussian_weights_validation():
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_gaussian_weights, 0.0, 8)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_gaussian_weights, float("nan"), 8)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_gaussian_weights, 1.0, 0)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_gaussian_weights, 1.0, 17)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_gaussian_weights, 1.0, 8, 65)
+    expect(vr.VR_ERR_INVALID_ARG, vr.vr_gaussian_weights, 100.0, 3, 5)  # cannot normalise
+    buf = (C.c_uint32 * 4)()
+    taps = C.c_int32()
+    assert vr.lib().vr_gaussian_weights(2.0, 8, -1, buf, 4, C.byref(taps)) == vr.VR_ERR_INVALID_ARG
 
 
 def test_mrf_validation(vctx):

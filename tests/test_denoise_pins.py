@@ -6,6 +6,7 @@ import itertools
 import statistics
 
 import numpy as np
+import pytest
 
 from oracle import denoise as dn
 
@@ -196,3 +197,69 @@ def test_mrf_leaves_a_ramp_and_a_constant_alone():
     c = np.full((4, 4, 4), 9, np.uint8)
     out, n, _, delta = dn.mrf(c, 8, 50)
     assert delta == 0 and n == 0 and np.array_equal(out, c)
+
+
+# ------------------------------------------------- quantised Gaussian weights
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden",
+                                    "gaussian_sigma1_r3_shift8.txt")
+
+
+def _golden_gaussian():
+    with open(GOLDEN) as fh:
+        rows = [l for l in fh if l.strip() and not l.startswith("#")]
+    return [int(x) for x in rows[0].split()]
+
+
+def test_gaussian_weights_hand_computed_case():
+    # sigma 1, radius 3, shift 8: worked out by hand (fixture header)
+    assert dn.gaussian_weights(1.0, 8, 3) == _golden_gaussian()
+
+
+def _trunc_normal_var(sigma, a):
+    """Variance of a normal N(0, sigma^2) truncated to [-a, a] (closed form)."""
+    import math
+    z = a / sigma
+    phi = math.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+    return sigma * sigma * (1.0 - 2.0 * z * phi / math.erf(z / math.sqrt(2.0)))
+
+
+@pytest.mark.parametrize("sigma,shift", [(1.5, 14), (2.0, 14), (3.0, 16), (4.0, 16),
+                                         (10.0, 16), (16.0, 16), (20.0, 16)])
+def test_gaussian_weights_properties(sigma, shift):
+    import math
+    w = np.array(dn.gaussian_weights(sigma, shift), np.int64)
+    r = (len(w) - 1) // 2
+    assert r == min(64, math.ceil(3 * sigma)) and len(w) == 2 * r + 1
+    assert w.sum() == 1 << shift                     # exact sum
+    assert np.array_equal(w, w[::-1])                # symmetric
+    assert (w >= 0).all()
+    assert (np.diff(w[:r]) >= 0).all()               # side weights rise towards the centre
+    # the centre carries the rounding remainder of the 2r side weights (each
+    # off by at most 1/2), so it is the exact value within r
+    c = 2.0 ** shift / (1.0 + 2.0 * np.exp(-np.arange(1, r + 1) ** 2 / (2 * sigma ** 2)).sum())
+    assert abs(w[r] - c) <= r + 0.5
+    # each side weight follows the continuous normal density scaled to 2^shift
+    # (the discrete normalisation differs from the continuous one by well
+    # under 1e-3 relative for sigma >= 1.5, less the truncated tails)
+    k = np.arange(-r, r + 1)
+    dens = np.exp(-k * k / (2.0 * sigma * sigma)) / (sigma * math.sqrt(2.0 * math.pi))
+    tail = math.erfc((r + 0.5) / (sigma * math.sqrt(2.0)))
+    approx = dens / (1.0 - tail) * 2.0 ** shift
+    side = np.arange(len(w)) != r
+    assert np.abs(w[side] - approx[side]).max() <= 1.0 + 2e-3 * approx.max()
+    # second moment: the normal truncated at r + 1/2 (midpoint rule)
+    var = float((w * k * k).sum()) / 2.0 ** shift
+    assert abs(var - _trunc_normal_var(sigma, r + 0.5)) <= 0.02 * sigma * sigma + 0.1
+
+
+def test_gaussian_weights_remainder_goes_to_the_centre():
+    # sigma 0.6, radius 2 (by hand): g = exp(-k^2 / 0.72) = 1, 0.24935,
+    # 0.00387, sum 1.50644.  Shift 4: 16 g / sum = 10.621, 2.648, 0.041 ->
+    # 11, 3, 0, sum 17: the centre gives one back, 10.  Shift 3: 5.311,
+    # 1.324, 0.021 -> 5, 1, 0, sum 7: the centre takes one more, 6.
+    assert dn.gaussian_weights(0.6, 4, 2) == [0, 3, 10, 3, 0]
+    assert dn.gaussian_weights(0.6, 3, 2) == [0, 1, 6, 1, 0]
+    # a flat wide kernel at a tiny shift cannot be normalised
+    with pytest.raises(ValueError):
+        dn.gaussian_weights(100.0, 3, 5)
