@@ -77,7 +77,8 @@ def load():
         lib.orc_shade.restype = C.c_int
         lib.orc_render.argtypes = [C.POINTER(_Volume), C.POINTER(_Transfer),
                                    C.POINTER(_Camera), C.POINTER(_View), P, P,
-                                   C.c_int64, P, P, P, P, P, P, P, P, C.c_int]
+                                   C.c_int64, P, P, P, P, P, P, P, P, P, C.c_int32,
+                                   C.c_int]
         lib.orc_render.restype = C.c_int
         _lib = lib
     return _lib
@@ -228,24 +229,36 @@ def render(vol: Volume, transfers, cam: Camera, width, height, eye=0, step=1.0,
                         res["nominal"].ctypes.data, res["count_margin"].ctypes.data,
                         res["band_lo"].ctypes.data, res["band_hi"].ctypes.data,
                         res["band_k"].ctypes.data, res["lit_margin"].ctypes.data,
-                        int(nthreads))
+                        None, 0, int(nthreads))
     if rc != 0:
         raise ValueError("orc_render rejected its arguments")
     if members and stop_at is None:
-        # Every member of each non-empty band, by forced stops (the band is a
-        # run of consecutive stop counts: opacity never decreases).
+        # Every member of each non-empty band: the band pixels marched once
+        # more, recording R_k at each stop count k of the band (one run of
+        # consecutive counts: opacity never decreases).
         bk = res["band_k"]
         idx = np.flatnonzero(bk[:, 0] >= 0)
         span = (bk[idx, 1] - bk[idx, 0] + 1) if idx.size else np.zeros(0, np.int64)
         L = int(span.max()) if idx.size else 0
         band = np.full((idx.size, L, 4), np.nan)
-        all_pix = (np.arange(npix, dtype=np.int64) if pixels is None else pixels)
-        for j in range(L):
-            sel = np.flatnonzero(span > j)
-            r = render(vol, transfers, cam, width, height, eye, step, term_alpha, band_eps,
-                       background, all_pix[idx[sel]], nthreads, light,
-                       stop_at=bk[idx[sel], 0] + j, members=False)
-            band[sel, j] = r["rgba"]
+        if idx.size:
+            all_pix = (np.arange(npix, dtype=np.int64) if pixels is None else pixels)
+            sub = np.ascontiguousarray(all_pix[idx], dtype=np.int64)
+            m = sub.size
+            scratch = {k: np.zeros(v.shape[1:] and (m,) + v.shape[1:] or (m,), v.dtype)
+                       for k, v in res.items()}
+            rc = lib.orc_render(C.byref(cv), tfs, C.byref(cc), C.byref(view), sub.ctypes.data,
+                                None, m, scratch["rgba"].ctypes.data,
+                                scratch["samples"].ctypes.data, scratch["nominal"].ctypes.data,
+                                scratch["count_margin"].ctypes.data,
+                                scratch["band_lo"].ctypes.data, scratch["band_hi"].ctypes.data,
+                                scratch["band_k"].ctypes.data, scratch["lit_margin"].ctypes.data,
+                                band.ctypes.data, L, int(nthreads))
+            if rc != 0:
+                raise ValueError("orc_render rejected its arguments")
+            # entries past a pixel's last member stay NaN
+            for q in range(m):
+                band[q, span[q]:] = np.nan
         res["band_idx"] = idx
         res["band_rgba"] = band
     if pixels is None:

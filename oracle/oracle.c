@@ -86,6 +86,10 @@ typedef struct {
     double* lit_margin;    /* [npix]     bound on the colour change that FP32
                                          rounding of the gradients can cause
                                          (0 when unlit)                          */
+    double* members;       /* NULL, or [npix][member_cap][4]: band member
+                                         R_k of stop count k written at
+                                         [k - smallest member count]             */
+    int32_t member_cap;
 } orc_result;
 
 /* ---------------------------------------------------------------- sampling */
@@ -357,6 +361,16 @@ static void band_add(double lo[4], double hi[4], int32_t k_range[2], const doubl
     if (k > k_range[1]) k_range[1] = k;
 }
 
+/* Records band member R_k (the result of the ray stopped after k samples)
+ * of the pixel in `slot`; the band is one run of stop counts (opacity never
+ * decreases), starting at k0. */
+static void member(const orc_result* res, int64_t slot, int k0, int k, const double r[4])
+{
+    if (!res->members || k - k0 >= res->member_cap) return;
+    memcpy(res->members + 4 * ((size_t)slot * (size_t)res->member_cap + (size_t)(k - k0)), r,
+           4 * sizeof(double));
+}
+
 typedef struct {
     const orc_volume* vol;
     const orc_transfer* tf;
@@ -426,7 +440,10 @@ static void render_pixel(const job_t* jb, int64_t slot)
          * after each of them (a ray whose opacity is that close to tau may
          * decide A >= tau either way, and then stops at the next sample). */
         int prev_in = fabs(A - tau) <= eps;
-        if (prev_in) band_add(blo, bhi, bk, out, 0);
+        if (prev_in) {
+            band_add(blo, bhi, bk, out, 0);
+            member(&jb->res, slot, 0, 0, out);
+        }
         if (target == 0) {
             memcpy(rgba, out, sizeof out);
             stopped = 1;
@@ -451,7 +468,10 @@ static void render_pixel(const job_t* jb, int64_t slot)
             A += (1.0 - A) * a_s;
             finish(view, C, A, out);
             const int in = fabs(A - tau) <= eps;
-            if (in || prev_in) band_add(blo, bhi, bk, out, k + 1);
+            if (in || prev_in) {
+                band_add(blo, bhi, bk, out, k + 1);
+                member(&jb->res, slot, bk[0], k + 1, out);
+            }
             prev_in = in;
             if (!stopped) {
                 memcpy(rgba, out, sizeof out);
@@ -493,14 +513,16 @@ static void* worker(void* arg)
  * width * height).  stop_at (NULL, or one entry per rendered pixel): an entry
  * k >= 0 stops that ray after exactly k samples (after its last sample if it
  * has fewer) instead of at the termination threshold, which yields the band
- * member R_k of the acceptance rule; -1 keeps the threshold.  nthreads <= 1
+ * member R_k of the acceptance rule; -1 keeps the threshold.  members (NULL,
+ * or [npix][member_cap][4]): every band member R_k met on the march, at
+ * [k - band_k[0]] of its pixel (the first member_cap of them).  nthreads <= 1
  * runs on the calling thread.  Returns 0, or -1 on an invalid argument. */
 int orc_render(const orc_volume* vol, const orc_transfer* tf, const orc_camera* cam,
                const orc_view* view, const int64_t* pixels, const int32_t* stop_at,
                int64_t npix,
                double* rgba, int32_t* samples, int32_t* nominal, double* count_margin,
                double* band_lo, double* band_hi, int32_t* band_k, double* lit_margin,
-               int nthreads)
+               double* members, int32_t member_cap, int nthreads)
 {
     if (!vol || !tf || !cam || !view || !rgba || !samples || !nominal || !count_margin
         || !band_lo || !band_hi || !band_k || !lit_margin)
@@ -528,6 +550,8 @@ int orc_render(const orc_volume* vol, const orc_transfer* tf, const orc_camera* 
     jb.res.band_hi = band_hi;
     jb.res.band_k = band_k;
     jb.res.lit_margin = lit_margin;
+    jb.res.members = member_cap > 0 ? members : NULL;
+    jb.res.member_cap = member_cap;
     jb.next = 0;
 
     if (nthreads <= 1) {
