@@ -180,33 +180,47 @@ typedef struct {
     vr_light light;         /* lighting; zero-initialised = off              */
 } vr_render_req;
 
-/* Ticket state reported by vr_poll. */
+/* Ticket state reported by vr_poll.  Stamps are steady-clock nanoseconds,
+ * 0 until reached: t_arrive_ns at vr_submit, t_admit_ns when the serving loop
+ * admitted the request and enqueued its batch, t_done_ns when the loop saw
+ * the batch finished, t_start_ns = t_done_ns minus the batch's span on the
+ * device (HIP events recorded before and after its kernels), i.e. when the
+ * device started the batch, on the same clock (set with t_done_ns). */
 typedef struct {
     int32_t state;        /* 0 pending, 1 running, 2 done, 3 failed          */
     int32_t err;          /* vr_status of a failed ticket                    */
-    uint64_t t_arrive_ns; /* steady-clock stamps; 0 until reached            */
+    uint64_t t_arrive_ns;
     uint64_t t_admit_ns;
     uint64_t t_start_ns;
     uint64_t t_done_ns;
+    uint64_t samples;     /* samples composited over all pixels and eyes
+                             (set when done): the nominal count, unchanged
+                             by empty-space skipping and early termination
+                             only stops counting                            */
     uint64_t rays;        /* pixels x eyes of the request                    */
 } vr_ticket_info;
 
-/* Open a context on HIP device `device` with a memory budget for volumes and
- * in-flight served requests (0 = the device's free memory at open time minus
+/* Open a context on HIP device `device` (the viewer's one graphics card that
+ * holds the series: Methods, acquisition paragraph) with a memory budget for
+ * volumes and in-flight served requests (0 = the device's free memory at open time minus
  * a 4 GiB reserve).  device = -1 opens a validation-only context with no GPU:
  * every call validates its arguments, then calls that need a GPU return
  * VR_ERR_UNSUPPORTED.  *out receives the context. */
 vr_status vr_init(int32_t device, uint64_t mem_budget_bytes, vr_ctx** out);
 
-/* Stop the serving thread and free the context.  VR_ERR_BUSY while served
+/* Stop the serving thread and free the context (the end of a viewing
+ * session; Abstract: the interactive loop).  VR_ERR_BUSY while served
  * tickets are pending or running, or volumes are still alive. */
 vr_status vr_shutdown(vr_ctx* ctx);
 
 /* Bytes of device storage a volume with this description needs (all
- * frames).  Pure host computation. */
+ * frames): bricks with their halo plus one macro-cell table per frame (the
+ * whole sequence resident in GPU memory: Methods, acquisition paragraph).
+ * Pure host computation. */
 vr_status vr_volume_storage_bytes(const vr_volume_desc* desc, uint64_t* bytes);
 
-/* Register a resident series in caller-owned device storage of at least
+/* Register a resident 5-D series (x, y, z, t, channel: Background; Methods,
+ * acquisition and import paragraphs) in caller-owned device storage of at least
  * vr_volume_storage_bytes(desc) bytes, 256-byte aligned.  Its bytes count
  * against the context's budget (VR_ERR_OUT_OF_MEMORY when they do not fit).
  * All channels start with the default transfer function (lo 0, hi 1, curve 0,
@@ -214,7 +228,10 @@ vr_status vr_volume_storage_bytes(const vr_volume_desc* desc, uint64_t* bytes);
 vr_status vr_create_volume(vr_ctx* ctx, const vr_volume_desc* desc, void* dev_storage,
                            uint64_t storage_bytes, vr_volume** out);
 
-/* Copy one frame into the volume's storage on `hip_stream`.  dev_src is a
+/* Copy one time point into the volume's storage on `hip_stream` (the
+ * sequence is downloaded to video memory frame by frame: Methods,
+ * acquisition paragraph; User Interface, work-flow paragraph): brick
+ * relayout, then the frame's macro-cell maxima.  dev_src is a
  * device array [channels][nz][ny][nx] of uint8 or uint16 (the volume's
  * dtype), contiguous; values above 2^bits - 1 are clamped to it. */
 vr_status vr_upload_frame(vr_volume* vol, int32_t frame, const void* dev_src,
@@ -246,47 +263,77 @@ vr_status vr_stream_frame(vr_volume* vol, int32_t slot, const void* host_src,
                           void* render_stream);
 
 /* Make render_stream wait until the last vr_stream_frame into `slot` has
- * landed (no wait if the slot was never streamed). */
+ * landed (no wait if the slot was never streamed).  Playback of buffered
+ * sequences: Methods, acquisition paragraph; Results and Discussion, time
+ * navigation. */
 vr_status vr_stream_ready(vr_volume* vol, int32_t slot, void* render_stream);
 
-/* Unregister a volume and return its bytes to the budget.  VR_ERR_BUSY while
+/* Unregister a volume (closing a data set: User Interface, work-flow
+ * paragraph) and return its bytes to the budget.  VR_ERR_BUSY while
  * a served ticket that reads it is pending or running. */
 vr_status vr_destroy_volume(vr_volume* vol);
 
-/* Set channel `channel`'s transfer function; copied.  Requests enqueued or
+/* Set channel `channel`'s colour, visibility and transfer function (User
+ * Interface, transfer-function paragraph: floor, ceiling, curve, alpha
+ * multiplier per channel); copied.  Requests enqueued or
  * submitted earlier keep the function they were given. */
 vr_status vr_set_transfer(vr_volume* vol, int32_t channel, const vr_transfer* tf);
 
-/* Enqueue one request on `hip_stream` (one kernel launch per call). */
+/* Enqueue one request on `hip_stream` (one kernel launch per call): the
+ * volume rendered for a view, in stereo if asked (User Interface, volume
+ * rendering paragraph; Results and Discussion, stereo viewing).  Rays jump
+ * over macro cells whose channel maxima are below every transfer-function
+ * floor; images and sample counts equal those of a walk over every sample. */
 vr_status vr_render(vr_ctx* ctx, const vr_render_req* req, void* hip_stream);
 
 /* Enqueue n requests as one persistent, load-balanced launch (replayed from
  * a captured HIP graph) on `hip_stream`.  Every request's output is bitwise
- * identical to what vr_render gives for it alone.  n = 0 is a no-op. */
+ * identical to what vr_render gives for it alone.  n = 0 is a no-op.  Uses
+ * the wave tile that vr_tune_batch (or the VR_AUTOTUNE_CACHE file) chose for
+ * the batch's shape class, else the default; never tunes, never waits for
+ * the device except when its staging tables are still being read by the
+ * previous batch on the same stream.  (A project addition: the paper's
+ * viewer renders one view at a time; User Interface section.) */
 vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
                           void* hip_stream);
 
+/* Autotune the batched launch for this batch's shape class (the set of data
+ * variants in it and the order of magnitude of its ray count): renders the
+ * batch with every candidate wave tile, synchronously on `hip_stream`, into
+ * the requests' own outputs (all candidates give the same bits), keeps the
+ * fastest for later vr_render_batch calls and served batches of that class,
+ * and appends it to the VR_AUTOTUNE_CACHE file when that variable names one.
+ * Blocks the caller for about ten batch times: call it at load time.
+ * *wave_w, *wave_h (either may be NULL) receive the chosen tile. */
+vr_status vr_tune_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n, void* hip_stream,
+                        int32_t* wave_w, int32_t* wave_h);
+
 /* Queue a request for the context's serving loop and return at once with a
- * ticket.  The loop admits queued requests when a slot is free and their
- * output bytes fit in the budget, batches the admitted ones, and overlaps
- * batches on several streams.  The request (and the volume's transfer
+ * ticket (the CPU stays free while the GPU renders: Abstract; interactive
+ * navigation through time points: Results and Discussion).  The loop admits
+ * queued requests when a slot is free and their output bytes fit in the
+ * budget, batches the admitted ones, and overlaps batches on several
+ * streams.  The request (and the volume's transfer
  * functions) are copied now.  VR_ERR_BUSY when 4096 tickets are pending. */
 vr_status vr_submit(vr_ctx* ctx, const vr_render_req* req, uint64_t* ticket);
 
-/* State and timestamps of a ticket.  Tickets stay queryable until released.
- * VR_ERR_NOT_FOUND for an unknown or released ticket. */
+/* State, timestamps and composited samples of a served request.  Tickets
+ * stay queryable until released.  VR_ERR_NOT_FOUND for an unknown or released
+ * ticket. */
 vr_status vr_poll(vr_ctx* ctx, uint64_t ticket, vr_ticket_info* info);
 
-/* Forget a finished (done or failed) ticket.  VR_ERR_BUSY if it is still
- * pending or running; VR_ERR_NOT_FOUND if unknown. */
+/* Forget a finished (done or failed) ticket (serving bookkeeping).
+ * VR_ERR_BUSY if it is still pending or running; VR_ERR_NOT_FOUND if
+ * unknown. */
 vr_status vr_release(vr_ctx* ctx, uint64_t ticket);
 
 /* Message of the calling thread's last error ("" after success).  Valid
  * until the thread's next vr_* call. */
 const char* vr_last_error(void);
 
-/* Test hook: trilinear field of every channel of `frame` at n index-space
- * points pts [n][3] (x, y, z), written to out [n][channels] float32 in raw
+/* Test hook: trilinear field of every channel of `frame` (the 3-D texture
+ * sampling of the User Interface section) at n index-space points
+ * pts [n][3] (x, y, z), written to out [n][channels] float32 in raw
  * intensity units, through the renderer's own sampling code.  pts and out
  * are device pointers. */
 vr_status vr_debug_sample(vr_volume* vol, int32_t frame, const float* pts, int32_t n,

@@ -22,6 +22,7 @@ __all__ = [
     "VR_FP32", "VR_FP16", "VR_ORTHO", "VR_PERSPECTIVE", "vr_denoise_workspace_bytes",
     "vr_remove_background", "vr_mrf_denoise", "gaussian_weights", "remove_background",
     "mrf_denoise", "vr_stream_frame", "vr_stream_ready", "vr_gaussian_weights",
+    "vr_tune_batch",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvr.so")
@@ -92,7 +93,7 @@ class vr_mrf_info(C.Structure):
 class vr_ticket_info(C.Structure):
     _fields_ = [("state", C.c_int32), ("err", C.c_int32), ("t_arrive_ns", C.c_uint64),
                 ("t_admit_ns", C.c_uint64), ("t_start_ns", C.c_uint64),
-                ("t_done_ns", C.c_uint64), ("rays", C.c_uint64)]
+                ("t_done_ns", C.c_uint64), ("samples", C.c_uint64), ("rays", C.c_uint64)]
 
 
 _lib = None
@@ -104,6 +105,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        # PyTorch links its own HIP runtime under the unversioned name, so a
+        # library loaded before it would bring a second runtime into the
+        # process, and the second one to start finds no device.  Importing
+        # torch first makes libvr bind to the runtime torch already holds.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         P, S = C.c_void_p, C.c_int
         sig = {
@@ -119,6 +125,8 @@ def lib():
             "vr_set_transfer": [P, C.c_int32, C.POINTER(vr_transfer)],
             "vr_render": [P, C.POINTER(vr_render_req), P],
             "vr_render_batch": [P, C.POINTER(vr_render_req), C.c_int32, P],
+            "vr_tune_batch": [P, C.POINTER(vr_render_req), C.c_int32, P,
+                              C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
             "vr_submit": [P, C.POINTER(vr_render_req), C.POINTER(C.c_uint64)],
             "vr_poll": [P, C.c_uint64, C.POINTER(vr_ticket_info)],
             "vr_release": [P, C.c_uint64],
@@ -130,12 +138,15 @@ def lib():
                                      C.c_uint64, P],
             "vr_mrf_denoise": [P, C.POINTER(vr_grid), C.c_int32, P, P, P, C.c_uint64, P,
                                C.POINTER(vr_mrf_info)],
-            "vr_test_fake_backend": [P, C.c_int32, C.c_double, C.c_int32, C.c_int32],
+            "vr_test_fake_backend": [P, C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                     C.c_double],
             "vr_test_batch_tile": [P, C.c_int32, C.c_int32],
             "vr_test_plain_tile": [P, C.c_int32, C.c_int32],
             "vr_test_block_map": [C.c_int32, C.c_void_p],
             "vr_test_clear_skip": [P, C.c_int32],
             "vr_test_large_addressing": [P, C.c_int32],
+            "vr_test_volume_large": [P, C.POINTER(C.c_int32)],
+            "vr_test_cell_shift": [P, C.c_int32],
             "vr_test_transparent_max": [C.c_float, C.c_float, C.c_int32, C.POINTER(C.c_float),
                                         C.POINTER(C.c_float), C.POINTER(C.c_int32)],
         }
@@ -221,6 +232,16 @@ def vr_render_batch(ctx, reqs, stream=None):
     n = len(reqs)
     arr = (vr_render_req * max(n, 1))(*reqs)
     _check(lib().vr_render_batch(ctx, arr, n, _stream(stream)))
+
+
+def vr_tune_batch(ctx, reqs, stream=None):
+    """Autotune the batched launch for this batch's shape class; returns the
+    chosen (wave_w, wave_h)."""
+    n = len(reqs)
+    arr = (vr_render_req * max(n, 1))(*reqs)
+    w, h = C.c_int32(), C.c_int32()
+    _check(lib().vr_tune_batch(ctx, arr, n, _stream(stream), C.byref(w), C.byref(h)))
+    return w.value, h.value
 
 
 def vr_submit(ctx, req: vr_render_req) -> int:
@@ -350,12 +371,24 @@ def vr_test_plain_tile(ctx, wave_w=0, wave_h=0):
     _check(lib().vr_test_plain_tile(ctx, wave_w, wave_h))
 
 
-def vr_test_clear_skip(ctx, on: bool):
-    _check(lib().vr_test_clear_skip(ctx, int(bool(on))))
+def vr_test_clear_skip(ctx, on):
+    """on: False/0 no skipping, True/1 both skips (default), 2 the per-sample
+    test only (every sample walked)."""
+    _check(lib().vr_test_clear_skip(ctx, int(on)))
 
 
 def vr_test_large_addressing(ctx, on: bool):
     _check(lib().vr_test_large_addressing(ctx, int(bool(on))))
+
+
+def vr_test_cell_shift(ctx, shift: int = 3):
+    _check(lib().vr_test_cell_shift(ctx, int(shift)))
+
+
+def vr_test_volume_large(vol) -> bool:
+    out = C.c_int32()
+    _check(lib().vr_test_volume_large(vol, C.byref(out)))
+    return bool(out.value)
 
 
 def vr_test_transparent_max(lo: float, hi: float, bits: int):
@@ -375,8 +408,9 @@ def vr_test_block_map(nblocks: int):
 
 
 def vr_test_fake_backend(ctx, slots: int, ns_per_ray: float, fail_width: int = -1,
-                         max_batch: int = 32):
-    _check(lib().vr_test_fake_backend(ctx, slots, ns_per_ray, fail_width, max_batch))
+                         max_batch: int = 32, launch_ms: float = 0.0):
+    _check(lib().vr_test_fake_backend(ctx, slots, ns_per_ray, fail_width, max_batch,
+                                      float(launch_ms)))
 
 
 # ---------------------------------------------------------- record helpers
@@ -428,14 +462,14 @@ class Volume:
 
     def __init__(self, ctx: Context, dims, channels, frames=1, dtype=VR_U8, bits=None,
                  spacing=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0), brick=(0, 0, 0),
-                 row_pairs=False):
+                 row_pairs=False, storage_bytes=None):
         import torch
         nx, ny, nz = dims
         bits = bits if bits is not None else (8 if dtype == VR_U8 else 16)
         self.desc = vr_volume_desc(nx, ny, nz, channels, frames, dtype, bits,
                                    (C.c_float * 3)(*spacing), (C.c_float * 3)(*origin),
                                    (C.c_int32 * 3)(*brick), int(bool(row_pairs)))
-        self.bytes = vr_volume_storage_bytes(self.desc)
+        self.bytes = storage_bytes or vr_volume_storage_bytes(self.desc)
         self.storage = torch.empty(self.bytes + 256, dtype=torch.uint8,
                                    device=f"cuda:{ctx.device}")
         base = self.storage.data_ptr()

@@ -97,8 +97,16 @@ static BrickGeom make_geom_with(const vr_volume_desc& d, bool large) {
     g.brick = g.plane * (b[2] + 1);
     g.word = word_bytes(d.channels, d.dtype == VR_U16);
     const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
-    g.frame_bytes = (words * (uint64_t)g.word + 255u) & ~(uint64_t)255u;
+    g.cell_off = (words * (uint64_t)g.word + 255u) & ~(uint64_t)255u;
+    set_cell_shift(&g, kCellShift);
     return g;
+}
+
+void set_cell_shift(BrickGeom* g, int shift) {
+    g->cshift = shift;
+    for (int a = 0; a < 3; ++a) g->nc[a] = (g->n[a] >> shift) + 1;
+    const uint64_t cells = (uint64_t)g->nc[0] * g->nc[1] * g->nc[2];
+    g->frame_bytes = (g->cell_off + cells * (uint64_t)g->word + 255u) & ~(uint64_t)255u;
 }
 
 // Default bricks depend on whether the volume needs large-volume addressing
@@ -111,9 +119,11 @@ BrickGeom make_geom(const vr_volume_desc& d) {
 }
 
 bool needs_large(const vr_volume_desc& d, const BrickGeom& g) {
-    const uint64_t words = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2] * (uint64_t)g.brick;
+    const uint64_t bricks = (uint64_t)g.nb[0] * g.nb[1] * g.nb[2];
+    const uint64_t words = bricks * (uint64_t)g.brick;
+    // The 32-bit sampler forms brick indices with 24-bit multiply-adds.
     return d.nx > kFloatAxis || d.ny > kFloatAxis || d.nz > kFloatAxis || words >= (1ull << 31) ||
-           g.frame_bytes >= (1ull << 32);
+           bricks >= (1ull << 24) || g.frame_bytes >= (1ull << 32);
 }
 
 vr_status check_desc(const vr_volume_desc* d) {
@@ -442,6 +452,7 @@ void make_params(const vr_render_req& r, const vr_transfer* tf_in, ReqParams* P)
     D.sy_scale = 2.0 / H;
     P->width = r.width;
     P->height = r.height;
+    P->skip_cells = v.ctx->cell_skip ? 1 : 0;
     P->out = r.out_rgba;
     P->samples = r.out_samples;
 }
@@ -476,7 +487,8 @@ vr_status vr_init(int32_t device, uint64_t mem_budget_bytes, vr_ctx** out) {
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess || device >= count) {
         delete ctx;
-        return fail(VR_ERR_UNSUPPORTED, "HIP device %d is not available", device);
+        return fail(VR_ERR_UNSUPPORTED, "HIP device %d is not available (hipGetDeviceCount: %s, %d devices)",
+                    device, hipGetErrorString(e), count);
     }
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) {
@@ -535,7 +547,8 @@ vr_status vr_create_volume(vr_ctx* ctx, const vr_volume_desc* desc, void* dev_st
     if (!dev_storage) return fail(VR_ERR_INVALID_ARG, "device storage is NULL");
     if (((uintptr_t)dev_storage & 255u) != 0)
         return fail(VR_ERR_INVALID_ARG, "device storage must be 256-byte aligned");
-    const BrickGeom g = make_geom(*desc);
+    BrickGeom g = make_geom(*desc);
+    if (ctx->cell_shift != kCellShift) set_cell_shift(&g, ctx->cell_shift);
     const uint64_t need = g.frame_bytes * (uint64_t)desc->frames;
     if (storage_bytes < need)
         return fail(VR_ERR_OUT_OF_MEMORY, "storage holds %llu bytes, the volume needs %llu",

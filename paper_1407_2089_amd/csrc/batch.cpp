@@ -116,9 +116,14 @@ BatchSlot* batch_slot_for(vr_ctx* ctx, hipStream_t stream, vr_status* st) {
     return s;
 }
 
-static vr_status graph_for(BatchSlot* s, uint64_t mask, int blocks, hipGraphExec_t* out) {
-    // variants present (48 bits) and the grid size (a power of two <= 2^17)
-    const uint64_t key = mask << 16 | (uint64_t)(31 - __builtin_clz((unsigned)blocks));
+// The batch's kernels, one per variant present with its own grid, as
+// parallel branches of one graph (built node by node), instantiated once per
+// (variants present, grid sizes).
+static vr_status graph_for(BatchSlot* s, uint64_t mask, const int32_t* blocks,
+                           hipGraphExec_t* out) {
+    std::string key;
+    for (int v = 0; v < kBatchVariants; ++v)
+        if (mask & (1ull << v)) key += std::to_string(v) + ":" + std::to_string(blocks[v]) + ",";
     auto it = s->graphs.find(key);
     if (it != s->graphs.end()) {
         *out = it->second.second;
@@ -126,15 +131,13 @@ static vr_status graph_for(BatchSlot* s, uint64_t mask, int blocks, hipGraphExec
     }
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipError_t e = hipStreamBeginCapture(s->capture, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t le = launch_batch(s->d_work, s->d_reqs, s->d_prefix, mask, blocks, s->capture);
-    e = hipStreamEndCapture(s->capture, &graph);
-    if (le != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return hip_fail(le, "batch launch capture");
+    hipError_t e = hipGraphCreate(&graph, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+    e = add_batch_nodes(graph, s->d_work, s->d_reqs, s->d_prefix, mask, blocks);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "batch graph nodes");
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
         (void)hipGraphDestroy(graph);
@@ -191,18 +194,51 @@ static void save_tuning(uint64_t key, const TileShape& t) {
 static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
                               const TileShape& ts);
 
-// Times every candidate on this batch (synchronously, on the slot's stream)
-// and keeps the fastest for the batch's shape class.
-static vr_status tune(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n, uint64_t key,
-                      TileShape* best) {
+// Lit requests and large volumes take plain launches on the slot's stream
+// (the batch kernels are unlit and 32-bit addressed); the rest form the
+// batch, returned in `rest`.
+static vr_status launch_plain_part(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
+                                   std::vector<ReqParams>* rest) {
+    rest->clear();
+    for (int q = 0; q < n; ++q) {
+        const ReqParams& P = params[q];
+        if (P.light.on == 0 && !variant_large(P.variant)) {
+            rest->push_back(P);
+            continue;
+        }
+        const hipError_t e = launch_render(P, ctx->plain_tile, ctx->clear_skip, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "render launch");
+    }
+    return VR_OK;
+}
+
+static void ensure_tuning_cache(vr_ctx* ctx) {
+    // caller holds ctx->mu
+    if (!ctx->tuning_cache_loaded) {
+        load_tuning_cache(ctx);
+        ctx->tuning_cache_loaded = true;
+    }
+}
+
+vr_status batch_tune(vr_ctx* ctx, BatchSlot* s, const ReqParams* params_in, int n,
+                     TileShape* best) {
+    std::vector<ReqParams> rest;
+    vr_status st = launch_plain_part(ctx, s, params_in, n, &rest);
+    if (st != VR_OK) return st;
+    *best = ctx->batch_tile;
+    if (rest.empty()) return VR_OK;
+    const ReqParams* params = rest.data();
+    n = (int)rest.size();
+    const uint64_t key = shape_class(params, n);
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return fail(VR_ERR_DEVICE, "autotune event");
     if (hipEventCreate(&b) != hipSuccess) {
         (void)hipEventDestroy(a);
         return fail(VR_ERR_DEVICE, "autotune event");
     }
+    // No lock is held while the candidates run: the tuned map is read and
+    // written under ctx->mu only.
     float best_ms = 1e30f;
-    vr_status st = VR_OK;
     for (const TileShape& c : kCandidates) {
         float ms_total = 0.0f;
         for (int rep = 0; rep < 2 && st == VR_OK; ++rep) {  // first run warms caches
@@ -225,72 +261,94 @@ static vr_status tune(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    if (st == VR_OK) {
+    if (st != VR_OK) return st;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ensure_tuning_cache(ctx);
         ctx->tuned[key] = *best;
-        save_tuning(key, *best);
     }
-    return st;
+    save_tuning(key, *best);
+    return VR_OK;
 }
 
-vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
-                        bool allow_tuning) {
+vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n) {
     if (n <= 0) return VR_OK;
-    // Lit requests and large volumes take plain launches on the slot's stream
-    // (the batch kernels are unlit and 32-bit addressed); the rest form the
-    // batch.
-    const auto plain = [](const ReqParams& P) {
-        return P.light.on != 0 || variant_large(P.variant);
-    };
-    std::vector<ReqParams> unlit;
+    std::vector<ReqParams> rest;
     bool any_plain = false;
-    for (int q = 0; q < n && !any_plain; ++q) any_plain = plain(params[q]);
+    for (int q = 0; q < n && !any_plain; ++q)
+        any_plain = params[q].light.on != 0 || variant_large(params[q].variant);
     if (any_plain) {
-        for (int q = 0; q < n; ++q) {
-            if (!plain(params[q])) {
-                unlit.push_back(params[q]);
-                continue;
-            }
-            const hipError_t e = launch_render(params[q], ctx->plain_tile, ctx->clear_skip,
-                                               s->stream);
-            if (e != hipSuccess) return hip_fail(e, "render launch");
-        }
-        params = unlit.data();
-        n = (int)unlit.size();
+        vr_status st = launch_plain_part(ctx, s, params, n, &rest);
+        if (st != VR_OK) return st;
+        params = rest.data();
+        n = (int)rest.size();
         if (n == 0) return VR_OK;
     }
     TileShape ts = ctx->batch_tile;
     if (!ctx->forced_tile && ctx->autotune) {
         const uint64_t key = shape_class(params, n);
-        std::unique_lock<std::mutex> lk(ctx->mu);
-        if (!ctx->tuning_cache_loaded) {
-            load_tuning_cache(ctx);
-            ctx->tuning_cache_loaded = true;
-        }
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ensure_tuning_cache(ctx);
         auto it = ctx->tuned.find(key);
-        if (it != ctx->tuned.end()) {
-            ts = it->second;
-        } else if (allow_tuning) {
-            vr_status st = tune(ctx, s, params, n, key, &ts);
-            if (st != VR_OK) return st;
-        }
+        if (it != ctx->tuned.end()) ts = it->second;
     }
     return enqueue_with(ctx, s, params, n, ts);
+}
+
+// Lays out the device tables of a batch in host memory (no allocation:
+// `order` and `cost` hold n entries of the caller's): requests grouped by data variant
+// (one kernel each), most expensive first within a group (a stable insertion
+// sort; batches are small), each request's first work item within its group,
+// and each variant's grid: its item count rounded up to a power of two (a
+// few instantiated graphs cover all batch sizes), at least one wave's worth
+// and at most kBatchBlocksMax, so that a block takes a handful of items of a
+// large group.  Returns VR_OK with *mask = 0 when no request has pixels.
+static vr_status build_tables(const ReqParams* params, int n, const TileShape& ts, int* order,
+                              double* cost, ReqParams* h_reqs, int32_t* h_prefix, BatchWork* w,
+                              uint64_t* mask, int32_t* blocks) {
+    for (int q = 0; q < n; ++q) cost[q] = request_cost(params[q]);
+    for (int q = 0; q < n; ++q) {
+        int i = q;
+        while (i > 0) {
+            const int o = order[i - 1];
+            const bool after = params[o].variant > params[q].variant ||
+                               (params[o].variant == params[q].variant && cost[o] < cost[q]);
+            if (!after) break;
+            order[i] = order[i - 1];
+            --i;
+        }
+        order[i] = q;
+    }
+    std::memset(w->group, 0, sizeof w->group);
+    *mask = 0;
+    int64_t items = 0;
+    for (int q = 0; q < n; ++q) {
+        const ReqParams& P = params[order[q]];
+        BatchGroup& g = w->group[P.variant];
+        if (g.n_req == 0) {
+            g.first = q;
+            items = 0;
+        }
+        h_reqs[q] = P;
+        h_prefix[q] = (int32_t)items;
+        items += tiles_per_eye(P.width, P.height, ts) * P.eyes;
+        if (items > (1 << 30)) return fail(VR_ERR_INVALID_ARG, "batch has too many tiles");
+        g.n_req += 1;
+        g.n_items = (int32_t)items;
+        if (items > 0) *mask |= 1ull << P.variant;
+    }
+    w->tile = ts;
+    for (int v = 0; v < kBatchVariants; ++v) {
+        int32_t b = kWave;
+        while (b < w->group[v].n_items && b < kBatchBlocksMax) b *= 2;
+        blocks[v] = (*mask & (1ull << v)) ? b : 0;
+    }
+    return VR_OK;
 }
 
 static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params, int n,
                               const TileShape& ts) {
     hipError_t e;
-    // Group by data variant (one persistent kernel each), most expensive
-    // request first within a group.
-    std::vector<int> order(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost(n);
-    for (int q = 0; q < n; ++q) cost[q] = request_cost(params[q]);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (params[a].variant != params[b].variant) return params[a].variant < params[b].variant;
-        return cost[a] > cost[b];
-    });
-
     if (n > s->capacity) {
         int cap = s->capacity;
         while (cap < n) cap *= 2;
@@ -303,34 +361,13 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
         if ((e = hipEventSynchronize(s->staged)) != hipSuccess) return hip_fail(e, "staging wait");
         s->staged_pending = false;
     }
-    BatchWork* w = s->h_work;
-    std::memset(w->group, 0, sizeof w->group);
+    std::vector<int> order((size_t)n);
+    std::vector<double> cost((size_t)n);
     uint64_t mask = 0;
-    int64_t items = 0;
-    for (int q = 0; q < n; ++q) {
-        const ReqParams& P = params[order[q]];
-        BatchGroup& g = w->group[P.variant];
-        if (g.n_req == 0) {
-            g.first = q;
-            items = 0;
-        }
-        s->h_reqs[q] = P;
-        s->h_prefix[q] = (int32_t)items;
-        items += tiles_per_eye(P.width, P.height, ts) * P.eyes;
-        if (items > (1 << 30)) return fail(VR_ERR_INVALID_ARG, "batch has too many tiles");
-        g.n_req += 1;
-        g.n_items = (int32_t)items;
-        if (items > 0) mask |= 1ull << P.variant;
-    }
-    if (mask == 0) return VR_OK;
-    w->tile = ts;
-    // Grid of every variant's kernel: the largest group's item count rounded
-    // up to a power of two (a few captured graphs cover all batch sizes),
-    // capped so that a block takes a handful of items of a large batch.
-    int64_t most = 0;
-    for (int v = 0; v < kBatchVariants; ++v) most = std::max<int64_t>(most, w->group[v].n_items);
-    int blocks = kWave;
-    while (blocks < most && blocks < kBatchBlocksMax) blocks *= 2;
+    int32_t blocks[kBatchVariants];
+    vr_status st = build_tables(params, n, ts, order.data(), cost.data(), s->h_reqs, s->h_prefix,
+                                s->h_work, &mask, blocks);
+    if (st != VR_OK || mask == 0) return st;
     if ((e = hipMemcpyAsync(s->d_reqs, s->h_reqs, sizeof(ReqParams) * (size_t)n,
                             hipMemcpyHostToDevice, s->stream)) != hipSuccess ||
         (e = hipMemcpyAsync(s->d_prefix, s->h_prefix, sizeof(int32_t) * (size_t)n,
@@ -343,7 +380,7 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
 
     if (ctx->use_graphs) {
         hipGraphExec_t exec = nullptr;
-        vr_status st = graph_for(s, mask, blocks, &exec);
+        st = graph_for(s, mask, blocks, &exec);
         if (st != VR_OK) return st;
         if ((e = hipGraphLaunch(exec, s->stream)) != hipSuccess)
             return hip_fail(e, "hipGraphLaunch");
@@ -386,7 +423,9 @@ extern "C" vr_status vr_test_plain_tile(vr_ctx* ctx, int32_t wave_w, int32_t wav
 
 extern "C" vr_status vr_test_clear_skip(vr_ctx* ctx, int32_t on) {
     if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    if (on < 0 || on > 2) return fail(VR_ERR_INVALID_ARG, "on must be 0, 1 or 2");
     ctx->clear_skip = on != 0;
+    ctx->cell_skip = on == 1;
     return ok();
 }
 
@@ -396,8 +435,23 @@ extern "C" vr_status vr_test_large_addressing(vr_ctx* ctx, int32_t on) {
     return ok();
 }
 
-extern "C" vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
-                                     void* hip_stream) {
+extern "C" vr_status vr_test_cell_shift(vr_ctx* ctx, int32_t shift) {
+    if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    if (shift < 2 || shift > 5) return fail(VR_ERR_INVALID_ARG, "cell shift %d outside 2..5", shift);
+    ctx->cell_shift = shift;
+    return ok();
+}
+
+extern "C" vr_status vr_test_volume_large(const vr_volume* vol, int32_t* large) {
+    if (!vol || !large) return fail(VR_ERR_INVALID_ARG, "volume or out is NULL");
+    *large = vol->large ? 1 : 0;
+    return ok();
+}
+
+// Validation and parameter snapshot shared by vr_render_batch and
+// vr_tune_batch.
+static vr_status batch_params(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
+                              std::vector<ReqParams>* P) {
     if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
     if (n < 0) return fail(VR_ERR_INVALID_ARG, "n < 0");
     if (n > 0 && !reqs) return fail(VR_ERR_INVALID_ARG, "requests are NULL");
@@ -409,17 +463,42 @@ extern "C" vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int
         }
     }
     if (ctx->device < 0) return fail(VR_ERR_UNSUPPORTED, "validation-only context");
-    if (n == 0) return ok();
-    std::vector<ReqParams> P((size_t)n);
+    P->resize((size_t)n);
     for (int q = 0; q < n; ++q) {
         std::lock_guard<std::mutex> lk(reqs[q].vol->tf_mu);
-        make_params(reqs[q], reqs[q].vol->tf, &P[q]);
+        make_params(reqs[q], reqs[q].vol->tf, &(*P)[q]);
     }
+    return VR_OK;
+}
+
+extern "C" vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
+                                     void* hip_stream) {
+    std::vector<ReqParams> P;
+    vr_status st = batch_params(ctx, reqs, n, &P);
+    if (st != VR_OK) return st;
+    if (n == 0) return ok();
     DeviceGuard dg(ctx->device);
-    vr_status st;
     BatchSlot* s = batch_slot_for(ctx, (hipStream_t)hip_stream, &st);
     if (!s) return st;
     st = batch_enqueue(ctx, s, P.data(), n);
     if (st != VR_OK) return st;
+    return ok();
+}
+
+extern "C" vr_status vr_tune_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
+                                   void* hip_stream, int32_t* wave_w, int32_t* wave_h) {
+    std::vector<ReqParams> P;
+    vr_status st = batch_params(ctx, reqs, n, &P);
+    if (st != VR_OK) return st;
+    TileShape best = ctx->batch_tile;
+    if (n > 0) {
+        DeviceGuard dg(ctx->device);
+        BatchSlot* s = batch_slot_for(ctx, (hipStream_t)hip_stream, &st);
+        if (!s) return st;
+        st = batch_tune(ctx, s, P.data(), n, &best);
+        if (st != VR_OK) return st;
+    }
+    if (wave_w) *wave_w = best.wave_w;
+    if (wave_h) *wave_h = best.wave_h;
     return ok();
 }

@@ -34,10 +34,16 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
 // in full (same output bits).
 hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_skip,
                          hipStream_t s);
-// Launch the batch kernels of the variants set in `mask`, `blocks`
-// single-wave blocks each.
+// Launch the batch kernels of the variants set in `mask`, blocks[v]
+// single-wave blocks for variant v, one after the other on `s`.
 hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
-                        const int32_t* dev_prefix, uint64_t mask, int blocks, hipStream_t s);
+                        const int32_t* dev_prefix, uint64_t mask, const int32_t* blocks,
+                        hipStream_t s);
+// The same kernels as independent nodes of `graph` (parallel branches: the
+// variants' kernels may overlap on the device).
+hipError_t add_batch_nodes(hipGraph_t graph, const BatchWork* dev_work,
+                           const ReqParams* dev_reqs, const int32_t* dev_prefix, uint64_t mask,
+                           const int32_t* blocks);
 hipError_t launch_debug_sample(const ReqParams& P, const float* pts, int n, float* out,
                                hipStream_t s);
 

@@ -181,6 +181,44 @@ __global__ __launch_bounds__(kRelayoutThreads) void relayout_scatter_kernel(
     }
 }
 
+// ------------------------------------------------------- macro-cell maxima
+// One thread per macro cell (grid x over cells along x, y and z one block row
+// per cell): per channel, the largest clamped voxel value over stored
+// coordinates [c M, c M + M] per axis, that is voxel indices
+// [c M - 1, c M + M - 1] clipped to the grid (the zero padding never raises a
+// maximum), packed like a voxel word at the frame's cell table.  A wave's
+// lanes read x runs M voxels apart, so one wave-wide load touches a few
+// consecutive cache lines.
+template <int C, bool U16>
+__global__ __launch_bounds__(256) void cellmax_kernel(BrickGeom g, const void* __restrict__ src,
+                                                      uint8_t* __restrict__ frame, uint32_t maxval) {
+    using T = typename WordT<C, U16>::T;
+    using S = typename std::conditional<U16, uint16_t, uint8_t>::type;
+    const S* in = reinterpret_cast<const S*>(src);
+    const int cx = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int cy = (int)blockIdx.y, cz = (int)blockIdx.z;
+    if (cx >= g.nc[0]) return;
+    const int M = 1 << g.cshift;
+    const int x0 = max((cx << g.cshift) - 1, 0), x1 = min((cx << g.cshift) + M - 1, g.n[0] - 1);
+    const int y0 = max((cy << g.cshift) - 1, 0), y1 = min((cy << g.cshift) + M - 1, g.n[1] - 1);
+    const int z0 = max((cz << g.cshift) - 1, 0), z1 = min((cz << g.cshift) + M - 1, g.n[2] - 1);
+    const size_t plane = (size_t)g.n[0] * g.n[1];
+    const size_t vol = plane * g.n[2];
+    uint32_t ch[kMaxChannels] = {};
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        uint32_t m = 0;
+        for (int k = z0; k <= z1; ++k)
+            for (int j = y0; j <= y1; ++j) {
+                const S* row = in + (size_t)c * vol + (size_t)k * plane + (size_t)j * g.n[0];
+                for (int i = x0; i <= x1; ++i) m = max(m, (uint32_t)row[i]);
+            }
+        ch[c] = m > maxval ? maxval : m;
+    }
+    T* cells = reinterpret_cast<T*>(frame + g.cell_off);
+    cells[((size_t)cz * g.nc[1] + cy) * g.nc[0] + cx] = pack_word<C, U16>(ch);
+}
+
 // ------------------------------------------------------------ plain render
 // Grid: one single-wave block per (eye, wave_w x wave_h pixel tile).  Blocks
 // of one wave let the dispatcher refill a SIMD as soon as any wave's rays
@@ -219,9 +257,9 @@ __global__ __launch_bounds__(kWave) void render_kernel(ReqParams P, TileShape ts
 // -------------------------------------------------------- batched render
 // Work items are (request, eye, wave tile) triples numbered request by
 // request in the order the host laid the requests out (most expensive
-// first); prefix[q] is the first item of request q.  Each wave pulls items
-// from a global counter until none are left: every wave reaches the exit once
-// the counter passes n_items.
+// first); prefix[q] is the first item of request q.  Block b takes items
+// b, b + grid, b + 2 grid, ... of its variant's group (after the XCD remap)
+// and leaves past the group's last item; there is no shared counter.
 __device__ __forceinline__ int find_req(const int32_t* __restrict__ prefix, int n, int item) {
     int lo = 0, hi = n - 1;  // largest q with prefix[q] <= item
     while (lo < hi) {
@@ -317,6 +355,8 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
     const uint64_t blocks64 = (words + 255) / 256;
     const unsigned gblocks = (unsigned)(blocks64 > 65536 ? 65536 : blocks64);
     const bool gather = g.shift[0] >= 3;  // bricks at least 8 voxels wide
+    if (g.nc[1] > 65535 || g.nc[2] > 65535) return hipErrorInvalidValue;
+    const dim3 cgrid(((unsigned)g.nc[0] + 255u) / 256u, (unsigned)g.nc[1], (unsigned)g.nc[2]);
 #define VR_RL(C, U)                                                                       \
     if (channels == C && u16 == U) {                                                      \
         if (gather)                                                                       \
@@ -325,6 +365,9 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
         else                                                                              \
             hipLaunchKernelGGL((relayout_scatter_kernel<C, U>), grid, dim3(kRelayoutThreads), 0, s, g, \
                                src, dst, maxval);                                         \
+        hipError_t e = hipGetLastError();                                                 \
+        if (e != hipSuccess) return e;                                                    \
+        hipLaunchKernelGGL((cellmax_kernel<C, U>), cgrid, dim3(256), 0, s, g, src, dst, maxval); \
         return hipGetLastError();                                                         \
     }
     VR_RL(1, false) VR_RL(2, false) VR_RL(3, false) VR_RL(4, false) VR_RL(5, false)
@@ -368,15 +411,37 @@ hipError_t launch_render(const ReqParams& P, const TileShape& ts, bool clear_ski
 }
 
 hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
-                        const int32_t* dev_prefix, uint64_t mask, int blocks, hipStream_t s) {
-    if (blocks <= 0) return hipErrorInvalidValue;
+                        const int32_t* dev_prefix, uint64_t mask, const int32_t* blocks,
+                        hipStream_t s) {
     if (mask >> kBatchVariants) return hipErrorInvalidValue;
     for (int v = 0; v < kBatchVariants; ++v) {
         if (!(mask & (1ull << v))) continue;
-        if (!kBatch[v]) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(kBatch[v], dim3(blocks), dim3(kWave), 0, s, dev_work, dev_reqs,
+        if (!kBatch[v] || blocks[v] <= 0) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(kBatch[v], dim3(blocks[v]), dim3(kWave), 0, s, dev_work, dev_reqs,
                            dev_prefix);
         const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t add_batch_nodes(hipGraph_t graph, const BatchWork* dev_work,
+                           const ReqParams* dev_reqs, const int32_t* dev_prefix, uint64_t mask,
+                           const int32_t* blocks) {
+    if (mask >> kBatchVariants) return hipErrorInvalidValue;
+    for (int v = 0; v < kBatchVariants; ++v) {
+        if (!(mask & (1ull << v))) continue;
+        if (!kBatch[v] || blocks[v] <= 0) return hipErrorInvalidValue;
+        void* args[3] = {(void*)&dev_work, (void*)&dev_reqs, (void*)&dev_prefix};
+        hipKernelNodeParams np{};
+        np.func = (void*)kBatch[v];
+        np.gridDim = dim3((unsigned)blocks[v]);
+        np.blockDim = dim3(kWave);
+        np.sharedMemBytes = 0;
+        np.kernelParams = args;
+        np.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        const hipError_t e = hipGraphAddKernelNode(&node, graph, nullptr, 0, &np);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

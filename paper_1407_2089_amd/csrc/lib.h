@@ -52,7 +52,8 @@ struct BatchSlot {
     bool staged_pending = false;
     // Captured launches, one per (set of variants present, grid size) of a
     // batch (they hold the table addresses: dropped when the tables grow).
-    std::map<uint64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // key: the variants present and each one's grid size
+    std::map<std::string, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
 // Sets the calling thread's error message and returns `st`.
@@ -101,7 +102,9 @@ struct vr_ctx {
     vr::TileShape batch_tile{8, 8};
     vr::TileShape plain_tile{8, 8};  // wave tile of vr_render launches
     bool clear_skip = true;  // vr_render leaves out transparent samples' arithmetic
+    bool cell_skip = true;   // rays jump over macro cells shown transparent
     bool force_large = false;  // new volumes take large-volume addressing (test hook)
+    int cell_shift = vr::kCellShift;  // macro-cell edge of new volumes (test hook)
     std::map<uint64_t, vr::TileShape> tuned;
     vr::Scheduler* server = nullptr;  // created by the first vr_submit (server.cpp)
     std::mutex server_mu;
@@ -113,8 +116,11 @@ namespace vr {
 vr_status check_desc(const vr_volume_desc* d);
 vr_status check_request(const vr_ctx* ctx, const vr_render_req* r);
 BrickGeom make_geom(const vr_volume_desc& d);
+// Macro cells of 2^shift sample corners per axis: cell counts, frame size.
+void set_cell_shift(BrickGeom* g, int shift);
 // True when the volume needs large-volume addressing: an axis above
-// kFloatAxis voxels, or a frame of 2^31 stored words or 4 GiB and more.
+// kFloatAxis voxels, or a frame of 2^31 stored words, 2^24 bricks or 4 GiB
+// and more.
 bool needs_large(const vr_volume_desc& d, const BrickGeom& g);
 // Clamp bounds of the FP64 sample positions (large variants).
 void set_clamp_d64(const BrickGeom& g, ReqParams* P);
@@ -124,8 +130,13 @@ void make_params(const vr_render_req& r, const vr_transfer* tf, ReqParams* P);
 TileShape default_tile();
 
 // Batched path (batch.cpp).
-vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* slot, const ReqParams* params, int n,
-                        bool allow_tuning = true);
+// Enqueues a batch with the tile tuned for its shape class (or the default);
+// never tunes and never waits for the device beyond its staging buffers.
+vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* slot, const ReqParams* params, int n);
+// Times every candidate tile on this batch (synchronously) and records the
+// fastest for its shape class.
+vr_status batch_tune(vr_ctx* ctx, BatchSlot* slot, const ReqParams* params, int n,
+                     TileShape* best);
 BatchSlot* batch_slot_for(vr_ctx* ctx, hipStream_t stream, vr_status* st);
 BatchSlot* batch_slot_create(vr_ctx* ctx, hipStream_t stream, vr_status* st);
 void batch_slot_destroy(BatchSlot* slot);

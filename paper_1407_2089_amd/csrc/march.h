@@ -178,6 +178,7 @@ struct Sampler {
     uint32_t row_b;     // bytes per brick row
     uint32_t plane_b;   // bytes per brick plane
     uint32_t diag_b;    // row_b + plane_b
+    uint32_t cell_b;    // byte offset of the macro-cell table
 };
 
 __device__ __forceinline__ Sampler make_sampler(const uint8_t* vox, const BrickGeom& g) {
@@ -188,6 +189,7 @@ __device__ __forceinline__ Sampler make_sampler(const uint8_t* vox, const BrickG
     S.row_b = (uint32_t)(g.row * g.word);
     S.plane_b = (uint32_t)(g.plane * g.word);
     S.diag_b = S.row_b + S.plane_b;
+    S.cell_b = (uint32_t)g.cell_off;
     return S;
 }
 
@@ -254,6 +256,26 @@ template <> __device__ __forceinline__ Quad<uint2> load_quad_global<uint2>(const
                         make_uint2(b.z, b.w)}};
 }
 
+// Low corner floor(q) of the taps of a point given in stored coordinates,
+// after the clamp into [0, n + 1): the same two instructions (or FP64
+// operations) the fetch below performs, so that both agree on every point.
+__device__ __forceinline__ uint32_t corner(const Sampler& S, float q, int a) {
+    return (uint32_t)cvt_floor(__builtin_amdgcn_fmed3f(q, 0.0f, S.hi[a]));
+}
+__device__ __forceinline__ uint32_t corner(const SamplerL& S, double q, int a) {
+    return (uint32_t)__builtin_floor(__builtin_fmin(__builtin_fmax(q, 0.0), S.hi[a]));
+}
+
+// Word `idx` of the frame's macro-cell table.
+template <typename T>
+__device__ __forceinline__ T load_cell(const BrickGeom& g, const Sampler& S, uint32_t idx) {
+    return load_word<T>(S.rsrc, idx * (uint32_t)sizeof(T), S.cell_b);
+}
+template <typename T>
+__device__ __forceinline__ T load_cell(const BrickGeom& g, const SamplerL& S, uint32_t idx) {
+    return load_global<T>(S.vox + g.cell_off + (uint64_t)idx * sizeof(T));
+}
+
 // The 2x2x2 taps around one sample point, in flight or landed.
 template <typename T> struct Taps {
     T w000, w100, w010, w110, w001, w101, w011, w111;
@@ -268,8 +290,10 @@ template <typename T> struct Taps {
 // about (n + 1) * 6e-8 voxels, inside the face where the field is zero).  The low corner floor(q) then
 // lies in [0, n], so every tap is inside the frame; floor and fraction come
 // from the same value, so they always agree.  Every factor and partial sum of
-// the word index is below 2^24 (a frame holds < 2^31 words and a brick >= 125
-// of them), so 24-bit multiply-adds are exact.
+// the brick index is below 2^24 (a frame with 2^24 bricks or more takes the
+// large-volume sampler), and so is every in-brick word index, so 24-bit
+// multiply-adds are exact; the brick's first word, below 2^31, fits the low
+// 32 bits of the 24-bit product.
 template <typename T, bool PAIRS>
 __device__ __forceinline__ Taps<T> fetch(const BrickGeom& g, const Sampler& S, float qx,
                                          float qy, float qz) {
@@ -383,9 +407,16 @@ __device__ __forceinline__ double fma_r(double a, double b, double c) {
     return __builtin_fma(a, b, c);
 }
 
+__device__ __forceinline__ float ceil_r(float x) { return ceilf(x); }
+__device__ __forceinline__ double ceil_r(double x) { return __builtin_ceil(x); }
+
 __device__ __forceinline__ float lerp(float a, float b, float f) { return fmaf(f, b - a, a); }
+// An explicit fused multiply-add: left to floating-point contraction, the
+// compiler may fuse the product in one kernel and round it in another, and
+// kernels that must agree bit for bit (with and without the skips, plain and
+// batched) would not.
 __device__ __forceinline__ half2_t lerp(half2_t a, half2_t b, half2_t f) {
-    return f * (b - a) + a;
+    return __builtin_elementwise_fma(f, b - a, a);
 }
 
 // Trilinear field (raw units) of every channel from landed taps.  kLerp
@@ -449,8 +480,15 @@ __device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
         unpack_f16<C, U16>(t.w101, a101);
         unpack_f16<C, U16>(t.w011, a011);
         unpack_f16<C, U16>(t.w111, a111);
-        const _Float16 ex = (_Float16)fx, ey = (_Float16)fy, ez = (_Float16)fz;
-        const half2_t hx = {ex, ex}, hy = {ey, ey}, hz = {ez, ez};
+        // The fractions go to FP16 through one explicit conversion (round
+        // toward zero, both halves at once).  A plain cast would let the
+        // compiler merge a fraction rounded from FP64 to FP32 (large volumes)
+        // and then to FP16 into one direct FP64 to FP16 rounding in some
+        // inlined copies and not in others: the two round differently at
+        // ties, and kernels that must agree bit for bit would not.
+        const half2_t hx = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(fx, fx));
+        const half2_t hy = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(fy, fy));
+        const half2_t hz = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(fz, fz));
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
             half2_t c00 = lerp(a000[q], a100[q], hx);
@@ -528,6 +566,14 @@ __device__ __forceinline__ bool transparent(const Taps<T>& t, const Transparent&
         }
         return clear;
     }
+}
+
+// True when a macro cell's per-channel maxima pass the transparent test:
+// every sample whose low corner lies in the cell then has opacity exactly 0.
+template <int C, bool U16, typename T>
+__device__ __forceinline__ bool cell_clear(T w, const Transparent& z) {
+    const Taps<T> t{w, w, w, w, w, w, w, w, 0.0f, 0.0f, 0.0f};
+    return transparent<C, U16>(t, z);
 }
 
 // Trilinear field (raw units) of every channel at index-space point p.
@@ -756,27 +802,98 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         return fetch<Word, PAIRS>(P.g, S, fma_r(sj, d[0], pe[0]), fma_r(sj, d[1], pe[1]),
                                   fma_r(sj, d[2], pe[2]));
     };
+    // Empty-space skipping over macro cells (exact).  A lane marches through
+    // segments: at a segment boundary (k >= kend) it looks up the macro cell
+    // of sample k.  A cell shown transparent (its channel maxima all at or
+    // below the thresholds) lets the lane jump past the samples whose low
+    // corner lies in the cell, without loading their taps: each of them has
+    // opacity exactly 0, so leaving it out changes no output bit and no
+    // sample count.  Otherwise the cell's samples form the next segment,
+    // composited one by one.  A cell's samples are one run of indices: per
+    // axis, the clamped and floored position fma(fma(j, step, h), d, pe) is
+    // monotone in j, so when samples k and jl both have their corner in the
+    // cell, all between do.  jl comes from the cell's exit distance, folded
+    // per axis into one multiply-add in sample-index units; it is checked
+    // with the fetch's own arithmetic, and a failed check keeps sample k
+    // alone.  One cell step per lane and iteration bounds the work a wave
+    // spends on lanes that are between cells.
+    const bool cells_on = clear_ok && P.skip_cells != 0;
+    const uint32_t cs = (uint32_t)P.g.cshift;
+    R ex_mul[3], ex_add[3];  // crossing of stored coordinate b: index b ex_mul + ex_add
+    {
+        const R inv_step = (R)1 / step;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const R inv_d = d[a] != (R)0 ? (R)1 / d[a] : (R)0;
+            ex_mul[a] = inv_d * inv_step;
+            ex_add[a] = (-pe[a] * inv_d - half_step) * inv_step;
+        }
+    }
+    auto cell_of = [&](int j, uint32_t (&c)[3]) {
+        const R sj = fma_r((R)j, step, half_step);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) c[a] = corner(S, fma_r(sj, d[a], pe[a]), a) >> cs;
+    };
+    int count = n;
+    int kend = cells_on ? 0 : n;  // samples below kend lie in a non-transparent cell
     if (n > 0) {
         // Software pipeline over pairs of samples: the taps of the next
-        // sample are always in flight while the current one is interpolated
-        // and composited.  The pair's second sample is left out on lanes that
-        // finished on its first, so the only exit is at the end of the pair (a divergent loop: finished lanes are
-        // masked off and the wave leaves when none is live).  At equal sample
-        // index a wave's sample points lie on a patch parallel to the face its
-        // rays entered through, which the brick layout serves with few cache
-        // lines.  A fetch past a lane's last sample reads a clamped, in-frame
-        // address and is unused.
+        // sample are in flight while the current one is interpolated and
+        // composited, and the pair after is requested before the second is
+        // composited.  A lane's last sample of a segment leaves the second
+        // slot empty; the loop exits at the end of an iteration (a divergent
+        // loop: finished lanes are masked off and the wave leaves when none
+        // is live).  At equal sample index a wave's sample points lie on a
+        // patch parallel to the face its rays entered through, which the
+        // brick layout serves with few cache lines.  A fetch past a lane's
+        // last sample reads a clamped, in-frame address and is unused.
+        // `count` is the sample count: n, or one past the sample at which
+        // the opacity reached tau.
+        int ka = k;  // the sample whose taps `a` holds
         Taps<Word> a = fetch_at(k);
         bool live;
         do {
-            const Taps<Word> b = fetch_at(k + 1);
-            composite(a, true, k);
-            ++k;
-            const bool on = k < n && A < tau;
-            a = fetch_at(k + 1);
-            composite(b, on, k);
-            k += on ? 1 : 0;
-            live = on && k < n && A < tau;
+            if (k >= kend) {
+                uint32_t c[3];
+                cell_of(k, c);
+                const uint32_t idx =
+                    (c[2] * (uint32_t)P.g.nc[1] + c[1]) * (uint32_t)P.g.nc[0] + c[0];
+                const Word w = load_cell<Word>(P.g, S, idx);
+                R jx = (R)n;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    if (d[ax] != (R)0) {
+                        const R bound = (R)((d[ax] > (R)0 ? c[ax] + 1u : c[ax]) << cs);
+                        const R t = fma_r(bound, ex_mul[ax], ex_add[ax]);
+                        jx = t < jx ? t : jx;
+                    }
+                }
+                int jl = jx > (R)k ? (int)ceil_r(jx) - 1 : k;
+                jl = jl < k ? k : (jl > n - 1 ? n - 1 : jl);
+                if (jl > k) {
+                    uint32_t e[3];
+                    cell_of(jl, e);
+                    if (e[0] != c[0] || e[1] != c[1] || e[2] != c[2]) jl = k;
+                }
+                if (cell_clear<C, U16>(w, P.clear)) k = jl + 1;
+                else kend = jl + 1;
+            }
+            if (k < kend) {
+                if (ka != k) {
+                    a = fetch_at(k);
+                    ka = k;
+                }
+                const Taps<Word> b = fetch_at(k + 1);
+                composite(a, true, k);
+                if (A >= tau) count = k + 1;
+                const bool on = A < tau && k + 1 < kend;
+                ka = on ? k + 2 : k + 1;
+                a = fetch_at(ka);
+                composite(b, on, k + 1);
+                if (on && A >= tau) count = k + 2;
+                k = ka;
+            }
+            live = k < n && A < tau;
         } while (live);
     }
 
@@ -789,7 +906,15 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         o.w = fmaf(T, P.bg[3], A);
         const size_t pix = ((size_t)eye * P.height + py) * P.width + px;
         reinterpret_cast<float4*>(P.out)[pix] = o;
-        if (P.samples) P.samples[pix] = k;
+        if (P.samples) P.samples[pix] = count;
+    }
+    if (P.nsamples) {
+        // The request's composited samples: a wave-wide sum (every lane of
+        // the wave arrives here), one atomic add per wave.
+        int v = valid ? count : 0;
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+        if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(P.nsamples, (unsigned long long)v);
     }
 }
 

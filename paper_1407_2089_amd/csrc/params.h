@@ -66,6 +66,12 @@ inline constexpr bool variant_exists(int v) {
 // for x = 0 .. Bx.  The four taps of a sample in one plane are then four
 // consecutive words (one or two wide loads per plane instead of two narrow
 // ones per row), at the price of storing every inner row twice.
+//
+// Macro cells (empty-space skipping): the low corners s0 in [0, n] are also
+// grouped into cells of M = 2^cshift per axis.  After the bricks, each frame
+// stores one word per cell (same packing as a voxel word) holding, per
+// channel, the largest value any tap of a sample whose low corner lies in
+// the cell can read: voxels of stored coordinates [c M, c M + M] per axis.
 struct BrickGeom {
     int32_t n[3];       // voxels per axis
     int32_t shift[3];   // log2 of the brick edge per axis
@@ -75,9 +81,15 @@ struct BrickGeom {
     int32_t brick;      // words per brick = (Bz + 1) plane
     int32_t word;       // bytes per word
     int32_t pairs;      // 1: row-pair layout
+    int32_t cshift;     // log2 of the macro-cell edge
+    int32_t nc[3];      // macro cells per axis = floor(n / M) + 1
     float clamp_hi[3];  // largest float below n + 1 per axis
+    int32_t pad_;
+    uint64_t cell_off;  // byte offset of the cell table in a frame (multiple of 256)
     uint64_t frame_bytes; // bytes per frame, multiple of 256
 };
+
+constexpr int kCellShift = 3;  // macro cells of 8 x 8 x 8 low corners
 
 // Transfer function of one channel, folded so that u = raw * scale + bias.
 struct ChanTF {
@@ -137,9 +149,10 @@ struct ReqParams {
     float bg[4];            // bg_a * bg_rgb, bg_a
     float sx_scale, sy_scale; // 2 / W, 2 / H
     int32_t width, height, eyes;
-    int32_t pad_;
+    int32_t skip_cells;     // 1: rays jump over macro cells shown transparent
     float* out;             // [eyes][H][W][4]
     int32_t* samples;       // [eyes][H][W] or null
+    unsigned long long* nsamples;  // device counter: += samples composited, or null
     // Large variants: the same ray basis in FP64, and the clamp bound of
     // stored coordinates (largest double below n + 1 per axis).
     struct {

@@ -14,6 +14,7 @@
 #pragma once
 #include <stdint.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -49,40 +50,54 @@ class Backend {
     virtual ~Backend() = default;
     virtual int slots() const = 0;
     // Start one batch on `slot`.  Returns VR_OK or the failure of the launch.
+    // Called without the scheduler's lock held.
     virtual vr_status launch(int slot, const std::vector<Job*>& jobs) = 0;
-    // True once the slot's last batch has finished; *err is its status.
-    virtual bool finished(int slot, vr_status* err) = 0;
+    // True once the slot's last batch has finished; *err is its status and
+    // *device_ns the time it took on the device.
+    virtual bool finished(int slot, vr_status* err, uint64_t* device_ns) = 0;
+    // Samples composited for job q of the slot's finished batch.
+    virtual uint64_t samples(int slot, int q) const = 0;
 };
 
-// CPU stand-in: a batch "runs" for rays x ns_per_ray nanoseconds; a batch
-// that holds a request of width fail_width fails.
+// CPU stand-in: a batch "runs" for rays x ns_per_ray nanoseconds and
+// reports one sample per ray; a batch that holds a request of width
+// fail_width fails; launch() itself takes launch_ns (a slow enqueue).
 class FakeBackend : public Backend {
   public:
-    FakeBackend(int n, double ns_per_ray, int fail_width)
-        : ns_per_ray_(ns_per_ray), fail_width_(fail_width), end_(n, 0), fail_(n, false) {}
+    FakeBackend(int n, double ns_per_ray, int fail_width, uint64_t launch_ns = 0)
+        : ns_per_ray_(ns_per_ray), fail_width_(fail_width), launch_ns_(launch_ns),
+          start_(n, 0), end_(n, 0), fail_(n, false), rays_(n) {}
     int slots() const override { return (int)end_.size(); }
     vr_status launch(int slot, const std::vector<Job*>& jobs) override {
         double rays = 0.0;
         bool f = false;
+        rays_[slot].clear();
         for (Job* j : jobs) {
             rays += (double)j->info.rays;
+            rays_[slot].push_back(j->info.rays);
             f = f || j->params.width == fail_width_;
         }
-        end_[slot] = now_ns() + (uint64_t)(rays * ns_per_ray_);
+        if (launch_ns_) std::this_thread::sleep_for(std::chrono::nanoseconds(launch_ns_));
+        start_[slot] = now_ns();
+        end_[slot] = start_[slot] + (uint64_t)(rays * ns_per_ray_);
         fail_[slot] = f;
         return VR_OK;
     }
-    bool finished(int slot, vr_status* err) override {
+    bool finished(int slot, vr_status* err, uint64_t* device_ns) override {
         if (now_ns() < end_[slot]) return false;
         *err = fail_[slot] ? VR_ERR_DEVICE : VR_OK;
+        *device_ns = end_[slot] - start_[slot];
         return true;
     }
+    uint64_t samples(int slot, int q) const override { return rays_[slot][q]; }
 
   private:
     double ns_per_ray_;
     int fail_width_;
-    std::vector<uint64_t> end_;
+    uint64_t launch_ns_;
+    std::vector<uint64_t> start_, end_;
     std::vector<bool> fail_;
+    std::vector<std::vector<uint64_t>> rays_;
 };
 
 class Scheduler {
@@ -157,15 +172,25 @@ class Scheduler {
         if (j->refs) j->refs->fetch_sub(1);
     }
 
-    // One pass of completion and admission; true if anything changed.
-    bool step() {
+    // One pass of completion and admission; true if anything changed.  `lk`
+    // holds mu_ on entry and on return; it is released around each launch,
+    // so that submit and poll never wait for the backend.  Only this thread
+    // touches busy_ and running_, and jobs in running_ are past pending
+    // (state 1), which release() does not erase.
+    bool step(std::unique_lock<std::mutex>& lk) {
         bool changed = false;
         const uint64_t t = now_ns();
         for (int s = 0; s < (int)busy_.size(); ++s) {
             if (!busy_[s]) continue;
             vr_status err = VR_OK;
-            if (!backend_->finished(s, &err)) continue;
-            for (Job* j : running_[s]) {
+            uint64_t device_ns = 0;
+            if (!backend_->finished(s, &err, &device_ns)) continue;
+            for (size_t q = 0; q < running_[s].size(); ++q) {
+                Job* j = running_[s][q];
+                // device start on the host clock: the completion stamp minus
+                // the batch's span on the device
+                j->info.t_start_ns = t - std::min(device_ns, t - j->info.t_admit_ns);
+                if (err == VR_OK) j->info.samples = backend_->samples(s, (int)q);
                 finish(j, err == VR_OK ? 2 : 3, err, t);
                 inflight_bytes_ -= j->out_bytes;
                 --inflight_jobs_;
@@ -198,9 +223,10 @@ class Scheduler {
             for (Job* j : batch) {
                 j->info.state = 1;
                 j->info.t_admit_ns = ts;
-                j->info.t_start_ns = ts;
             }
+            lk.unlock();
             const vr_status st = backend_->launch(s, batch);
+            lk.lock();
             if (st != VR_OK) {
                 for (Job* j : batch) {
                     finish(j, 3, st, now_ns());
@@ -220,7 +246,7 @@ class Scheduler {
         std::unique_lock<std::mutex> lk(mu_);
         uint64_t last_activity = now_ns();
         while (!stop_) {
-            const bool changed = step();
+            const bool changed = step(lk);
             bool any_busy = false;
             for (bool b : busy_) any_busy = any_busy || b;
             if (changed || any_busy) last_activity = now_ns();

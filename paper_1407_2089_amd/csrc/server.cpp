@@ -12,75 +12,116 @@
 
 namespace vr {
 
-// GPU backend: one stream, one batched-launch workspace and one completion
-// event per slot.
+// GPU backend: per slot one stream, one batched-launch workspace, a pair of
+// timing events around the batch's kernels, a completion event after the
+// read-back of its sample counters, and the counters themselves (one per
+// request of the batch, device and pinned host copies).
 class HipBackend : public Backend {
   public:
-    HipBackend(vr_ctx* ctx, int n, vr_status* st) : ctx_(ctx) {
+    HipBackend(vr_ctx* ctx, int n, int max_batch, vr_status* st)
+        : ctx_(ctx), max_batch_(max_batch) {
         *st = VR_OK;
         for (int s = 0; s < n; ++s) {
-            hipStream_t stream = nullptr;
-            hipEvent_t ev = nullptr;
-            hipError_t e = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            Slot sl;
+            hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreate(&sl.t0);
+            if (e == hipSuccess) e = hipEventCreate(&sl.t1);
+            if (e == hipSuccess)
+                e = hipMalloc(&sl.d_count, sizeof(unsigned long long) * (size_t)max_batch);
+            if (e == hipSuccess)
+                e = hipHostMalloc(&sl.h_count, sizeof(unsigned long long) * (size_t)max_batch,
+                                  hipHostMallocDefault);
             if (e != hipSuccess) {
-                *st = hip_fail(e, "serving stream");
-                if (stream) (void)hipStreamDestroy(stream);
+                *st = hip_fail(e, "serving slot");
+                destroy(sl);
                 return;
             }
-            BatchSlot* b = batch_slot_create(ctx, stream, st);
-            if (!b) {
-                (void)hipEventDestroy(ev);
-                (void)hipStreamDestroy(stream);
+            sl.batch = batch_slot_create(ctx, sl.stream, st);
+            if (!sl.batch) {
+                destroy(sl);
                 return;
             }
-            streams_.push_back(stream);
-            events_.push_back(ev);
-            slots_.push_back(b);
+            slots_.push_back(sl);
         }
     }
     ~HipBackend() override {
-        for (size_t s = 0; s < slots_.size(); ++s) {
-            batch_slot_destroy(slots_[s]);
-            (void)hipEventDestroy(events_[s]);
-            (void)hipStreamDestroy(streams_[s]);
-        }
+        for (Slot& sl : slots_) destroy(sl);
     }
     int slots() const override { return (int)slots_.size(); }
     vr_status launch(int slot, const std::vector<Job*>& jobs) override {
-        hipError_t e;
-        if (jobs.size() == 1) {
+        Slot& sl = slots_[slot];
+        const int n = (int)jobs.size();
+        if (n > max_batch_) return fail(VR_ERR_INVALID_ARG, "batch of %d requests", n);
+        sl.n = n;
+        // counters cleared by a kernel-free memset on the stream: the batch's
+        // graph is launched after it and does not contain it
+        hipError_t e = hipMemsetAsync(sl.d_count, 0, sizeof(unsigned long long) * (size_t)n,
+                                      sl.stream);
+        if (e == hipSuccess) e = hipEventRecord(sl.t0, sl.stream);
+        if (e != hipSuccess) return hip_fail(e, "serving launch");
+        params_.resize(jobs.size());
+        for (int q = 0; q < n; ++q) {
+            params_[q] = jobs[q]->params;
+            params_[q].nsamples = sl.d_count + q;
+        }
+        if (n == 1) {
             // A lone request takes the plain launch: its parameters travel as
             // kernel arguments, with no table upload and no graph.
-            e = launch_render(jobs[0]->params, ctx_->plain_tile, ctx_->clear_skip,
-                              streams_[slot]);
+            e = launch_render(params_[0], ctx_->plain_tile, ctx_->clear_skip, sl.stream);
             if (e != hipSuccess) return hip_fail(e, "render launch");
         } else {
-            params_.resize(jobs.size());
-            for (size_t q = 0; q < jobs.size(); ++q) params_[q] = jobs[q]->params;
             // The loop never stops to tune: a shape class tuned by
-            // vr_render_batch (or loaded from the cache file) is used, else the
+            // vr_tune_batch (or loaded from the cache file) is used, else the
             // default tile.
-            vr_status st = batch_enqueue(ctx_, slots_[slot], params_.data(), (int)jobs.size(),
-                                         /*allow_tuning=*/false);
+            vr_status st = batch_enqueue(ctx_, sl.batch, params_.data(), n);
             if (st != VR_OK) return st;
         }
-        e = hipEventRecord(events_[slot], streams_[slot]);
-        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = hipEventRecord(sl.t1, sl.stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(sl.h_count, sl.d_count, sizeof(unsigned long long) * (size_t)n,
+                                hipMemcpyDeviceToHost, sl.stream)) != hipSuccess ||
+            (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess)
+            return hip_fail(e, "serving launch");
         return VR_OK;
     }
-    bool finished(int slot, vr_status* err) override {
-        hipError_t e = hipEventQuery(events_[slot]);
+    bool finished(int slot, vr_status* err, uint64_t* device_ns) override {
+        Slot& sl = slots_[slot];
+        hipError_t e = hipEventQuery(sl.done);
         if (e == hipErrorNotReady) return false;
         *err = e == hipSuccess ? VR_OK : VR_ERR_DEVICE;
+        float ms = 0.0f;
+        *device_ns = 0;
+        if (e == hipSuccess && hipEventElapsedTime(&ms, sl.t0, sl.t1) == hipSuccess && ms > 0.0f)
+            *device_ns = (uint64_t)((double)ms * 1e6);
         return true;
+    }
+    uint64_t samples(int slot, int q) const override {
+        const Slot& sl = slots_[slot];
+        return q < sl.n ? (uint64_t)sl.h_count[q] : 0;
     }
 
   private:
+    struct Slot {
+        hipStream_t stream = nullptr;
+        hipEvent_t done = nullptr, t0 = nullptr, t1 = nullptr;
+        unsigned long long* d_count = nullptr;
+        unsigned long long* h_count = nullptr;  // pinned
+        BatchSlot* batch = nullptr;
+        int n = 0;
+    };
+    static void destroy(Slot& sl) {
+        if (sl.batch) batch_slot_destroy(sl.batch);  // synchronises the stream
+        if (sl.d_count) (void)hipFree(sl.d_count);
+        if (sl.h_count) (void)hipHostFree(sl.h_count);
+        for (hipEvent_t ev : {sl.done, sl.t0, sl.t1})
+            if (ev) (void)hipEventDestroy(ev);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        sl = Slot{};
+    }
+
     vr_ctx* ctx_;
-    std::vector<hipStream_t> streams_;
-    std::vector<hipEvent_t> events_;
-    std::vector<BatchSlot*> slots_;
+    int max_batch_;
+    std::vector<Slot> slots_;
     std::vector<ReqParams> params_;
 };
 
@@ -117,7 +158,7 @@ static vr_status ensure_server(vr_ctx* ctx) {
         return fail(VR_ERR_UNSUPPORTED, "validation-only context has no serving backend");
     vr_status st;
     (void)hipSetDevice(ctx->device);
-    HipBackend* b = new HipBackend(ctx, kDefaultSlots, &st);
+    HipBackend* b = new HipBackend(ctx, kDefaultSlots, kMaxBatch, &st);
     if (st != VR_OK) {
         delete b;
         return st;
@@ -198,17 +239,19 @@ vr_status vr_release(vr_ctx* ctx, uint64_t ticket) {
 }
 
 vr_status vr_test_fake_backend(vr_ctx* ctx, int32_t slots, double ns_per_ray,
-                               int32_t fail_width, int32_t max_batch) {
+                               int32_t fail_width, int32_t max_batch, double launch_ms) {
     if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
-    if (slots < 1 || slots > 64 || !(ns_per_ray >= 0.0) || max_batch < 1)
+    if (slots < 1 || slots > 64 || !(ns_per_ray >= 0.0) || max_batch < 1 ||
+        !(launch_ms >= 0.0) || !(launch_ms <= 10000.0))
         return fail(VR_ERR_INVALID_ARG, "bad fake backend parameters");
     std::lock_guard<std::mutex> lk(ctx->server_mu);
     if (ctx->server) {
         if (!ctx->server->idle()) return fail(VR_ERR_BUSY, "serving loop is busy");
         delete ctx->server;
     }
-    ctx->server = new Scheduler(new FakeBackend(slots, ns_per_ray, fail_width), max_batch,
-                                serve_budget(ctx));
+    ctx->server = new Scheduler(
+        new FakeBackend(slots, ns_per_ray, fail_width, (uint64_t)(launch_ms * 1e6)), max_batch,
+        serve_budget(ctx));
     return ok();
 }
 

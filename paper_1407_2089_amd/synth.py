@@ -389,12 +389,13 @@ def tiny_scene(seed=1):
                  256, 256, False, 0.5, 1.0)
 
 
-def realistic_scene(seed=2, width=1920, height=1080, dims=(512, 512, 64)):
+def realistic_scene(seed=2, width=1920, height=1080, dims=(512, 512, 64), volume=True):
     """2-channel 12-bit uint16 512x512x64: 40 ellipsoidal cells (green) and 10
     spline vessels (red) with Poisson noise; perspective stereo 1920x1080 per
     eye from azimuth 30, elevation 50 degrees, fov 45; step 1, early
-    termination at alpha 0.99."""
-    vol = cells_and_vessels(dims, 2, 12, seed, n_cells=40, n_tubes=10)
+    termination at alpha 0.99.  volume=False leaves the voxels out (None):
+    the render parameters alone."""
+    vol = cells_and_vessels(dims, 2, 12, seed, n_cells=40, n_tubes=10) if volume else None
     cam = orbit_camera(dims, 30.0, 50.0, 45.0)
     lo, hi = 300.0 / 4095.0, 3000.0 / 4095.0
     tfs = [TF(lo, hi, 0.0, 1.0, (0.0, 1.0, 0.0)), TF(lo, hi, 0.0, 1.0, (1.0, 0.0, 0.0))]

@@ -15,7 +15,7 @@ from . import synth
 from . import (VR_FP16, VR_FP32, VR_U8, VR_U16, Volume, gaussian_weights, make_grid,
                make_lowpass, make_request, vr_denoise_workspace_bytes, vr_mrf_denoise, vr_poll,
                vr_release, vr_remove_background, vr_render, vr_render_batch, vr_stream_frame,
-               vr_stream_ready, vr_submit)
+               vr_stream_ready, vr_submit, vr_tune_batch)
 
 SIZES_BATCH = [(960, 540), (1280, 720), (1600, 900), (1920, 1080)]
 SIZES_SERVE = [(960, 540), (1920, 1080), (2560, 1440), (3840, 2160)]
@@ -73,14 +73,16 @@ def count_samples(ctx, reqs):
 
 # ------------------------------------------------------------------ batching
 
-def batching(ctx, n_req=64, n_vol=16, seed=4, reps=5):
-    """64 stereo requests over 16 volumes of uneven size (2^21..2^26 voxels,
-    1-4 channels, u8 / u16-12 / u16-16; row pairs where the voxel word allows):
-    one vr_render_batch call against 64 sequential vr_render calls (one launch
-    per stereo request)."""
+def batching_setup(ctx, n_req=64, n_vol=16, seed=4):
+    """The batching workload's volumes and requests: 64 stereo requests over
+    16 volumes of uneven size (2^21..2^26 voxels, 1-4 channels, u8 / u16-12 /
+    u16-16; row pairs where the voxel word allows), 960x540..1920x1080 per
+    eye, random view directions.  Returns (volumes, their DeviceSeries,
+    meta [(dims, channels, bits)], requests, outputs, request -> volume
+    index, cameras)."""
     import torch
     rng = np.random.default_rng(seed)
-    vols, meta = [], []
+    vols, sers, meta = [], [], []
     log("batching: generating volumes")
     for q in range(n_vol):
         voxels = 2.0 ** rng.uniform(21, 26)
@@ -93,8 +95,9 @@ def batching(ctx, n_req=64, n_vol=16, seed=4, reps=5):
         tfs = default_tfs(ch)
         # the faster layout wherever it exists (single frames: storage is cheap)
         vols.append(load_series(ctx, ser, 1, tfs, row_pairs=pairs_allowed(ch, bits)))
+        sers.append(ser)
         meta.append(((nxy, nxy, nz), ch, bits))
-    reqs, outs = [], []
+    reqs, outs, which, cams = [], [], [], []
     for q in range(n_req):
         v = int(rng.integers(0, n_vol))
         dims = meta[v][0]
@@ -103,6 +106,16 @@ def batching(ctx, n_req=64, n_vol=16, seed=4, reps=5):
         out = torch.empty((2, h, w, 4), dtype=torch.float32, device="cuda")
         reqs.append(make_request(vols[v].ptr, 0, cam, w, h, True, 1.0, 0.99, out))
         outs.append(out)
+        which.append(v)
+        cams.append(cam)
+    return vols, sers, meta, reqs, outs, which, cams
+
+
+def batching(ctx, n_req=64, n_vol=16, seed=4, reps=5):
+    """The batching workload (batching_setup): one vr_render_batch call
+    against 64 sequential vr_render calls (one launch per stereo request)."""
+    import torch
+    vols, _, meta, reqs, outs, _, _ = batching_setup(ctx, n_req, n_vol, seed)
     counts = count_samples(ctx, reqs)
     total_samples = sum(counts)
     eff_bytes = sum(c * 8 * meta_bytes(meta, vols, reqs[i]) for i, c in enumerate(counts))
@@ -115,8 +128,9 @@ def batching(ctx, n_req=64, n_vol=16, seed=4, reps=5):
     def run_batch():
         vr_render_batch(ctx.ptr, reqs, stream)
 
-    # warm-up (the first batch of this shape class runs the autotuner)
+    # warm-up, and the autotuner's choice of wave tile for this shape class
     run_plain()
+    tile = vr_tune_batch(ctx.ptr, reqs, stream)
     run_batch()
     torch.cuda.synchronize()
     # bitwise equality of the two paths
@@ -154,7 +168,7 @@ def batching(ctx, n_req=64, n_vol=16, seed=4, reps=5):
         "plain_samples_per_s": total_samples / t_plain,
         "batch_samples_per_s": total_samples / t_batch,
         "batch_eff_GBps": eff_bytes / t_batch / 1e9,
-        "speedup": t_plain / t_batch,
+        "speedup": t_plain / t_batch, "tuned_tile": list(tile),
     }
 
 
@@ -596,50 +610,6 @@ def montage_setup(ctx, seed=3, brick=(0, 0, 0)):
     for c, tf in enumerate(tfs):
         vol.set_transfer(c, tf)
     return vol, src, tfs
-
-
-def ray_crop(cam, W, H, eye, px, py, dims, margin=3):
-    """Index-space box [lo, hi) holding the part of pixel (px, py)'s ray that
-    lies in the volume's extended box [-1, n] per axis, widened by `margin`
-    voxels and clipped to the grid (unit spacing, origin 0); None if the ray
-    misses.  Rendering that crop (origin moved to lo) gives the ray the same
-    samples as the whole volume, so single pixels of a volume too large to
-    copy whole can be checked on their own."""
-    f = np.array(cam.forward, float)
-    f /= np.linalg.norm(f)
-    rt = np.cross(f, np.array(cam.up, float))
-    rt /= np.linalg.norm(rt)
-    u = np.cross(rt, f)
-    sx = (px + 0.5) * 2.0 / W - 1.0
-    sy = 1.0 - (py + 0.5) * 2.0 / H
-    c = np.array(cam.center, float)
-    if cam.projection == "perspective":
-        h = cam.convergence * np.tan(0.5 * cam.fov_y)
-        w = h * W / H
-        s = float(eye)
-        o = c + s * 0.5 * cam.eye_separation * rt
-        d = cam.convergence * f - s * 0.5 * cam.eye_separation * rt + sx * w * rt + sy * h * u
-        t0 = 0.0
-    else:
-        h = 0.5 * cam.ortho_height
-        w = h * W / H
-        o = c + sx * w * rt + sy * h * u
-        d = f
-        t0 = -np.inf
-    t1 = np.inf
-    n = np.array(dims, float)
-    for a in range(3):
-        if d[a] != 0.0:
-            ta, tb = (-1.0 - o[a]) / d[a], (n[a] - o[a]) / d[a]
-            t0, t1 = max(t0, min(ta, tb)), min(t1, max(ta, tb))
-        elif not -1.0 <= o[a] <= n[a]:
-            return None
-    if not t0 < t1:
-        return None
-    p0, p1 = o + t0 * d, o + t1 * d
-    lo = np.maximum(np.floor(np.minimum(p0, p1)) - margin, 0).astype(int)
-    hi = np.minimum(np.ceil(np.maximum(p0, p1)) + margin + 1, n).astype(int)
-    return lo, hi
 
 
 def montage_camera():

@@ -25,7 +25,8 @@ def declared_symbols(header="vr.h"):
 def test_library_exports_every_declared_symbol():
     L = vr.lib()
     names = declared_symbols()
-    assert "vr_render" in names and "vr_submit" in names and len(names) == 16
+    assert "vr_render" in names and "vr_submit" in names and len(names) == 17
+    assert "vr_tune_batch" in names
     assert "vr_stream_frame" in names and "vr_stream_ready" in names
     dn = declared_symbols("vr_denoise.h")
     assert dn == ["vr_denoise_workspace_bytes", "vr_gaussian_weights", "vr_mrf_denoise",
@@ -43,6 +44,16 @@ def desc(nx=64, ny=48, nz=20, ch=2, frames=3, dtype=vr.VR_U16, bits=12, brick=(0
 WORD = {1: 1, 2: 2, 3: 4, 4: 4, 5: 8, 6: 8}   # bytes per voxel word of uint8 channels
 
 
+def with_cells(brick_bytes, dims, word):
+    """Frame bytes: the bricks padded to 256 bytes, then one word per macro
+    cell of 8 x 8 x 8 sample corners (floor(n / 8) + 1 cells per axis),
+    padded to 256 bytes."""
+    cells = 1
+    for n in dims:
+        cells *= n // 8 + 1
+    return (brick_bytes + 255) // 256 * 256 + (cells * word + 255) // 256 * 256
+
+
 @pytest.mark.parametrize("dims,ch,dtype,brick", [
     ((64, 48, 20), 2, vr.VR_U16, (16, 16, 16)),
     ((1, 1, 1), 1, vr.VR_U8, (4, 4, 4)),
@@ -57,8 +68,7 @@ def test_storage_bytes_follow_brick_layout(dims, ch, dtype, brick):
     word = WORD[ch] * (1 if dtype == vr.VR_U8 else 2)
     nb = [math.ceil((n + 1) / b) for n, b in zip(dims, brick)]
     per_brick = (brick[0] + 1) * (brick[1] + 1) * (brick[2] + 1)
-    frame = nb[0] * nb[1] * nb[2] * per_brick * word
-    frame = (frame + 255) // 256 * 256
+    frame = with_cells(nb[0] * nb[1] * nb[2] * per_brick * word, dims, word)
     assert vr.vr_volume_storage_bytes(d) == 3 * frame
 
 
@@ -80,8 +90,7 @@ def test_storage_bytes_of_the_row_pair_layout(dims, ch, dtype, brick):
         brick = {1: (16, 16, 16), 2: (8, 32, 8), 4: (4, 16, 16)}[word]
     nb = [math.ceil((n + 1) / b) for n, b in zip(dims, brick)]
     per_brick = brick[1] * 2 * (brick[0] + 1) * (brick[2] + 1)
-    frame = nb[0] * nb[1] * nb[2] * per_brick * word
-    frame = (frame + 255) // 256 * 256
+    frame = with_cells(nb[0] * nb[1] * nb[2] * per_brick * word, dims, word)
     assert vr.vr_volume_storage_bytes(d) == 2 * frame
 
 
@@ -142,6 +151,26 @@ def test_invalid_spacing_bits_and_brick():
         assert e.value.status == vr.VR_ERR_INVALID_ARG
 
 
+@pytest.mark.parametrize("dims,large", [((2048, 2048, 255), True), ((2044, 2044, 255), True),
+                                        ((2040, 2044, 255), False), ((1024, 1024, 64), False)])
+def test_2_to_the_24_bricks_take_the_large_addressing(dims, large):
+    # 4 x 4 x 4 bricks of 1-byte words: 2044 x 2044 x 255 voxels give
+    # 512 x 512 x 64 = 2^24 bricks (2.1e9 words, under 2^31 and 4 GiB), where
+    # the 32-bit sampler's 24-bit brick products would wrap; one brick column
+    # less stays on the 32-bit path
+    ctx = vr.vr_init(-1, 1 << 40)
+    try:
+        d = desc(*dims, ch=1, frames=1, dtype=vr.VR_U8, bits=8, brick=(4, 4, 4))
+        nb = [math.ceil((n + 1) / 4) for n in dims]
+        assert (nb[0] * nb[1] * nb[2] >= 1 << 24) == large
+        assert nb[0] * nb[1] * nb[2] * 125 < 1 << 31
+        v = vr.vr_create_volume(ctx, d, FAKE, vr.vr_volume_storage_bytes(d))
+        assert vr.vr_test_volume_large(v) == large
+        vr.vr_destroy_volume(v)
+    finally:
+        vr.vr_shutdown(ctx)
+
+
 def test_large_volume_limits():
     # a frame of 2^31 words or more, 4 GiB or more, or an axis above 8192
     # voxels takes the large-volume addressing: accepted, sized as any other
@@ -154,8 +183,8 @@ def test_large_volume_limits():
     # smaller volumes with 8-byte words keep 8 x 8 x 8
     def frame(dims, b, word):
         nb = [math.ceil((n + 1) / e) for n, e in zip(dims, b)]
-        f = nb[0] * nb[1] * nb[2] * (b[0] + 1) * (b[1] + 1) * (b[2] + 1) * word
-        return (f + 255) // 256 * 256
+        return with_cells(nb[0] * nb[1] * nb[2] * (b[0] + 1) * (b[1] + 1) * (b[2] + 1) * word,
+                          dims, word)
     mont = (10173, 3858, 74)
     assert vr.vr_volume_storage_bytes(desc(*mont, ch=5, frames=1, dtype=vr.VR_U8, bits=8)) == \
         frame(mont, (4, 16, 8), 8)

@@ -1,0 +1,218 @@
+"""Empty-space skipping over macro cells must change no output bit and no
+sample count: rays that jump over cells whose per-channel maxima lie below
+every channel's transfer-function floor give the same image as rays that
+walk every sample, and both match the oracle.  The scenes put sparse
+structure among wide empty regions and look at it along the axes (ray
+components of exactly 0, samples on cell faces), obliquely, in
+orthographic and stereo perspective views, through the FP64 large-volume
+path and through batched and served launches."""
+import time
+
+import numpy as np
+import pytest
+
+import gpu
+import orc
+import paper_1407_2089_amd as vr
+from paper_1407_2089_amd import synth
+from paper_1407_2089_amd.synth import TF, Cam, Scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    torch.cuda.init()
+    c = vr.Context(0)
+    yield c
+    try:
+        c.close()
+    except vr.VrError:
+        pass
+
+
+def sparse_volume(seed, shape, dtype, full, n_blobs=6, noise=0.05):
+    """Few bright blobs of radius 1-4 voxels over noise below the floor."""
+    c, nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    vol = rng.integers(0, max(2, int(full * noise)), size=shape).astype(np.int64)
+    zz, yy, xx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for ch in range(c):
+        for _ in range(n_blobs):
+            ctr = rng.uniform([0, 0, 0], [nz - 1, ny - 1, nx - 1])
+            r = rng.uniform(1.0, 4.0)
+            d2 = (zz - ctr[0]) ** 2 + (yy - ctr[1]) ** 2 + (xx - ctr[2]) ** 2
+            peak = rng.uniform(0.5, 1.0) * full
+            vol[ch] += (peak * np.exp(-d2 / (2 * r * r))).astype(np.int64)
+    return np.minimum(vol, full).astype(dtype)
+
+
+def render_modes(ctx, sc, precision=vr.VR_FP32, vol=None):
+    """(full walk, per-sample skip only, both skips) images of one scene."""
+    own = vol is None
+    if own:
+        vol = gpu.make_volume(ctx, sc)
+    out = []
+    try:
+        for mode in (0, 2, 1):
+            vr.vr_test_clear_skip(ctx.ptr, mode)
+            out.append(gpu.render(ctx, sc, precision, vol=vol))
+    finally:
+        vr.vr_test_clear_skip(ctx.ptr, 1)
+        if own:
+            vol.destroy()
+    return out
+
+
+def same_bits(a, b):
+    (ra, sa), (rb, sb) = a, b
+    assert np.array_equal(sa, sb), int((sa != sb).sum())
+    assert np.array_equal(ra.view(np.uint32), rb.view(np.uint32))
+
+
+def tfs_for(ch, full, lo=0.3):
+    cols = [(0.1, 1.0, 0.2), (1.0, 0.2, 0.1), (0.2, 0.3, 1.0), (1.0, 1.0, 0.1),
+            (0.8, 0.2, 0.9), (0.2, 0.9, 0.9)]
+    return [TF(lo + 0.02 * c, min(1.0, lo + 0.5), 0.1 * c, 1.0, cols[c]) for c in range(ch)]
+
+
+AXES = [((0, 0, 1), (0, -1, 0)), ((0, 0, -1), (0, -1, 0)), ((1, 0, 0), (0, 0, 1)),
+        ((-1, 0, 0), (0, 1, 0)), ((0, 1, 0), (0, 0, -1)), ((0, -1, 0), (1, 0, 0))]
+
+
+@pytest.mark.parametrize("axis", range(6))
+@pytest.mark.parametrize("step", [1.0, 0.5, 0.37])
+def test_axis_aligned_ortho_views(ctx, axis, step):
+    """Rays along an axis: two direction components are exactly 0, and with
+    step 1 the sample corners fall on integer stored coordinates (cell faces
+    at multiples of 8)."""
+    nx, ny, nz = 45, 38, 29
+    vol = sparse_volume(11 + axis, (1, nz, ny, nx), np.uint8, 255)
+    fwd, up = AXES[axis]
+    ctr = np.array([(nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2]) - 60.0 * np.array(fwd)
+    cam = Cam("ortho", tuple(ctr), fwd, up, ortho_height=50.0)
+    sc = Scene("axis", vol, 8, tfs_for(1, 255), cam, 64, 56, False, step, 1.0)
+    full, sample_only, both = render_modes(ctx, sc)
+    same_bits(full, sample_only)
+    same_bits(full, both)
+    gpu.compare(both[0], both[1], orc.render_all(sc), 1e-3)
+
+
+@pytest.mark.parametrize("precision", [vr.VR_FP32, vr.VR_FP16])
+@pytest.mark.parametrize("ch,dtype,bits", [(1, np.uint8, 8), (2, np.uint16, 12), (3, np.uint8, 8),
+                                           (4, np.uint8, 8), (4, np.uint16, 16), (5, np.uint8, 8),
+                                           (6, np.uint16, 12)])
+@pytest.mark.parametrize("view", range(3))
+def test_oblique_stereo_views(ctx, ch, dtype, bits, precision, view):
+    full_v = (1 << bits) - 1
+    nx, ny, nz = 70, 61, 37
+    vol = sparse_volume(31 + 7 * ch + view, (ch, nz, ny, nx), dtype, full_v, n_blobs=4)
+    az, el = [(30.0, 50.0), (123.0, -20.0), (251.0, 71.0)][view]
+    cam = synth.orbit_camera((nx, ny, nz), az, el, 45.0)
+    sc = Scene("oblique", vol, bits, tfs_for(ch, full_v), cam, 88, 64, True, 1.0, 0.99)
+    full, sample_only, both = render_modes(ctx, sc, precision)
+    same_bits(full, sample_only)
+    same_bits(full, both)
+    if view == 0:
+        tol = 1e-3 if precision == vr.VR_FP32 else 4e-3
+        gpu.compare(both[0], both[1], orc.render_all(sc), tol)
+
+
+@pytest.mark.parametrize("row_pairs,brick", [(False, (0, 0, 0)), (True, (0, 0, 0)),
+                                             (False, (4, 4, 4)), (False, (32, 8, 16))])
+def test_layouts_and_realistic_content(ctx, row_pairs, brick):
+    sc = synth.realistic_scene(width=200, height=120, dims=(160, 144, 40))
+    vol = gpu.make_volume(ctx, sc, brick=brick, row_pairs=row_pairs)
+    try:
+        full, sample_only, both = render_modes(ctx, sc, vol=vol)
+    finally:
+        vol.destroy()
+    same_bits(full, sample_only)
+    same_bits(full, both)
+    gpu.compare(both[0], both[1], orc.render_all(sc), 1e-3)
+
+
+def test_lit_render(ctx):
+    nx, ny, nz = 64, 52, 33
+    vol = sparse_volume(5, (2, nz, ny, nx), np.uint16, 4095)
+    cam = synth.orbit_camera((nx, ny, nz), 60.0, 30.0, 45.0)
+    sc = Scene("lit", vol, 12, tfs_for(2, 4095), cam, 72, 48, True, 0.8, 0.99,
+               light=synth.Light((0.3, -0.5, 0.8), 0.3, 0.7))
+    full, sample_only, both = render_modes(ctx, sc)
+    same_bits(full, sample_only)
+    same_bits(full, both)
+    gpu.compare(both[0], both[1], orc.render_all(sc), 1e-3)
+
+
+@pytest.mark.parametrize("ch,dtype,bits", [(2, np.uint16, 12), (5, np.uint8, 8)])
+def test_large_addressing(ctx, ch, dtype, bits):
+    """The FP64 path steps, clamps and floors in double: its cell walk checks
+    its own arithmetic."""
+    full_v = (1 << bits) - 1
+    nx, ny, nz = 58, 49, 30
+    vol = sparse_volume(77 + ch, (ch, nz, ny, nx), dtype, full_v)
+    cam = synth.orbit_camera((nx, ny, nz), 200.0, 35.0, 45.0)
+    sc = Scene("large", vol, bits, tfs_for(ch, full_v), cam, 64, 48, True, 1.0, 0.99)
+    vr.vr_test_large_addressing(ctx.ptr, True)
+    try:
+        v = gpu.make_volume(ctx, sc)
+    finally:
+        vr.vr_test_large_addressing(ctx.ptr, False)
+    try:
+        assert vr.vr_test_volume_large(v.ptr)
+        full, sample_only, both = render_modes(ctx, sc, vol=v)
+    finally:
+        v.destroy()
+    same_bits(full, sample_only)
+    same_bits(full, both)
+    gpu.compare(both[0], both[1], orc.render_all(sc), 1e-3)
+
+
+def test_transparent_volume_takes_no_sample_arithmetic_and_keeps_counts(ctx):
+    """Everything below the floor: every ray jumps from cell to cell to its
+    exit, and still reports the nominal sample count of the oracle."""
+    nx, ny, nz = 50, 40, 30
+    vol = sparse_volume(3, (1, nz, ny, nx), np.uint8, 255, n_blobs=0)
+    cam = synth.orbit_camera((nx, ny, nz), 40.0, 25.0, 45.0)
+    sc = Scene("empty", vol, 8, tfs_for(1, 255, lo=0.5), cam, 64, 40, True, 0.6, 1.0)
+    full, sample_only, both = render_modes(ctx, sc)
+    same_bits(full, both)
+    gpu.compare(both[0], both[1], orc.render_all(sc), 1e-3)
+    assert np.all(both[0] == 0.0) and both[1].max() > 0
+
+
+def test_batched_and_served_match_plain(ctx):
+    """Batched and served launches take the same cell walk."""
+    import torch
+    nx, ny, nz = 66, 57, 35
+    scs = []
+    for q in range(3):
+        vol = sparse_volume(90 + q, (2, nz, ny, nx), np.uint16, 4095)
+        cam = synth.orbit_camera((nx, ny, nz), 50.0 + 70 * q, 20.0 + 15 * q, 45.0)
+        scs.append(Scene("b", vol, 12, tfs_for(2, 4095), cam, 72 + 8 * q, 40 + 8 * q, True,
+                         1.0, 0.99))
+    vols = [gpu.make_volume(ctx, sc) for sc in scs]
+    try:
+        plain = [gpu.render(ctx, sc, vol=v) for sc, v in zip(scs, vols)]
+        outs = [gpu.alloc_out(sc) for sc in scs]
+        reqs = [gpu.request_for(v, sc, o, s) for sc, v, (o, s) in zip(scs, vols, outs)]
+        vr.vr_render_batch(ctx.ptr, reqs, torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        for (o, s), p in zip(outs, plain):
+            same_bits((o.cpu().numpy(), s.cpu().numpy()), p)
+        outs2 = [gpu.alloc_out(sc) for sc in scs]
+        tickets = [vr.vr_submit(ctx.ptr, gpu.request_for(v, sc, o, s))
+                   for sc, v, (o, s) in zip(scs, vols, outs2)]
+        t0 = time.time()
+        for t in tickets:
+            while vr.vr_poll(ctx.ptr, t).state < 2:
+                assert time.time() - t0 < 60.0, f"ticket {t} stuck"
+                time.sleep(0.0002)
+            assert vr.vr_poll(ctx.ptr, t).state == 2
+            vr.vr_release(ctx.ptr, t)
+        for (o, s), p in zip(outs2, plain):
+            same_bits((o.cpu().numpy(), s.cpu().numpy()), p)
+    finally:
+        for v in vols:
+            v.destroy()

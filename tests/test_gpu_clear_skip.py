@@ -27,17 +27,22 @@ def ctx():
         pass
 
 
-def render_both(ctx, sc, precision):
-    """Render with the skip on and off; restore the default."""
+def render_both(ctx, sc, precision, cells=True):
+    """Render with the skips on and off; restore the default.  With cells the
+    skipping render also jumps over transparent macro cells; it is compared
+    with the per-sample skip alone as well."""
     vol = gpu.make_volume(ctx, sc)
     try:
         vr.vr_test_clear_skip(ctx.ptr, False)
         full = gpu.render(ctx, sc, precision, vol=vol)
+        vr.vr_test_clear_skip(ctx.ptr, 2)
+        sample_only = gpu.render(ctx, sc, precision, vol=vol)
         vr.vr_test_clear_skip(ctx.ptr, True)
         skip = gpu.render(ctx, sc, precision, vol=vol)
     finally:
         vr.vr_test_clear_skip(ctx.ptr, True)
         vol.destroy()
+    assert_same_bits(full, sample_only)
     return full, skip
 
 

@@ -77,6 +77,39 @@ def test_frame_above_2_gib(ctx, row_pairs, dims):
         v.destroy()
 
 
+def test_2_to_the_24_bricks(ctx):
+    """2048 x 2048 x 255 uint8 voxels in 4 x 4 x 4 bricks: 513 x 513 x 64
+    bricks (above 2^24) in a 2.1 GB frame (under 2^31 words).  The volume
+    takes the large-volume addressing, and samples in the last brick layer,
+    whose brick indices pass 2^24, reproduce the field v = k (a brick index
+    wrapped modulo 2^24 would read the first layer's values instead)."""
+    import torch
+    nx, ny, nz = dims = (2048, 2048, 255)
+    v = vr.Volume(ctx, dims, 1, 1, vr.VR_U8, 8, brick=(4, 4, 4))
+    assert v.bytes < 2 ** 31
+    try:
+        assert vr.vr_test_volume_large(v.ptr)
+        k = torch.arange(nz, device="cuda", dtype=torch.uint8)
+        src = k[None, :, None, None].expand(1, nz, ny, nx).contiguous()
+        v.upload(0, src)
+        del src
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(3)
+        n = 1 << 16
+        # brick (bx, by, 63) has index >= 2^24 once 513 by + bx >= 197569
+        lo = np.array([0, 1560, 251.5])
+        hi = np.array([nx - 1, ny - 1, nz - 1])
+        pts = rng.uniform(lo, hi, size=(n, 3)).astype(np.float32)
+        pts[:2] = [[nx - 1, ny - 1, nz - 1], [0, ny - 1, nz - 1.5]]
+        out = torch.zeros(n, dtype=torch.float32, device="cuda")
+        vr.vr_debug_sample(v.ptr, 0, torch.from_numpy(pts).cuda(), n, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().astype(np.float64)
+        np.testing.assert_allclose(got, pts[:, 2].astype(np.float64), rtol=2e-6, atol=0)
+    finally:
+        v.destroy()
+
+
 COEF_4G = ((16, 16, 32, 7), (3, 29, 30, 1000))  # < 2^16 on 1024 x 1024 x 800
 
 
@@ -162,11 +195,11 @@ def oracle_pixels_on_crops(src, sc, eye, pixels):
     """Oracle results of single pixels of one eye, each rendered on its ray's
     crop of the device volume `src` [C][Z][Y][X]."""
     import oracle
-    from paper_1407_2089_amd import workloads
+    from oracle.crop import ray_crop
     res = []
     for pix in pixels:
         px, py = int(pix) % sc.width, int(pix) // sc.width
-        box = workloads.ray_crop(sc.cam, sc.width, sc.height, eye, px, py,
+        box = ray_crop(sc.cam, sc.width, sc.height, eye, px, py,
                        (src.shape[3], src.shape[2], src.shape[1]))
         lo, hi = box if box is not None else (np.zeros(3, int), np.ones(3, int))
         crop = src[:, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]].cpu().numpy()

@@ -1,9 +1,12 @@
 """GPU: playback of a series kept in pinned host memory through a ring of
 device slots (vr_stream_frame / vr_stream_ready) renders every frame exactly
-as the resident series does, bit for bit, with copies overlapping renders."""
+as the resident series does, bit for bit, with copies overlapping renders,
+and streamed frames match the oracle on the frames' own voxels."""
 import numpy as np
 import pytest
 
+import gpu
+import orc
 import paper_1407_2089_amd as vr
 from paper_1407_2089_amd import synth, workloads
 
@@ -102,3 +105,12 @@ def _streamed_playback(ctx, ch, bits, pairs, slots, halves):
         assert torch.equal(got[1][t], ref[1][t]), t
         assert torch.equal(got[0][t].view(torch.int32), ref[0][t].view(torch.int32)), t
     assert float(ref[0][F - 1][..., 3].max()) > 0.1
+    # streamed frames against the oracle on the frame's own voxels
+    for t in (0, F // 2, F - 1):
+        data = host[t].numpy()
+        if data.dtype == np.int16:
+            data = data.view(np.uint16)
+        sc = synth.Scene("stream", data, bits, tfs, cams[t], W, H, True, 1.0, 0.99)
+        st = gpu.compare(got[0][t].cpu().numpy(), got[1][t].cpu().numpy(), orc.render_all(sc),
+                         1e-3)
+        print(f"streamed frame {t}: {st}", flush=True)

@@ -24,10 +24,10 @@ def served():
     need = vr.vr_volume_storage_bytes(d)
     holder = {}
 
-    def make(budget, slots=2, ns_per_ray=0.0, fail_width=-1, max_batch=32):
+    def make(budget, slots=2, ns_per_ray=0.0, fail_width=-1, max_batch=32, launch_ms=0.0):
         ctx = vr.vr_init(-1, budget + need)
         vol = vr.vr_create_volume(ctx, d, FAKE, need)
-        vr.vr_test_fake_backend(ctx, slots, ns_per_ray, fail_width, max_batch)
+        vr.vr_test_fake_backend(ctx, slots, ns_per_ray, fail_width, max_batch, launch_ms)
         holder["ctx"], holder["vol"] = ctx, vol
         return ctx, vol
 
@@ -75,8 +75,37 @@ def test_all_tickets_complete_with_ordered_timestamps(served):
         i = infos[t]
         assert i.state == 2 and i.err == 0
         assert 0 < i.t_arrive_ns <= i.t_admit_ns <= i.t_start_ns <= i.t_done_ns
+        assert i.samples == i.rays  # the fake backend composites one sample per ray
     assert infos[ts[3]].rays == (64 + 24) * 48 * 2
     assert len(set(ts)) == 20
+
+
+def test_start_stamp_is_the_device_span_before_completion(served):
+    # a lone 400 x 250 stereo request "runs" 200000 rays x 1000 ns = 200 ms:
+    # its start stamp lies that span before its completion stamp
+    ctx, vol = served(1 << 30, slots=1, ns_per_ray=1000.0)
+    t = vr.vr_submit(ctx, req(vol, 400, 250))
+    i = wait(ctx, [t])[t]
+    span = i.t_done_ns - i.t_start_ns
+    assert 0.2e9 <= span <= 0.2e9 + 0.05e9, span
+    assert i.t_admit_ns <= i.t_start_ns
+
+
+def test_poll_and_submit_do_not_wait_for_a_slow_launch(served):
+    # each launch takes 400 ms of the serving thread; meanwhile submit and
+    # poll answer at once (the loop does not hold its lock across a launch)
+    ctx, vol = served(1 << 30, slots=1, launch_ms=400.0)
+    a = vr.vr_submit(ctx, req(vol, 16, 16))
+    while vr.vr_poll(ctx, a).state == 0:
+        time.sleep(0.0005)
+    t0 = time.perf_counter()
+    more = []
+    for _ in range(20):
+        assert vr.vr_poll(ctx, a).state in (1, 2)
+        more.append(vr.vr_submit(ctx, req(vol, 16, 16)))
+    dt = time.perf_counter() - t0
+    assert dt < 0.1, dt
+    wait(ctx, [a] + more)
 
 
 def test_late_arrival_is_admitted_while_first_batch_runs(served):
