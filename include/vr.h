@@ -308,6 +308,22 @@ vr_status vr_render_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
 vr_status vr_tune_batch(vr_ctx* ctx, const vr_render_req* reqs, int32_t n, void* hip_stream,
                         int32_t* wave_w, int32_t* wave_h);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * batched launch as vr_render_batch (bitwise the same outputs) that calls no
+ * hipMalloc, hipFree or other allocating routine.  Its tables live in a
+ * static device array of the library (about 256 KiB per GPU, held until the
+ * process ends): n must not exceed 256 (VR_ERR_INVALID_ARG otherwise).  The
+ * tables reach that array by asynchronous copies from pinned staging that
+ * vr_init sets up; the variant kernels are launched directly (no graph).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls on one stream are ordered, calls that overlap on the device
+ * (other streams or contexts of the same GPU) race and must be serialised by
+ * the caller.  Uses the tuned wave tile of the batch's shape class, else the
+ * default; never tunes. */
+vr_status vr_render_batch_noalloc(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
+                                  void* hip_stream);
+
 /* Queue a request for the context's serving loop and return at once with a
  * ticket (the CPU stays free while the GPU renders: Abstract; interactive
  * navigation through time points: Results and Discussion).  The loop admits

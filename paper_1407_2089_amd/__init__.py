@@ -22,7 +22,7 @@ __all__ = [
     "VR_FP32", "VR_FP16", "VR_ORTHO", "VR_PERSPECTIVE", "vr_denoise_workspace_bytes",
     "vr_remove_background", "vr_mrf_denoise", "gaussian_weights", "remove_background",
     "mrf_denoise", "vr_stream_frame", "vr_stream_ready", "vr_gaussian_weights",
-    "vr_tune_batch",
+    "vr_tune_batch", "vr_render_batch_noalloc",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvr.so")
@@ -125,6 +125,7 @@ def lib():
             "vr_set_transfer": [P, C.c_int32, C.POINTER(vr_transfer)],
             "vr_render": [P, C.POINTER(vr_render_req), P],
             "vr_render_batch": [P, C.POINTER(vr_render_req), C.c_int32, P],
+            "vr_render_batch_noalloc": [P, C.POINTER(vr_render_req), C.c_int32, P],
             "vr_tune_batch": [P, C.POINTER(vr_render_req), C.c_int32, P,
                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
             "vr_submit": [P, C.POINTER(vr_render_req), C.POINTER(C.c_uint64)],
@@ -232,6 +233,12 @@ def vr_render_batch(ctx, reqs, stream=None):
     n = len(reqs)
     arr = (vr_render_req * max(n, 1))(*reqs)
     _check(lib().vr_render_batch(ctx, arr, n, _stream(stream)))
+
+
+def vr_render_batch_noalloc(ctx, reqs, stream=None):
+    n = len(reqs)
+    arr = (vr_render_req * max(n, 1))(*reqs)
+    _check(lib().vr_render_batch_noalloc(ctx, arr, n, _stream(stream)))
 
 
 def vr_tune_batch(ctx, reqs, stream=None):

@@ -511,6 +511,11 @@ vr_status vr_init(int32_t device, uint64_t mem_budget_bytes, vr_ctx** out) {
         mem_budget_bytes = free_b > reserve ? free_b - reserve : free_b / 2;
     }
     ctx->budget = mem_budget_bytes;
+    vr_status st = noalloc_init(ctx);
+    if (st != VR_OK) {
+        delete ctx;
+        return st;
+    }
     *out = ctx;
     return ok();
 }
@@ -524,6 +529,7 @@ vr_status vr_shutdown(vr_ctx* ctx) {
     DeviceGuard dg(ctx->device);
     for (auto& kv : ctx->batch_slots) batch_slot_destroy(kv.second);
     ctx->batch_slots.clear();
+    if (ctx->device >= 0) noalloc_release(ctx);
     delete ctx;
     return ok();
 }

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -392,9 +393,136 @@ static vr_status enqueue_with(vr_ctx* ctx, BatchSlot* s, const ReqParams* params
     return VR_OK;
 }
 
+// ------------------------------------------------- allocation-free batches
+// vr_render_batch_noalloc keeps its tables in `scratch`, a static device
+// array of this file (one copy per GPU, held until the process ends): the
+// batch description, up to kNoAllocRequests request descriptors and their
+// first work items.  Host code never passes `scratch` itself (its name is a
+// host-side stand-in); it uses the address hipGetSymbolAddress gives on each
+// device, kept in the context by vr_init.  Tables reach the array by an
+// asynchronous copy from pinned staging (two halves that alternate; a half
+// is rewritten once the copy out of it has run), then the variant kernels
+// are launched directly.  Every call on a GPU shares that GPU's array: calls
+// that overlap on the device (different streams, or contexts) race; calls on
+// one stream are ordered.
+constexpr int kNoAllocRequests = 256;
+struct NoAllocTables {
+    BatchWork work;
+    ReqParams reqs[kNoAllocRequests];
+    int32_t prefix[kNoAllocRequests];
+};
+constexpr size_t kNoAllocScratchBytes = (sizeof(NoAllocTables) + 255) & ~(size_t)255;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+vr_status noalloc_init(vr_ctx* ctx) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    ctx->noalloc_dev = (uint8_t*)ptr;
+    ctx->noalloc_params = new ReqParams[kNoAllocRequests];
+    for (int h = 0; h < 2; ++h) {
+        if ((e = hipHostMalloc(&ctx->noalloc_host[h], sizeof(NoAllocTables),
+                               hipHostMallocDefault)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&ctx->noalloc_ev[h], hipEventDisableTiming)) !=
+                hipSuccess) {
+            noalloc_release(ctx);
+            return hip_fail(e, "allocation-free batch staging");
+        }
+    }
+    return VR_OK;
+}
+
+void noalloc_release(vr_ctx* ctx) {
+    for (int h = 0; h < 2; ++h) {
+        if (ctx->noalloc_ev[h]) {
+            (void)hipEventSynchronize(ctx->noalloc_ev[h]);
+            (void)hipEventDestroy(ctx->noalloc_ev[h]);
+        }
+        if (ctx->noalloc_host[h]) (void)hipHostFree(ctx->noalloc_host[h]);
+        ctx->noalloc_ev[h] = nullptr;
+        ctx->noalloc_host[h] = nullptr;
+    }
+    ctx->noalloc_dev = nullptr;
+    delete[] ctx->noalloc_params;
+    ctx->noalloc_params = nullptr;
+}
+
 }  // namespace vr
 
 using namespace vr;
+
+extern "C" vr_status vr_render_batch_noalloc(vr_ctx* ctx, const vr_render_req* reqs, int32_t n,
+                                             void* hip_stream) {
+    if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");
+    if (n < 0) return fail(VR_ERR_INVALID_ARG, "n < 0");
+    if (n > kNoAllocRequests)
+        return fail(VR_ERR_INVALID_ARG, "%d requests: the allocation-free batch takes at most %d",
+                    n, kNoAllocRequests);
+    if (n > 0 && !reqs) return fail(VR_ERR_INVALID_ARG, "requests are NULL");
+    for (int q = 0; q < n; ++q) {
+        vr_status st = check_request(ctx, &reqs[q]);
+        if (st != VR_OK) return st;
+    }
+    if (ctx->device < 0) return fail(VR_ERR_UNSUPPORTED, "validation-only context");
+    if (n == 0) return ok();
+    if (!ctx->noalloc_dev) return fail(VR_ERR_DEVICE, "allocation-free batches are not set up");
+    DeviceGuard dg(ctx->device);
+    const hipStream_t stream = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lk(ctx->noalloc_mu);
+    const int h = ctx->noalloc_next;
+    hipError_t e;
+    if (ctx->noalloc_used[h] && (e = hipEventSynchronize(ctx->noalloc_ev[h])) != hipSuccess)
+        return hip_fail(e, "staging wait");
+    NoAllocTables* T = (NoAllocTables*)ctx->noalloc_host[h];
+    // Parameters in the staging's request array first; lit requests and large
+    // volumes take plain launches (their parameters travel as kernel
+    // arguments), the rest are compacted to the front.
+    int m = 0;
+    for (int q = 0; q < n; ++q) {
+        ReqParams P;
+        {
+            std::lock_guard<std::mutex> tl(reqs[q].vol->tf_mu);
+            make_params(reqs[q], reqs[q].vol->tf, &P);
+        }
+        if (P.light.on != 0 || variant_large(P.variant)) {
+            if ((e = launch_render(P, ctx->plain_tile, ctx->clear_skip, stream)) != hipSuccess)
+                return hip_fail(e, "render launch");
+            continue;
+        }
+        T->reqs[m++] = P;
+    }
+    if (m == 0) return ok();
+    TileShape ts = ctx->batch_tile;
+    if (!ctx->forced_tile && ctx->autotune) {
+        std::lock_guard<std::mutex> tl(ctx->mu);
+        auto it = ctx->tuned.find(shape_class(T->reqs, m));
+        if (it != ctx->tuned.end()) ts = it->second;
+    }
+    // build_tables reads the parameters from a second array: the sorted copy
+    // goes to the staging's tables.
+    ReqParams* unsorted = ctx->noalloc_params;
+    int order[kNoAllocRequests];
+    double cost[kNoAllocRequests];
+    for (int q = 0; q < m; ++q) unsorted[q] = T->reqs[q];
+    uint64_t mask = 0;
+    int32_t blocks[kBatchVariants];
+    vr_status st = build_tables(unsorted, m, ts, order, cost, T->reqs, T->prefix, &T->work, &mask,
+                                blocks);
+    if (st != VR_OK) return st;
+    if (mask == 0) return ok();
+    NoAllocTables* D = (NoAllocTables*)ctx->noalloc_dev;
+    const size_t bytes = offsetof(NoAllocTables, reqs) + sizeof(ReqParams) * (size_t)m;
+    if ((e = hipMemcpyAsync(D, T, bytes, hipMemcpyHostToDevice, stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(D->prefix, T->prefix, sizeof(int32_t) * (size_t)m,
+                            hipMemcpyHostToDevice, stream)) != hipSuccess ||
+        (e = hipEventRecord(ctx->noalloc_ev[h], stream)) != hipSuccess)
+        return hip_fail(e, "table upload");
+    ctx->noalloc_used[h] = true;
+    ctx->noalloc_next = 1 - h;
+    if ((e = launch_batch(&D->work, D->reqs, D->prefix, mask, blocks, stream)) != hipSuccess)
+        return hip_fail(e, "batch launch");
+    return ok();
+}
 
 extern "C" vr_status vr_test_batch_tile(vr_ctx* ctx, int32_t wave_w, int32_t wave_h) {
     if (!ctx) return fail(VR_ERR_INVALID_ARG, "context is NULL");

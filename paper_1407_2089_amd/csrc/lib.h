@@ -108,6 +108,16 @@ struct vr_ctx {
     std::map<uint64_t, vr::TileShape> tuned;
     vr::Scheduler* server = nullptr;  // created by the first vr_submit (server.cpp)
     std::mutex server_mu;
+    // vr_render_batch_noalloc (batch.cpp): the device address of the
+    // library's static scratch array on this context's device, and pinned
+    // staging of its tables, all set up by vr_init.
+    uint8_t* noalloc_dev = nullptr;
+    void* noalloc_host[2] = {nullptr, nullptr};
+    hipEvent_t noalloc_ev[2] = {nullptr, nullptr};
+    bool noalloc_used[2] = {false, false};
+    int noalloc_next = 0;
+    vr::ReqParams* noalloc_params = nullptr;  // host array of kNoAllocRequests
+    std::mutex noalloc_mu;
 };
 
 namespace vr {
@@ -130,6 +140,10 @@ void make_params(const vr_render_req& r, const vr_transfer* tf, ReqParams* P);
 TileShape default_tile();
 
 // Batched path (batch.cpp).
+// Sets up vr_render_batch_noalloc on the context's device (the device is
+// current): the scratch array's address and the pinned staging.
+vr_status noalloc_init(vr_ctx* ctx);
+void noalloc_release(vr_ctx* ctx);
 // Enqueues a batch with the tile tuned for its shape class (or the default);
 // never tunes and never waits for the device beyond its staging buffers.
 vr_status batch_enqueue(vr_ctx* ctx, BatchSlot* slot, const ReqParams* params, int n);

@@ -25,7 +25,7 @@ def declared_symbols(header="vr.h"):
 def test_library_exports_every_declared_symbol():
     L = vr.lib()
     names = declared_symbols()
-    assert "vr_render" in names and "vr_submit" in names and len(names) == 17
+    assert "vr_render" in names and "vr_submit" in names and len(names) == 18
     assert "vr_tune_batch" in names
     assert "vr_stream_frame" in names and "vr_stream_ready" in names
     dn = declared_symbols("vr_denoise.h")
