@@ -47,8 +47,8 @@ static void free_tables(BatchSlot* s) {
 
 static void drop_graphs(BatchSlot* s) {
     for (auto& kv : s->graphs) {
-        if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
-        if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
     }
     s->graphs.clear();
 }
@@ -119,33 +119,40 @@ BatchSlot* batch_slot_for(vr_ctx* ctx, hipStream_t stream, vr_status* st) {
 
 // The batch's kernels, one per variant present with its own grid, as
 // parallel branches of one graph (built node by node), instantiated once per
-// (variants present, grid sizes).
+// set of variants present; a batch whose grids differ from the last launch
+// of that graph updates the nodes in place (no new instantiation: serving
+// forms batches of ever-changing sizes).
 static vr_status graph_for(BatchSlot* s, uint64_t mask, const int32_t* blocks,
                            hipGraphExec_t* out) {
-    std::string key;
-    for (int v = 0; v < kBatchVariants; ++v)
-        if (mask & (1ull << v)) key += std::to_string(v) + ":" + std::to_string(blocks[v]) + ",";
-    auto it = s->graphs.find(key);
+    hipError_t e;
+    auto it = s->graphs.find(mask);
     if (it != s->graphs.end()) {
-        *out = it->second.second;
+        BatchSlot::Graph& g = it->second;
+        for (int v = 0; v < kBatchVariants; ++v) {
+            if (!(mask & (1ull << v)) || g.blocks[v] == blocks[v]) continue;
+            e = set_batch_node_grid(g.exec, g.node[v], v, blocks[v], s->d_work, s->d_reqs,
+                                    s->d_prefix);
+            if (e != hipSuccess) return hip_fail(e, "batch graph update");
+            g.blocks[v] = blocks[v];
+        }
+        *out = g.exec;
         return VR_OK;
     }
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipError_t e = hipGraphCreate(&graph, 0);
-    if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
-    e = add_batch_nodes(graph, s->d_work, s->d_reqs, s->d_prefix, mask, blocks);
+    BatchSlot::Graph g;
+    if ((e = hipGraphCreate(&g.graph, 0)) != hipSuccess) return hip_fail(e, "hipGraphCreate");
+    e = add_batch_nodes(g.graph, s->d_work, s->d_reqs, s->d_prefix, mask, blocks, g.node);
     if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
+        (void)hipGraphDestroy(g.graph);
         return hip_fail(e, "batch graph nodes");
     }
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
+        (void)hipGraphDestroy(g.graph);
         return hip_fail(e, "hipGraphInstantiate");
     }
-    s->graphs[key] = {graph, exec};
-    *out = exec;
+    for (int v = 0; v < kBatchVariants; ++v) g.blocks[v] = blocks[v];
+    s->graphs[mask] = g;
+    *out = g.exec;
     return VR_OK;
 }
 

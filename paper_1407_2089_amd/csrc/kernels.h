@@ -40,10 +40,15 @@ hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
                         const int32_t* dev_prefix, uint64_t mask, const int32_t* blocks,
                         hipStream_t s);
 // The same kernels as independent nodes of `graph` (parallel branches: the
-// variants' kernels may overlap on the device).
+// variants' kernels may overlap on the device); nodes[v] receives variant
+// v's node.
 hipError_t add_batch_nodes(hipGraph_t graph, const BatchWork* dev_work,
                            const ReqParams* dev_reqs, const int32_t* dev_prefix, uint64_t mask,
-                           const int32_t* blocks);
+                           const int32_t* blocks, hipGraphNode_t* nodes);
+// Sets the grid of variant v's node in an instantiated batch graph.
+hipError_t set_batch_node_grid(hipGraphExec_t exec, hipGraphNode_t node, int v, int blocks,
+                               const BatchWork* dev_work, const ReqParams* dev_reqs,
+                               const int32_t* dev_prefix);
 hipError_t launch_debug_sample(const ReqParams& P, const float* pts, int n, float* out,
                                hipStream_t s);
 

@@ -427,9 +427,10 @@ hipError_t launch_batch(const BatchWork* dev_work, const ReqParams* dev_reqs,
 
 hipError_t add_batch_nodes(hipGraph_t graph, const BatchWork* dev_work,
                            const ReqParams* dev_reqs, const int32_t* dev_prefix, uint64_t mask,
-                           const int32_t* blocks) {
+                           const int32_t* blocks, hipGraphNode_t* nodes) {
     if (mask >> kBatchVariants) return hipErrorInvalidValue;
     for (int v = 0; v < kBatchVariants; ++v) {
+        nodes[v] = nullptr;
         if (!(mask & (1ull << v))) continue;
         if (!kBatch[v] || blocks[v] <= 0) return hipErrorInvalidValue;
         void* args[3] = {(void*)&dev_work, (void*)&dev_reqs, (void*)&dev_prefix};
@@ -440,11 +441,25 @@ hipError_t add_batch_nodes(hipGraph_t graph, const BatchWork* dev_work,
         np.sharedMemBytes = 0;
         np.kernelParams = args;
         np.extra = nullptr;
-        hipGraphNode_t node = nullptr;
-        const hipError_t e = hipGraphAddKernelNode(&node, graph, nullptr, 0, &np);
+        const hipError_t e = hipGraphAddKernelNode(&nodes[v], graph, nullptr, 0, &np);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t set_batch_node_grid(hipGraphExec_t exec, hipGraphNode_t node, int v, int blocks,
+                               const BatchWork* dev_work, const ReqParams* dev_reqs,
+                               const int32_t* dev_prefix) {
+    if (v < 0 || v >= kBatchVariants || !kBatch[v] || blocks <= 0) return hipErrorInvalidValue;
+    void* args[3] = {(void*)&dev_work, (void*)&dev_reqs, (void*)&dev_prefix};
+    hipKernelNodeParams np{};
+    np.func = (void*)kBatch[v];
+    np.gridDim = dim3((unsigned)blocks);
+    np.blockDim = dim3(kWave);
+    np.sharedMemBytes = 0;
+    np.kernelParams = args;
+    np.extra = nullptr;
+    return hipGraphExecKernelNodeSetParams(exec, node, &np);
 }
 
 typedef void (*debug_fn)(ReqParams, const float*, int, float*);

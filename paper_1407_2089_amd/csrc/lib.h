@@ -52,8 +52,16 @@ struct BatchSlot {
     bool staged_pending = false;
     // Captured launches, one per (set of variants present, grid size) of a
     // batch (they hold the table addresses: dropped when the tables grow).
-    // key: the variants present and each one's grid size
-    std::map<std::string, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // One instantiated graph per set of variants present (the key), with
+    // each variant's node and the grid it was last launched with (updated in
+    // place when a batch needs another).
+    struct Graph {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipGraphNode_t node[kBatchVariants] = {};
+        int32_t blocks[kBatchVariants] = {};
+    };
+    std::map<uint64_t, Graph> graphs;
 };
 
 // Sets the calling thread's error message and returns `st`.

@@ -910,11 +910,15 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
     }
     if (P.nsamples) {
         // The request's composited samples: a wave-wide sum (every lane of
-        // the wave arrives here), one atomic add per wave.
+        // the wave arrives here), then one atomic add per wave with samples,
+        // to the counter slot of its hardware block (device-scope atomics on
+        // one address would serialise across the XCDs).
         int v = valid ? count : 0;
 #pragma unroll
         for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-        if ((threadIdx.x & (kWave - 1)) == 0) atomicAdd(P.nsamples, (unsigned long long)v);
+        if ((threadIdx.x & (kWave - 1)) == 0 && v != 0)
+            atomicAdd(P.nsamples + (blockIdx.x % kCountSlots) * kCountStride,
+                      (unsigned long long)v);
     }
 }
 

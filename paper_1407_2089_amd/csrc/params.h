@@ -152,7 +152,10 @@ struct ReqParams {
     int32_t skip_cells;     // 1: rays jump over macro cells shown transparent
     float* out;             // [eyes][H][W][4]
     int32_t* samples;       // [eyes][H][W] or null
-    unsigned long long* nsamples;  // device counter: += samples composited, or null
+    // Samples composited, or null: kCountSlots counters kCountStride words
+    // apart (one per 64-byte line), a wave adding to the one its block picks,
+    // so that a request's waves do not all serialise on one address.
+    unsigned long long* nsamples;
     // Large variants: the same ray basis in FP64, and the clamp bound of
     // stored coordinates (largest double below n + 1 per axis).
     struct {
@@ -161,6 +164,9 @@ struct ReqParams {
         double clamp_hi[3];
     } d64;
 };
+
+constexpr int kCountSlots = 64;
+constexpr int kCountStride = 8;
 
 // Work decomposition: one item = one wave's pixel tile of one eye of one
 // request.  Waves take items independently (a wave whose rays end early

@@ -27,11 +27,9 @@ class HipBackend : public Backend {
             if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventCreate(&sl.t0);
             if (e == hipSuccess) e = hipEventCreate(&sl.t1);
+            if (e == hipSuccess) e = hipMalloc(&sl.d_count, count_bytes(max_batch));
             if (e == hipSuccess)
-                e = hipMalloc(&sl.d_count, sizeof(unsigned long long) * (size_t)max_batch);
-            if (e == hipSuccess)
-                e = hipHostMalloc(&sl.h_count, sizeof(unsigned long long) * (size_t)max_batch,
-                                  hipHostMallocDefault);
+                e = hipHostMalloc(&sl.h_count, count_bytes(max_batch), hipHostMallocDefault);
             if (e != hipSuccess) {
                 *st = hip_fail(e, "serving slot");
                 destroy(sl);
@@ -56,14 +54,13 @@ class HipBackend : public Backend {
         sl.n = n;
         // counters cleared by a kernel-free memset on the stream: the batch's
         // graph is launched after it and does not contain it
-        hipError_t e = hipMemsetAsync(sl.d_count, 0, sizeof(unsigned long long) * (size_t)n,
-                                      sl.stream);
+        hipError_t e = hipMemsetAsync(sl.d_count, 0, count_bytes(n), sl.stream);
         if (e == hipSuccess) e = hipEventRecord(sl.t0, sl.stream);
         if (e != hipSuccess) return hip_fail(e, "serving launch");
         params_.resize(jobs.size());
         for (int q = 0; q < n; ++q) {
             params_[q] = jobs[q]->params;
-            params_[q].nsamples = sl.d_count + q;
+            params_[q].nsamples = sl.d_count + (size_t)q * kCountSlots * kCountStride;
         }
         if (n == 1) {
             // A lone request takes the plain launch: its parameters travel as
@@ -78,8 +75,8 @@ class HipBackend : public Backend {
             if (st != VR_OK) return st;
         }
         if ((e = hipEventRecord(sl.t1, sl.stream)) != hipSuccess ||
-            (e = hipMemcpyAsync(sl.h_count, sl.d_count, sizeof(unsigned long long) * (size_t)n,
-                                hipMemcpyDeviceToHost, sl.stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(sl.h_count, sl.d_count, count_bytes(n), hipMemcpyDeviceToHost,
+                                sl.stream)) != hipSuccess ||
             (e = hipEventRecord(sl.done, sl.stream)) != hipSuccess)
             return hip_fail(e, "serving launch");
         return VR_OK;
@@ -97,10 +94,18 @@ class HipBackend : public Backend {
     }
     uint64_t samples(int slot, int q) const override {
         const Slot& sl = slots_[slot];
-        return q < sl.n ? (uint64_t)sl.h_count[q] : 0;
+        if (q >= sl.n) return 0;
+        uint64_t s = 0;
+        const unsigned long long* c = sl.h_count + (size_t)q * kCountSlots * kCountStride;
+        for (int i = 0; i < kCountSlots; ++i) s += c[(size_t)i * kCountStride];
+        return s;
     }
 
   private:
+    // Counter slots of n requests (kCountSlots per request, one per line).
+    static size_t count_bytes(int n) {
+        return sizeof(unsigned long long) * (size_t)n * kCountSlots * kCountStride;
+    }
     struct Slot {
         hipStream_t stream = nullptr;
         hipEvent_t done = nullptr, t0 = nullptr, t1 = nullptr;
