@@ -4,10 +4,22 @@ Default workload: 2-channel 12-bit uint16 512x512x64 confocal-like volume
 (40 ellipsoidal cells, 10 spline vessels, Poisson noise), perspective stereo
 pair 1920x1080 per eye, step 1 voxel, early termination at alpha 0.99, FP32.
 One step = one stereo pair (one vr_render launch, both eyes).  Prints one
-JSON line: ray-samples/s (composited samples, the method's nominal count),
-stereo frames/s, the HBM roofline of the render kernel on effective sampled
-bytes (8 taps x channels x bytes per voxel per sample), and the FP64 CPU
-oracle timed on a bounded pixel sample of the same frame.
+JSON line:
+  - value: ray-samples/s (composited samples, the method's nominal count,
+    which empty-space skipping leaves unchanged) and stereo frames/s, timed
+    after a warm-up of at least 0.3 s;
+  - roofline: the render kernel's median launch time (HIP events on its
+    stream), its effective sampled bytes (8 taps x channels x bytes per
+    voxel per sample) over that time against the 8 TB/s HBM peak, the
+    compulsory-byte fraction (the frame's voxels and the image, once), the
+    same launch without the exact skips, and HBM traffic and VALU busy
+    measured by rocprofv3 counter passes over the same launch (child
+    processes);
+  - cpu_baseline: the FP64 oracle timed on the host cores;
+  - batching: 64 mixed requests, one batched launch against 64 plain ones;
+  - serving: 150 GB of resident series, Poisson arrivals served by the
+    continuous-batching loop against a FIFO server of plain launches,
+    p50/p99 latency and frames/s per rate.
 """
 import argparse
 import json
@@ -20,7 +32,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-COUNTERS = os.path.join(ROOT, "profiles", "render_2ch_u16_realistic_stereo_counters.txt")
 
 
 def _light():
@@ -28,54 +39,73 @@ def _light():
     return Light((0.4, -0.3, -0.8), 0.3, 0.7)
 
 
-def render_kernel_hash():
-    """sha256 of the render kernel's source (march.h, params.h and the plain
-    render kernel's part of kernels.hip)."""
-    import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1407_2089_amd", "csrc")
-    for f in ("march.h", "params.h"):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
-    with open(os.path.join(csrc, "kernels.hip")) as fh:
-        k = fh.read()
-    a = k.index("// ------------------------------------------------------------ plain render")
-    b = k.index("// -------------------------------------------------------- batched render")
-    h.update(k[a:b].encode())
-    return h.hexdigest()
+# rocprofv3 counter passes of the headline kernel, each in a child process of
+# its own (one pass per run: the profiler does not split counters over passes)
+COUNTER_PASSES = [("FETCH_SIZE",), ("WRITE_SIZE",), ("VALUBusy",),
+                  ("SQ_INSTS_VALU", "SQ_INSTS_VMEM_RD", "SQ_WAVES")]
 
 
-def measured_counters():
-    """From the committed rocprofv3 counter summary of the headline kernel:
-    HBM-side bytes per launch (FETCH_SIZE and WRITE_SIZE, scaled by a plain
-    copy's readings), VALU busy and TA busy fractions; an empty dict once the
-    kernel's source has changed since the counters were taken."""
+def _pmc_pass(counters, child_args, tag, workdir, timeout_s=150):
+    """Runs `rocprofv3 --pmc <counters> -- python3 bench.py <child_args>` and
+    returns {counter: mean value per dispatch} over the dispatches whose
+    kernel name contains `tag`, or raises RuntimeError."""
+    import csv
+    import glob
+    import signal
+    import subprocess
+    out_dir = os.path.join(workdir, "pmc_" + "_".join(counters) + "_" + str(len(child_args)))
+    cmd = ["rocprofv3", "--pmc", *counters, "-d", out_dir, "-o", "pmc", "--output-format",
+           "csv", "--", sys.executable, os.path.abspath(__file__), *child_args]
+    env = dict(os.environ, TMPDIR="/tmp")
+    proc = subprocess.Popen(cmd, cwd="/tmp", env=env, stdout=subprocess.PIPE,
+                            stderr=subprocess.STDOUT, start_new_session=True)
     try:
-        with open(COUNTERS) as fh:
-            text = fh.read()
-    except OSError:
-        return {}
-    import re
-    h = re.search(r"sha256 \(.*\):\s*([0-9a-f]{64})", text)
-    if not h or h.group(1) != render_kernel_hash():
-        return {}
-    out = {}
-    t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
-    if t:
-        out["traffic"] = int(t.group(1))
-    v = re.search(r"VALUBusy ([0-9.]+) %", text)
-    if v:
-        out["valu_busy"] = float(v.group(1)) / 100.0
-    a = re.search(r"TA busy ([0-9.]+) %", text)
-    if a:
-        out["ta_busy"] = float(a.group(1)) / 100.0
-    return out
+        text, _ = proc.communicate(timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        os.killpg(proc.pid, signal.SIGKILL)
+        proc.communicate()
+        raise RuntimeError(f"rocprofv3 --pmc {' '.join(counters)} timed out")
+    files = glob.glob(os.path.join(out_dir, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        tail = text.decode(errors="replace")[-400:]
+        raise RuntimeError(f"rocprofv3 --pmc {' '.join(counters)} wrote no counters "
+                           f"(rc {proc.returncode}): {tail}")
+    sums, dispatches = {}, {}
+    for f in files:
+        with open(f, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if tag not in row.get("Kernel_Name", ""):
+                    continue
+                name = row["Counter_Name"]
+                sums[name] = sums.get(name, 0.0) + float(row["Counter_Value"])
+                dispatches.setdefault(name, set()).add(row.get("Dispatch_Id"))
+    if not sums:
+        raise RuntimeError(f"no dispatch of {tag} in the counters of {' '.join(counters)}")
+    return {k: v / len(dispatches[k]) for k, v in sums.items()}
 
 
-def measured_traffic():
-    """HBM-side bytes per launch of the headline kernel (see
-    measured_counters), or None."""
-    return measured_counters().get("traffic")
+def live_counters(scene_npy, extra, workdir):
+    """Counter passes over the headline kernel (skips on) and a plain 1 GiB
+    copy, in child processes: HBM-side bytes per launch (FETCH_SIZE and
+    WRITE_SIZE in KiB, each scaled by what it reads for the copy of known
+    size), VALU busy and VALU / vector-memory instructions per launch."""
+    child = ["--mode", "counters", "--scene-npy", scene_npy] + list(extra)
+    r = {}
+    for counters in COUNTER_PASSES:
+        log(f"counters: {' '.join(counters)}")
+        r.update(_pmc_pass(counters, child, "render_kernel", workdir))
+    copy = {}
+    for counters in (("FETCH_SIZE",), ("WRITE_SIZE",)):
+        log(f"counters: copy calibration {counters[0]}")
+        copy.update(_pmc_pass(counters, ["--mode", "copy"], "copy", workdir))
+    gib_kib = float(1 << 20)  # the copy reads and writes 1 GiB = 2^20 KiB
+    f_scale = gib_kib / copy["FETCH_SIZE"]
+    w_scale = gib_kib / copy["WRITE_SIZE"]
+    traffic = (r["FETCH_SIZE"] * f_scale + r["WRITE_SIZE"] * w_scale) * 1024.0
+    return {"traffic": traffic, "fetch_kib": r["FETCH_SIZE"], "write_kib": r["WRITE_SIZE"],
+            "fetch_scale": f_scale, "write_scale": w_scale,
+            "valu_busy": r["VALUBusy"] / 100.0, "valu_insts": r["SQ_INSTS_VALU"],
+            "vmem_rd_insts": r["SQ_INSTS_VMEM_RD"], "waves": r["SQ_WAVES"]}
 
 
 def log(msg):
@@ -157,7 +187,7 @@ def montage_cpu_baseline(src, cam, tfs, W, H, target_s=10.0):
     import numpy as np
 
     import oracle
-    from paper_1407_2089_amd import workloads
+    from oracle.crop import ray_crop
     rng = np.random.default_rng(12345)
     otf = [oracle.Transfer(t.lo, t.hi, t.curve, t.alpha_mul, t.rgb, t.visible) for t in tfs]
     ocam = oracle.Camera(cam.projection, cam.center, cam.forward, cam.up, cam.fov_y,
@@ -167,7 +197,7 @@ def montage_cpu_baseline(src, cam, tfs, W, H, target_s=10.0):
     while spent < target_s:
         pix = int(rng.integers(W * H))
         eye = -1 if rng.integers(0, 2) == 0 else 1
-        box = workloads.ray_crop(cam, W, H, eye, pix % W, pix // W, dims)
+        box = ray_crop(cam, W, H, eye, pix % W, pix // W, dims)
         if box is None:
             continue
         lo, hi = box
@@ -225,8 +255,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", choices=["fp32", "fp16"], default="fp32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--mode", choices=["render", "copy"], default="render",
-                    help="copy: a plain 1 GiB device copy, to calibrate HBM byte counters")
+    ap.add_argument("--mode", choices=["render", "copy", "counters"], default="render",
+                    help="copy: a plain 1 GiB device copy, to calibrate HBM byte counters; "
+                         "counters: the headline launch alone (a counter pass's child)")
     ap.add_argument("--workload", choices=["realistic", "tiny", "batch", "serve", "precision",
                                            "layout", "denoise", "stream", "montage"],
                     default="realistic",
@@ -248,6 +279,16 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-gb", type=float, default=150.0)
     ap.add_argument("--serve-rates", default="25,100,400,1000,1600,2400,3200,4000")
+    ap.add_argument("--no-counters", action="store_true",
+                    help="skip the rocprofv3 counter passes of the headline kernel")
+    ap.add_argument("--no-batch", dest="batch", action="store_false",
+                    help="skip the batching leg (64 mixed requests) of the default run")
+    ap.add_argument("--no-serve", dest="serve", action="store_false",
+                    help="skip the serving leg of the default run")
+    ap.add_argument("--serve-rates-short", default="400,2400,6000",
+                    help="arrival rates of the default run's serving leg")
+    ap.add_argument("--serve-short-seconds", type=float, default=4.0)
+    ap.add_argument("--scene-npy", default="", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -303,6 +344,12 @@ def main():
         print(json.dumps(res), flush=True)
         return
 
+    if args.mode == "counters":
+        sc = synth.realistic_scene(volume=not args.scene_npy)
+        if args.lit:
+            sc.light = _light()
+        counters_child(args, sc)
+        return
     log("generating workload")
     sc = synth.realistic_scene()
     if args.lit:
@@ -332,40 +379,71 @@ def main():
     req = vr.make_request(vol.ptr, 0, sc.cam, sc.width, sc.height, True, sc.step,
                           sc.term_alpha, out, precision=prec, light=sc.light)
 
-    def timed(r):
-        log(f"warmup {args.warmup}")
-        for _ in range(args.warmup):
+    def timed(r, steps, warmup):
+        """Warm-up of `warmup` launches and at least 0.3 s (clocks settle),
+        then `steps` launches, each bracketed by events on the launch stream;
+        returns (wall seconds of the timed launches, median and mean kernel
+        ms)."""
+        for _ in range(warmup):
             vr.vr_render(ctx.ptr, r, stream)
-        torch.cuda.synchronize()
-        log(f"timing {args.steps} steps")
+        t_end = time.perf_counter() + 0.3
+        while time.perf_counter() < t_end:
+            for _ in range(20):
+                vr.vr_render(ctx.ptr, r, stream)
+            torch.cuda.synchronize()
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(args.steps)]
+              for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(args.steps):
+        for k in range(steps):
             ev[k][0].record(stream)
             vr.vr_render(ctx.ptr, r, stream)
             ev[k][1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        return wall, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        ms = [a.elapsed_time(b) for a, b in ev]
+        return wall, float(np.median(ms)), float(np.mean(ms))
 
-    wall, kernel_ms = timed(req)
+    log(f"warmup {args.warmup} launches and 0.3 s; timing {args.steps} steps")
+    wall, kernel_ms, kernel_mean_ms = timed(req, args.steps, args.warmup)
     ms_per_step = 1000.0 * wall / args.steps
     value = samples_per_step * args.steps / wall
+    # the same launch without the exact skips (every sample walked and
+    # composited), and with the per-sample test only (every sample walked)
+    log("no-skip kernels")
+    vr.vr_test_clear_skip(ctx.ptr, 0)
+    _, noskip_ms, _ = timed(req, max(args.steps, 20), 2)
+    vr.vr_test_clear_skip(ctx.ptr, 2)
+    _, sample_skip_ms, _ = timed(req, max(args.steps, 20), 2)
+    vr.vr_test_clear_skip(ctx.ptr, 1)
     unlit_ms = None
     if args.lit:
         log("unlit kernel for the ratio")
-        _, unlit_ms = timed(vr.make_request(vol.ptr, 0, sc.cam, sc.width, sc.height, True,
-                                            sc.step, sc.term_alpha, out, precision=prec))
+        _, unlit_ms, _ = timed(vr.make_request(vol.ptr, 0, sc.cam, sc.width, sc.height, True,
+                                               sc.step, sc.term_alpha, out, precision=prec),
+                               max(args.steps, 20), 2)
 
     bytes_per_sample = 8 * c * 2
     alg_bytes = samples_per_step * bytes_per_sample
-    headline_layout = (args.precision == "fp32" and brick == (0, 0, 0) and not args.tile
-                       and pairs and not args.lit)
-    counters = measured_counters() if headline_layout else {}
-    traffic = counters.get("traffic")
+    # compulsory: every voxel of the frame once (the whole volume is in view)
+    # plus the stereo image once
+    compulsory = nx * ny * nz * c * 2 + out.numel() * 4
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
+    noskip_achieved = alg_bytes / (noskip_ms * 1e-3) / 1e9
+    kernel_name = (f"render_kernel<2ch,u16,{args.precision},{args.layout}"
+                   + (",lit>" if args.lit else ">"))
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                "traffic_unit": "bytes/launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": kernel_name, "kernel_ms": kernel_ms, "kernel_mean_ms": kernel_mean_ms,
+                "bytes_per_launch": alg_bytes,
+                "bytes_note": "effective bytes: 8 taps x channels x 2 B per composited sample, "
+                              "priced as HBM bytes although caches serve most taps",
+                "compulsory_bytes": compulsory,
+                "compulsory_frac": compulsory / (kernel_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                "noskip_kernel_ms": noskip_ms, "noskip_achieved": noskip_achieved,
+                "noskip_frac": noskip_achieved / PEAK_HBM_GBS,
+                "sample_skip_only_kernel_ms": sample_skip_ms}
     result = {
         "metric": "ray-samples/s",
         "value": value,
@@ -387,35 +465,89 @@ def main():
                    "tile": args.tile or "8,8",
                    "samples_per_step": samples_per_step},
         "stereo_fps": args.steps / wall,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "traffic_unit": "bytes/launch (L2-to-fabric FETCH_SIZE + WRITE_SIZE, "
-                                     "copy-calibrated)",
-                     "kernel": f"render_kernel<2ch,u16,{args.precision},{args.layout}"
-                               + (",lit>" if args.lit else ">"),
-                     "kernel_ms": kernel_ms, "bytes_per_launch": alg_bytes,
-                     # effective bytes price every tap as an HBM byte; the measured
-                     # fabric-side rate of the same launches, for comparison:
-                     "traffic_GBps": (traffic / (kernel_ms * 1e-3) / 1e9
-                                      if traffic is not None else None),
-                     # what does limit the kernel (rocprofv3 counters of the same launch)
-                     "valu_busy": counters.get("valu_busy"),
-                     "ta_busy": counters.get("ta_busy")},
+        "roofline": roofline,
     }
     if args.lit:
         result["config"]["light"] = {"direction": list(sc.light.direction),
                                      "ambient": sc.light.ambient, "diffuse": sc.light.diffuse}
-        # effective bytes count the sample's own 8 taps only; the six gradient
-        # samples of each shaded sample are not priced
-        result["roofline"]["bytes_note"] = "8 taps per sample; gradient samples not counted"
+        roofline["bytes_note"] += "; the six gradient samples of a shaded sample not counted"
         result["unlit_kernel_ms"] = unlit_ms
         result["lit_over_unlit"] = kernel_ms / unlit_ms
     vol.destroy()
-    ctx.close()
+    del out, smp
+
+    if not args.no_counters:
+        import tempfile
+        workdir = tempfile.mkdtemp(prefix="vr_bench_", dir="/tmp")
+        scene_npy = os.path.join(workdir, "scene.npy")
+        np.save(scene_npy, sc.volume)
+        try:
+            extra = ["--layout", args.layout, "--precision", args.precision,
+                     "--brick", args.brick] + (["--lit"] if args.lit else [])
+            cnt = live_counters(scene_npy, extra, workdir)
+            roofline["traffic"] = cnt["traffic"]
+            roofline["traffic_GBps"] = cnt["traffic"] / (kernel_ms * 1e-3) / 1e9
+            roofline["valu_busy"] = cnt["valu_busy"]
+            roofline["valu_insts_per_sample"] = cnt["valu_insts"] * 64 / samples_per_step
+            roofline["vmem_rd_insts"] = cnt["vmem_rd_insts"]
+            roofline["counters_source"] = (
+                "measured by this run: rocprofv3 --pmc FETCH_SIZE | WRITE_SIZE | VALUBusy | "
+                "SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_WAVES over the headline launch (bench.py "
+                "--mode counters, child processes), FETCH_SIZE and WRITE_SIZE scaled by a "
+                f"1 GiB copy ({cnt['fetch_scale']:.3f}, {cnt['write_scale']:.3f})")
+        except Exception as e:  # counters are reported, never required
+            roofline["counters_source"] = f"not measured: {e}"
+        finally:
+            import shutil
+            shutil.rmtree(workdir, ignore_errors=True)
+
     if not args.no_cpu:
         log("cpu baseline")
         result["cpu_baseline"] = cpu_baseline(sc)
+
+    from paper_1407_2089_amd import workloads
+    if args.batch:
+        log("batching: 64 mixed requests, batched vs plain launches")
+        b = workloads.batching(ctx)
+        result["batching"] = {k: b[k] for k in (
+            "requests", "plain_stereo_fps", "batch_stereo_fps", "speedup", "bitwise_equal",
+            "plain_samples_per_s", "batch_samples_per_s", "tuned_tile", "total_samples")}
+        result["batching"]["workload"] = b["workload"]
+    if args.serve_gb > 0 and args.serve:
+        log(f"serving: {args.serve_gb} GB resident, rates {args.serve_rates_short}")
+        rates = tuple(int(r) for r in args.serve_rates_short.split(","))
+        sv = workloads.serving(ctx, total_gb=args.serve_gb, seconds=args.serve_short_seconds,
+                               rates=rates)
+        result["serving"] = sv
+    ctx.close()
     print(json.dumps(result), flush=True)
+
+
+def counters_child(args, sc):
+    """Child of a counter pass: the headline launch (skips on) three times
+    after one warm-up, nothing else on the GPU but the upload."""
+    import numpy as np
+    import torch
+
+    import paper_1407_2089_amd as vr
+    vol_np = np.load(args.scene_npy) if args.scene_npy else sc.volume
+    ctx = vr.Context(0)
+    c, nz, ny, nx = vol_np.shape
+    brick = tuple(int(b) for b in args.brick.split(","))
+    vol = vr.Volume(ctx, (nx, ny, nz), c, 1, vr.VR_U16, sc.bits, brick=brick,
+                    row_pairs=args.layout == "pairs")
+    vol.upload(0, torch.from_numpy(vol_np.view(np.int16)).cuda())
+    for ch, tf in enumerate(sc.tfs):
+        vol.set_transfer(ch, tf)
+    out = torch.empty((2, sc.height, sc.width, 4), dtype=torch.float32, device="cuda")
+    prec = vr.VR_FP16 if args.precision == "fp16" else vr.VR_FP32
+    req = vr.make_request(vol.ptr, 0, sc.cam, sc.width, sc.height, True, sc.step,
+                          sc.term_alpha, out, precision=prec, light=sc.light)
+    for _ in range(4):
+        vr.vr_render(ctx.ptr, req)
+    torch.cuda.synchronize()
+    vol.destroy()
+    ctx.close()
 
 
 if __name__ == "__main__":
