@@ -92,6 +92,9 @@ def test_every_lit_variant_matches_the_oracle(ctx, ch, dtype, bits, pairs, preci
     ref = orc.render_all(sc, band_eps=tol)
     st = gpu.compare(rgba, smp, ref, tol)
     log(f"  {st}, lit margin max {ref['lit_margin'].max():.2e}")
+    # The allowance for FP32 gradient rounding stays below the tolerance
+    # itself, so the widened bound stays meaningful.
+    assert ref["lit_margin"].max() < tol
     assert rgba[..., :3].max() > 0.05  # something was lit
 
 
@@ -117,6 +120,7 @@ def test_lighting_changes_colour_only(ctx):
     ref = orc.render_all(sc)
     st = gpu.compare(lit[0], lit[1], ref, TOL32)
     log(f"lit realistic 480x270 {st}, lit margin max {ref['lit_margin'].max():.2e}")
+    assert ref["lit_margin"].max() < TOL32
 
 
 def test_lit_random_configurations(ctx):
@@ -140,7 +144,9 @@ def test_lit_random_configurations(ctx):
             vr.vr_test_clear_skip(ctx.ptr, True)
             v.destroy()
         assert np.array_equal(full[1], smp) and same_bits(full[0], rgba)
-        gpu.compare(rgba, smp, orc.render_all(sc, band_eps=tol), tol)
+        ref = orc.render_all(sc, band_eps=tol)
+        assert ref["lit_margin"].max() < tol
+        gpu.compare(rgba, smp, ref, tol)
 
 
 def lit_and_unlit_requests(ctx, n, seed):
