@@ -213,6 +213,24 @@ def montage_cpu_baseline(src, cam, tfs, W, H, target_s=10.0):
                       f"ray's crop, FP64, one thread, {spent:.1f} s"}
 
 
+def choose_layout(args, ctx, dims, channels, dtype, bits, src, tfs, views, stream):
+    """(brick, row_pairs, how) for a frame: --layout auto asks vr_tune_layout
+    (timed on the given views, before any timed region); bricks / pairs take
+    --brick as given."""
+    import paper_1407_2089_amd as vr
+    if args.layout != "auto":
+        brick = tuple(int(b) for b in args.brick.split(","))
+        return brick, args.layout == "pairs", "given on the command line"
+    C = vr.C
+    desc = vr.vr_volume_desc(*dims, channels, 1, dtype, bits, (C.c_float * 3)(1, 1, 1),
+                             (C.c_float * 3)(0, 0, 0), (C.c_int32 * 3)(0, 0, 0), 0)
+    t0 = time.time()
+    ms = vr.vr_tune_layout(ctx.ptr, desc, tfs, src, views, reps=10, stream=stream)
+    return (tuple(desc.brick), bool(desc.row_pairs),
+            f"vr_tune_layout: fastest of its candidates on this view ({ms:.4f} ms median "
+            f"per launch, {time.time() - t0:.1f} s of tuning)")
+
+
 def tiny(args):
     """Launch-bound small case: 1-channel u8 64x64x32, ortho mono 256x256."""
     import numpy as np
@@ -222,11 +240,15 @@ def tiny(args):
     from paper_1407_2089_amd import synth
     sc = synth.tiny_scene()
     ctx = vr.Context(0)
-    vol = vr.Volume(ctx, (64, 64, 32), 1, 1, vr.VR_U8, 8, row_pairs=args.layout == "pairs")
-    vol.upload(0, torch.from_numpy(sc.volume).cuda())
-    vol.set_transfer(0, sc.tfs[0])
+    src = torch.from_numpy(sc.volume).cuda()
     out = torch.empty((1, 256, 256, 4), dtype=torch.float32, device="cuda")
     smp = torch.empty((1, 256, 256), dtype=torch.int32, device="cuda")
+    view = vr.make_request(None, 0, sc.cam, 256, 256, False, 0.5, 1.0, out)
+    brick, pairs, tune = choose_layout(args, ctx, (64, 64, 32), 1, vr.VR_U8, 8, src, sc.tfs,
+                                       [view], torch.cuda.current_stream())
+    vol = vr.Volume(ctx, (64, 64, 32), 1, 1, vr.VR_U8, 8, brick=brick, row_pairs=pairs)
+    vol.upload(0, src)
+    vol.set_transfer(0, sc.tfs[0])
     req = vr.make_request(vol.ptr, 0, sc.cam, 256, 256, False, 0.5, 1.0, out, out_samples=smp)
     vr.vr_render(ctx.ptr, req)
     torch.cuda.synchronize()
@@ -243,7 +265,7 @@ def tiny(args):
     vol.destroy()
     ctx.close()
     return {"workload": "tiny: 1ch u8 64x64x32 blobs, ortho mono 256x256, step 0.5",
-            "layout": args.layout,
+            "layout": "pairs" if pairs else "bricks", "brick": list(brick), "layout_choice": tune,
             "samples": samples, "median_ms": med, "samples_per_s": samples / (med * 1e-3),
             "eff_GBps": samples * 8 / (med * 1e-3) / 1e9}
 
@@ -268,11 +290,11 @@ def main():
                          "playback of the 48-frame series from pinned host memory")
     ap.add_argument("--brick", default="0,0,0", help="brick edge per axis (0,0,0 = default)")
     ap.add_argument("--tile", default="", help="wave_w,wave_h (pixels per wave) of vr_render")
-    ap.add_argument("--layout", choices=["bricks", "pairs"], default="pairs",
-                    help="voxel layout of the realistic and tiny frames: bricks with row "
-                         "pairs (default; two 16-byte loads per sample for the realistic "
-                         "frame, 2.2x the storage) or plain bricks (the library's default "
-                         "layout)")
+    ap.add_argument("--layout", choices=["auto", "bricks", "pairs"], default="auto",
+                    help="voxel layout of the realistic and tiny frames: auto (default: "
+                         "vr_tune_layout times its candidate layouts on the bench's own view "
+                         "before the timed region), bricks with row pairs (--brick applies), "
+                         "or plain bricks")
     ap.add_argument("--lit", action="store_true",
                     help="light the realistic frame (one directional light, gradients from "
                          "central differences); also times the unlit kernel for the ratio")
@@ -356,18 +378,21 @@ def main():
         sc.light = _light()
     ctx = vr.Context(0)
     c, nz, ny, nx = sc.volume.shape
-    brick = tuple(int(b) for b in args.brick.split(","))
-    pairs = args.layout == "pairs"
-    vol = vr.Volume(ctx, (nx, ny, nz), c, 1, vr.VR_U16, sc.bits, brick=brick, row_pairs=pairs)
-    if args.tile:
-        vr.vr_test_plain_tile(ctx.ptr, *[int(t) for t in args.tile.split(",")])
     stream = torch.cuda.current_stream()
-    vol.upload(0, torch.from_numpy(sc.volume.view(np.int16)).cuda(), stream)
-    for ch, tf in enumerate(sc.tfs):
-        vol.set_transfer(ch, tf)
+    src = torch.from_numpy(sc.volume.view(np.int16)).cuda()
     prec = vr.VR_FP16 if args.precision == "fp16" else vr.VR_FP32
     out = torch.empty((2, sc.height, sc.width, 4), dtype=torch.float32, device="cuda")
     smp = torch.empty((2, sc.height, sc.width), dtype=torch.int32, device="cuda")
+    view = vr.make_request(None, 0, sc.cam, sc.width, sc.height, True, sc.step, sc.term_alpha,
+                           out, precision=prec, light=sc.light)
+    brick, pairs, tune = choose_layout(args, ctx, (nx, ny, nz), c, vr.VR_U16, sc.bits, src,
+                                       sc.tfs, [view], stream)
+    vol = vr.Volume(ctx, (nx, ny, nz), c, 1, vr.VR_U16, sc.bits, brick=brick, row_pairs=pairs)
+    if args.tile:
+        vr.vr_test_plain_tile(ctx.ptr, *[int(t) for t in args.tile.split(",")])
+    vol.upload(0, src, stream)
+    for ch, tf in enumerate(sc.tfs):
+        vol.set_transfer(ch, tf)
 
     # Count the composited samples of one step (the frame is the same every step).
     req_count = vr.make_request(vol.ptr, 0, sc.cam, sc.width, sc.height, True, sc.step,
@@ -430,7 +455,8 @@ def main():
     compulsory = nx * ny * nz * c * 2 + out.numel() * 4
     achieved = alg_bytes / (kernel_ms * 1e-3) / 1e9
     noskip_achieved = alg_bytes / (noskip_ms * 1e-3) / 1e9
-    kernel_name = (f"render_kernel<2ch,u16,{args.precision},{args.layout}"
+    layout_name = "pairs" if pairs else "bricks"
+    kernel_name = (f"render_kernel<2ch,u16,{args.precision},{layout_name}"
                    + (",lit>" if args.lit else ">"))
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": None,
@@ -461,7 +487,7 @@ def main():
                                "perspective stereo 1920x1080 per eye, step 1, alpha 0.99"
                                + (", lit (one directional light)" if args.lit else ""),
                    "eyes": 2, "width": sc.width, "height": sc.height, "brick": list(brick),
-                   "layout": args.layout, "storage_bytes": vol.bytes,
+                   "layout": layout_name, "layout_choice": tune, "storage_bytes": vol.bytes,
                    "tile": args.tile or "8,8",
                    "samples_per_step": samples_per_step},
         "stereo_fps": args.steps / wall,
@@ -482,8 +508,8 @@ def main():
         scene_npy = os.path.join(workdir, "scene.npy")
         np.save(scene_npy, sc.volume)
         try:
-            extra = ["--layout", args.layout, "--precision", args.precision,
-                     "--brick", args.brick] + (["--lit"] if args.lit else [])
+            extra = ["--layout", layout_name, "--precision", args.precision,
+                     "--brick", ",".join(str(b) for b in brick)] + (["--lit"] if args.lit else [])
             cnt = live_counters(scene_npy, extra, workdir)
             roofline["traffic"] = cnt["traffic"]
             roofline["traffic_GBps"] = cnt["traffic"] / (kernel_ms * 1e-3) / 1e9

@@ -228,6 +228,27 @@ vr_status vr_volume_storage_bytes(const vr_volume_desc* desc, uint64_t* bytes);
 vr_status vr_create_volume(vr_ctx* ctx, const vr_volume_desc* desc, void* dev_storage,
                            uint64_t storage_bytes, vr_volume** out);
 
+/* Choose the voxel layout of a dataset by measurement (a project addition:
+ * the brick layout is this library's; the paper keeps each time point as one
+ * 3-D texture, User Interface section).  Every candidate layout (brick edges
+ * and row pairs; all store the same voxels and give the same image bits)
+ * whose storage for desc->frames frames stays within max_bytes (0: no limit)
+ * is built from one frame, dev_frame [channels][nz][ny][nx] on the device
+ * (as vr_upload_frame takes it), in scratch storage that this call allocates
+ * and frees; the n_views requests are rendered from it, `reps` timed renders
+ * each after two untimed ones, with the transfer functions tfs[0 ..
+ * channels - 1] (the requests' vol and frame members are ignored; their
+ * outputs receive the renders).  The layout with the least sum of per-view
+ * median times is written into desc->brick and desc->row_pairs (the library
+ * default layouts are tried first and kept on ties), that sum into *best_ms
+ * when best_ms is not NULL.  Synchronous on hip_stream: blocks for about
+ * 14 x n_views x (reps + 2) renders; call it at load time, before creating
+ * the volume.  Counts each scratch volume against the context's budget while
+ * it exists.  VR_ERR_OUT_OF_MEMORY when no candidate fits. */
+vr_status vr_tune_layout(vr_ctx* ctx, vr_volume_desc* desc, const vr_transfer* tfs,
+                         const void* dev_frame, const vr_render_req* views, int32_t n_views,
+                         int32_t reps, uint64_t max_bytes, void* hip_stream, float* best_ms);
+
 /* Copy one time point into the volume's storage on `hip_stream` (the
  * sequence is downloaded to video memory frame by frame: Methods,
  * acquisition paragraph; User Interface, work-flow paragraph): brick

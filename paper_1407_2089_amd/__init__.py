@@ -22,7 +22,7 @@ __all__ = [
     "VR_FP32", "VR_FP16", "VR_ORTHO", "VR_PERSPECTIVE", "vr_denoise_workspace_bytes",
     "vr_remove_background", "vr_mrf_denoise", "gaussian_weights", "remove_background",
     "mrf_denoise", "vr_stream_frame", "vr_stream_ready", "vr_gaussian_weights",
-    "vr_tune_batch", "vr_render_batch_noalloc",
+    "vr_tune_batch", "vr_render_batch_noalloc", "vr_tune_layout",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvr.so")
@@ -128,6 +128,9 @@ def lib():
             "vr_render_batch_noalloc": [P, C.POINTER(vr_render_req), C.c_int32, P],
             "vr_tune_batch": [P, C.POINTER(vr_render_req), C.c_int32, P,
                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)],
+            "vr_tune_layout": [P, C.POINTER(vr_volume_desc), C.POINTER(vr_transfer), P,
+                               C.POINTER(vr_render_req), C.c_int32, C.c_int32, C.c_uint64, P,
+                               C.POINTER(C.c_float)],
             "vr_submit": [P, C.POINTER(vr_render_req), C.POINTER(C.c_uint64)],
             "vr_poll": [P, C.c_uint64, C.POINTER(vr_ticket_info)],
             "vr_release": [P, C.c_uint64],
@@ -249,6 +252,21 @@ def vr_tune_batch(ctx, reqs, stream=None):
     w, h = C.c_int32(), C.c_int32()
     _check(lib().vr_tune_batch(ctx, arr, n, _stream(stream), C.byref(w), C.byref(h)))
     return w.value, h.value
+
+
+def vr_tune_layout(ctx, desc: vr_volume_desc, tfs, dev_frame, views, reps=10, max_bytes=0,
+                   stream=None):
+    """Choose the layout of `desc` by timing `views` on each candidate built
+    from dev_frame; updates desc.brick and desc.row_pairs in place and
+    returns the winner's summed median time in ms."""
+    tf_arr = (vr_transfer * len(tfs))(*[t if isinstance(t, vr_transfer) else
+                                        make_transfer(t.lo, t.hi, t.curve, t.alpha_mul, t.rgb,
+                                                      t.visible) for t in tfs])
+    arr = (vr_render_req * max(len(views), 1))(*views)
+    ms = C.c_float()
+    _check(lib().vr_tune_layout(ctx, C.byref(desc), tf_arr, _ptr(dev_frame), arr, len(views),
+                                reps, max_bytes, _stream(stream), C.byref(ms)))
+    return ms.value
 
 
 def vr_submit(ctx, req: vr_render_req) -> int:

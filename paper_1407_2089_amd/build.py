@@ -15,7 +15,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels.hip", "denoise.hip", "api.cpp", "batch.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "denoise.hip", "api.cpp", "batch.cpp", "server.cpp", "tune.cpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

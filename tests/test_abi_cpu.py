@@ -25,7 +25,7 @@ def declared_symbols(header="vr.h"):
 def test_library_exports_every_declared_symbol():
     L = vr.lib()
     names = declared_symbols()
-    assert "vr_render" in names and "vr_submit" in names and len(names) == 18
+    assert "vr_render" in names and "vr_submit" in names and len(names) == 19
     assert "vr_tune_batch" in names
     assert "vr_stream_frame" in names and "vr_stream_ready" in names
     dn = declared_symbols("vr_denoise.h")
@@ -358,6 +358,30 @@ def test_transfer_validation(vvol):
     expect(vr.VR_ERR_INVALID_ARG, vr.vr_set_transfer, v, 2, vr.make_transfer())
     expect(vr.VR_ERR_INVALID_ARG, vr.vr_upload_frame, v, 5, FAKE)
     expect(vr.VR_ERR_UNSUPPORTED, vr.vr_upload_frame, v, 1, FAKE)
+
+
+def test_tune_layout_validation(vctx):
+    L = vr.lib()
+    d = desc(frames=1)
+    tfs = (vr.vr_transfer * 1)(vr.make_transfer())
+    reqs = (vr.vr_render_req * 1)()
+    ms = C.c_float()
+    args = lambda **k: dict(dict(ctx=vctx, desc=C.byref(d), tfs=tfs, frame=FAKE, views=reqs,
+                                 n=1, reps=5, max_bytes=0, stream=None, ms=C.byref(ms)), **k)
+    def call(**k):
+        a = args(**k)
+        return L.vr_tune_layout(a["ctx"], a["desc"], a["tfs"], a["frame"], a["views"], a["n"],
+                                a["reps"], a["max_bytes"], a["stream"], a["ms"])
+    assert call(ctx=None) == vr.VR_ERR_INVALID_ARG
+    assert call(desc=None) == vr.VR_ERR_INVALID_ARG
+    assert call(tfs=None) == vr.VR_ERR_INVALID_ARG
+    assert call(frame=None) == vr.VR_ERR_INVALID_ARG
+    assert call(n=0) == vr.VR_ERR_INVALID_ARG
+    assert call(views=None) == vr.VR_ERR_INVALID_ARG
+    assert call(reps=0) == vr.VR_ERR_INVALID_ARG
+    assert call(reps=1001) == vr.VR_ERR_INVALID_ARG
+    assert call() == vr.VR_ERR_UNSUPPORTED  # validation-only context
+    assert list(d.brick) == [0, 0, 0] and d.row_pairs == 0  # untouched on failure
 
 
 def test_null_arguments_do_not_crash():
