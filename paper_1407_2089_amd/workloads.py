@@ -12,10 +12,10 @@ import time
 import numpy as np
 
 from . import synth
-from . import (VR_FP16, VR_FP32, VR_U8, VR_U16, Volume, gaussian_weights, make_grid,
+from . import (VR_FP16, VR_FP32, VR_U8, VR_U16, C, Volume, gaussian_weights, make_grid,
                make_lowpass, make_request, vr_denoise_workspace_bytes, vr_mrf_denoise, vr_poll,
                vr_release, vr_remove_background, vr_render, vr_render_batch, vr_stream_frame,
-               vr_stream_ready, vr_submit, vr_tune_batch)
+               vr_stream_ready, vr_submit, vr_tune_batch, vr_tune_layout, vr_volume_desc)
 
 SIZES_BATCH = [(960, 540), (1280, 720), (1600, 900), (1920, 1080)]
 SIZES_SERVE = [(960, 540), (1920, 1080), (2560, 1440), (3840, 2160)]
@@ -39,13 +39,29 @@ def pairs_allowed(channels, bits):
     return channels <= 2 or (channels <= 4 and bits <= 8)
 
 
-def load_series(ctx, series, frames, tfs, stream=None, row_pairs=False):
+def tune_layout(ctx, series, tfs, reps=3):
+    """(brick, row_pairs) that vr_tune_layout picks for frame 0 of a
+    DeviceSeries, timed on a 1920x1080 stereo overview."""
+    import torch
+    nx, ny, nz = series.dims
+    dtype = VR_U8 if series.bits <= 8 else VR_U16
+    desc = vr_volume_desc(nx, ny, nz, series.channels, 1, dtype, series.bits,
+                          (C.c_float * 3)(1, 1, 1), (C.c_float * 3)(0, 0, 0),
+                          (C.c_int32 * 3)(0, 0, 0), 0)
+    out = torch.empty((2, 1080, 1920, 4), dtype=torch.float32, device="cuda")
+    cam = synth.orbit_camera(series.dims, 30.0, 40.0, 40.0)
+    view = make_request(None, 0, cam, 1920, 1080, True, 1.0, 0.99, out)
+    vr_tune_layout(ctx.ptr, desc, tfs, series.frame(0), [view], reps=reps)
+    return tuple(desc.brick), bool(desc.row_pairs)
+
+
+def load_series(ctx, series, frames, tfs, stream=None, row_pairs=False, brick=(0, 0, 0)):
     """Create a resident volume and upload every frame of a DeviceSeries."""
     import torch
     nx, ny, nz = series.dims
     dtype = VR_U8 if series.bits <= 8 else VR_U16
     vol = Volume(ctx, (nx, ny, nz), series.channels, frames, dtype, series.bits,
-                 row_pairs=row_pairs)
+                 brick=brick, row_pairs=row_pairs)
     for t in range(frames):
         f = series.frame(t)
         vol.upload(t, f, stream or torch.cuda.current_stream())
@@ -76,7 +92,7 @@ def count_samples(ctx, reqs):
 def batching_setup(ctx, n_req=64, n_vol=16, seed=4):
     """The batching workload's volumes and requests: 64 stereo requests over
     16 volumes of uneven size (2^21..2^26 voxels, 1-4 channels, u8 / u16-12 /
-    u16-16; row pairs where the voxel word allows), 960x540..1920x1080 per
+    u16-16; each layout chosen by vr_tune_layout), 960x540..1920x1080 per
     eye, random view directions.  Returns (volumes, their DeviceSeries,
     meta [(dims, channels, bits)], requests, outputs, request -> volume
     index, cameras)."""
@@ -93,8 +109,9 @@ def batching_setup(ctx, n_req=64, n_vol=16, seed=4):
         bits = (8, 12, 16)[kind]
         ser = synth.DeviceSeries((nxy, nxy, nz), ch, bits, 4000 + q)
         tfs = default_tfs(ch)
-        # the faster layout wherever it exists (single frames: storage is cheap)
-        vols.append(load_series(ctx, ser, 1, tfs, row_pairs=pairs_allowed(ch, bits)))
+        # each dataset's layout chosen by vr_tune_layout on one overview
+        brick, pairs = tune_layout(ctx, ser, tfs)
+        vols.append(load_series(ctx, ser, 1, tfs, row_pairs=pairs, brick=brick))
         sers.append(ser)
         meta.append(((nxy, nxy, nz), ch, bits))
     reqs, outs, which, cams = [], [], [], []
@@ -160,7 +177,7 @@ def batching(ctx, n_req=64, n_vol=16, seed=4, reps=5):
         v.destroy()
     return {
         "workload": "batching: 64 stereo requests over 16 volumes (2^21..2^26 voxels, 1-4 "
-                    "channels, u8/u16-12/u16-16, row pairs where the word allows), "
+                    "channels, u8/u16-12/u16-16, each layout chosen by vr_tune_layout), "
                     "960x540..1920x1080 per eye, step 1, alpha 0.99",
         "requests": n_req, "total_samples": total_samples, "bitwise_equal": equal,
         "plain_s": t_plain, "batch_s": t_batch,
