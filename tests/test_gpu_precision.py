@@ -22,6 +22,7 @@ def test_precision_workload_errors_against_oracle():
     W, H = 1920, 1080
     rng = np.random.default_rng(33)
     worst = {vr.VR_FP32: 0.0, vr.VR_FP16: 0.0}
+    every = {vr.VR_FP32: 0.0, vr.VR_FP16: 0.0}
     for t in frames:
         f = ser.frame(t)
         host = f.cpu().numpy()
@@ -41,8 +42,11 @@ def test_precision_workload_errors_against_oracle():
             ref = orc.render_all(sc, band_eps=tol, pixels=pix)
             st = gpu.compare(img, ss, ref, tol)
             worst[prec] = max(worst[prec], st["max_err_outside_band"])
+            every[prec] = max(every[prec], st["max_err"])
             print(f"frame {t} {'fp16' if prec else 'fp32'}: {st}", flush=True)
         vol.destroy()
-    print(f"precision workload max-abs RGBA error: fp32 {worst[vr.VR_FP32]:.3e} "
-          f"fp16 {worst[vr.VR_FP16]:.3e}", flush=True)
+    print(f"precision workload max-abs RGBA error outside the termination band: "
+          f"fp32 {worst[vr.VR_FP32]:.3e} fp16 {worst[vr.VR_FP16]:.3e}; over every checked "
+          f"pixel against the oracle's own stop: fp32 {every[vr.VR_FP32]:.3e} "
+          f"fp16 {every[vr.VR_FP16]:.3e}", flush=True)
     ctx.close()
