@@ -1083,6 +1083,26 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
                 if (A >= tau) count = k;
                 live = k < n && A < tau;
             } while (live);
+        } else if (!cells_on) {
+            // Without macro cells (a frame with nothing to skip, or the test
+            // switched off): the same software pipeline over pairs of
+            // samples, with no segment bookkeeping in the dependent chain of
+            // a latency-bound launch (measured on the 256 x 256 mono frame:
+            // 0.0255 ms through the segment loop below).  The pair's second
+            // sample is left out on lanes that finished on its first.
+            Taps<Word> a = fetch_at(k);
+            bool live;
+            do {
+                const Taps<Word> b = fetch_at(k + 1);
+                composite(a, true, k);
+                ++k;
+                const bool on = k < n && A < tau;
+                a = fetch_at(k + 1);
+                composite(b, on, k);
+                k += on ? 1 : 0;
+                live = on && k < n && A < tau;
+            } while (live);
+            count = k;
         } else {
             // Software pipeline over pairs of samples: the taps of the next
             // sample are in flight while the current one is interpolated and
