@@ -312,14 +312,20 @@ __device__ __forceinline__ uint32_t corner(const SamplerL& S, double q, int a) {
     return (uint32_t)__builtin_floor(__builtin_fmin(__builtin_fmax(q, 0.0), S.hi[a]));
 }
 
-// Word `idx` of the frame's macro-cell table.
+// The word of macro cell c (cell coordinates) in the frame's cell table.  A
+// 32-bit-addressed frame, table included, stays below 4 GiB, so its cell
+// index and byte offset fit 32 bits; a large frame's index is formed in 64.
 template <typename T>
-__device__ __forceinline__ T load_cell(const BrickGeom& g, const Sampler& S, uint32_t idx) {
+__device__ __forceinline__ T load_cell(const BrickGeom& g, const Sampler& S,
+                                       const uint32_t (&c)[3]) {
+    const uint32_t idx = (c[2] * (uint32_t)g.nc[1] + c[1]) * (uint32_t)g.nc[0] + c[0];
     return load_word<T>(S.rsrc, idx * (uint32_t)sizeof(T), S.cell_b);
 }
 template <typename T>
-__device__ __forceinline__ T load_cell(const BrickGeom& g, const SamplerL& S, uint32_t idx) {
-    return load_global<T>(S.vox + g.cell_off + (uint64_t)idx * sizeof(T));
+__device__ __forceinline__ T load_cell(const BrickGeom& g, const SamplerL& S,
+                                       const uint32_t (&c)[3]) {
+    const uint64_t idx = ((uint64_t)c[2] * (uint32_t)g.nc[1] + c[1]) * (uint32_t)g.nc[0] + c[0];
+    return load_global<T>(S.vox + g.cell_off + idx * sizeof(T));
 }
 
 // The 2x2x2 taps around one sample point, in flight or landed.
@@ -1121,9 +1127,7 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
                 if (k >= kend) {
                     uint32_t c[3];
                     cell_of(k, c);
-                    const uint32_t idx =
-                        (c[2] * (uint32_t)P.g.nc[1] + c[1]) * (uint32_t)P.g.nc[0] + c[0];
-                    const Word w = load_cell<Word>(P.g, S, idx);
+                    const Word w = load_cell<Word>(P.g, S, c);
                     R jx = (R)n;
 #pragma unroll
                     for (int ax = 0; ax < 3; ++ax) {
