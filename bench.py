@@ -32,6 +32,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz lane-
+# instructions per second (one non-packed FP32 FMA per lane and clock:
+# 78.6 TFLOP/s, half the packed figure)
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 
 def _light():
@@ -517,6 +521,8 @@ def main():
             roofline["traffic_GBps"] = cnt["traffic"] / (kernel_mean_ms * 1e-3) / 1e9
             roofline["valu_busy"] = cnt["valu_busy"]
             roofline["valu_insts_per_sample"] = cnt["valu_insts"] * 64 / samples_per_step
+            roofline["valu_issue_frac"] = (cnt["valu_insts"] * 64 / (kernel_mean_ms * 1e-3)
+                                           / PEAK_VALU_LANE_OPS)
             roofline["vmem_rd_insts"] = cnt["vmem_rd_insts"]
             roofline["counters_source"] = (
                 "measured by this run: rocprofv3 --pmc FETCH_SIZE | WRITE_SIZE | VALUBusy | "
