@@ -355,7 +355,10 @@ def main():
         elif args.workload == "stream":
             res = workloads.streaming(ctx)
         elif args.workload == "montage":
-            res = workloads.montage(ctx, cpu=None if args.no_cpu else montage_cpu_baseline)
+            lay = None if args.layout == "auto" else (
+                tuple(int(b) for b in args.brick.split(",")), args.layout == "pairs")
+            res = workloads.montage(ctx, cpu=None if args.no_cpu else montage_cpu_baseline,
+                                    layout=lay)
         elif args.workload == "denoise":
             res = workloads.denoise(ctx)
             if not args.no_cpu:

@@ -607,16 +607,33 @@ MONTAGE_DIMS = (10173, 3858, 74)   # stitched SVZ montage, 5 channels, 8 bit
 MONTAGE_CHANNELS = 5
 
 
-def montage_setup(ctx, seed=3, brick=(0, 0, 0)):
+def montage_setup(ctx, seed=3, brick=(0, 0, 0), tune=False, row_pairs=False):
     """The five-channel uint8 montage resident in HBM (large-volume
-    addressing: 2.9 G voxels per channel, 23 GB of bricks) with the default
-    transfer functions; returns (volume, source tensor, tfs)."""
+    addressing: 2.9 G voxels per channel, 37.7 GB of default bricks) with the
+    default transfer functions; with tune, its layout is chosen by
+    vr_tune_layout on the overview (vol.layout_choice says which).  Returns
+    (volume, source tensor, tfs)."""
     log("montage: generating 10173x3858x74x5 uint8")
     src = synth.montage(MONTAGE_DIMS, MONTAGE_CHANNELS, seed, log=log)
     tfs = [synth.TF(20.0 / 255.0, 200.0 / 255.0, 0.0, 1.0, PALETTE[c])
            for c in range(MONTAGE_CHANNELS)]
     import torch
-    vol = Volume(ctx, MONTAGE_DIMS, MONTAGE_CHANNELS, 1, VR_U8, 8, brick=brick)
+    pairs, choice = row_pairs, f"given: brick {list(brick)}, row pairs {row_pairs}"
+    if tune:
+        desc = vr_volume_desc(*MONTAGE_DIMS, MONTAGE_CHANNELS, 1, VR_U8, 8,
+                              (C.c_float * 3)(1, 1, 1), (C.c_float * 3)(0, 0, 0),
+                              (C.c_int32 * 3)(0, 0, 0), 0)
+        out = torch.empty((2, 1080, 1920, 4), dtype=torch.float32, device="cuda")
+        view = make_request(None, 0, montage_camera(), 1920, 1080, True, 1.0, 0.99, out)
+        t0 = time.time()
+        ms = vr_tune_layout(ctx.ptr, desc, tfs, src, [view], reps=5)
+        del out
+        brick, pairs = tuple(desc.brick), bool(desc.row_pairs)
+        choice = (f"vr_tune_layout: brick {list(brick)}, row pairs {pairs} ({ms:.3f} ms on "
+                  f"the overview, {time.time() - t0:.1f} s of tuning)")
+        log(choice)
+    vol = Volume(ctx, MONTAGE_DIMS, MONTAGE_CHANNELS, 1, VR_U8, 8, brick=brick, row_pairs=pairs)
+    vol.layout_choice = choice
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     stream = torch.cuda.current_stream()
     a.record(stream)
@@ -633,13 +650,17 @@ def montage_camera():
     return synth.orbit_camera(MONTAGE_DIMS, 30.0, 55.0, 40.0, 0.6)
 
 
-def montage(ctx, reps=10, W=1920, H=1080, cpu=None):
+def montage(ctx, reps=10, W=1920, H=1080, cpu=None, layout=None):
     """Stereo 1920x1080 views of the montage (perspective, elevation 55
     degrees, the montage's long side filling the view).  `cpu`, if given, is
     called as cpu(src, cam, tfs, W, H) while the source is still on the GPU
-    and its result is returned as cpu_baseline."""
+    and its result is returned as cpu_baseline.  layout: None to let
+    vr_tune_layout choose, else (brick, row_pairs)."""
     import torch
-    vol, src, tfs = montage_setup(ctx)
+    if layout is None:
+        vol, src, tfs = montage_setup(ctx, tune=True)
+    else:
+        vol, src, tfs = montage_setup(ctx, brick=tuple(layout[0]), row_pairs=bool(layout[1]))
     cam = montage_camera()
     base = cpu(src, cam, tfs, W, H) if cpu is not None else None
     del src
@@ -666,11 +687,13 @@ def montage(ctx, reps=10, W=1920, H=1080, cpu=None):
     eff = samples * 8 * word / (ms * 1e-3) / 1e9
     frame_bytes = vol.bytes
     relayout_ms = vol.relayout_ms
+    choice = vol.layout_choice
     vol.destroy()
     return {"workload": "montage: 5ch u8 10173x3858x74 (one frame, 14.5 GB of voxels, "
                         f"{frame_bytes / 1e9:.1f} GB of bricks), stereo {W}x{H}, step 1.0, "
                         "tau 0.99, perspective elevation 55 deg",
-            "frame_bytes": frame_bytes, "samples": samples, "ms_per_step": ms,
+            "frame_bytes": frame_bytes, "layout_choice": choice, "samples": samples,
+            "ms_per_step": ms,
             # upload: read 5 B per voxel, write the bricks
             "relayout_ms": relayout_ms,
             "relayout_GBps": (5 * 10173 * 3858 * 74 + frame_bytes) / (relayout_ms * 1e-3) / 1e9,
