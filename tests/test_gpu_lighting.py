@@ -226,3 +226,35 @@ def test_lit_flat_plateaus_have_no_gradient(ctx, ch):
     sc.light = Light((0.3, -0.4, 0.9), 0.2, 0.8)
     rgba, smp = gpu.render(ctx, sc)
     gpu.compare(rgba, smp, orc.render_all(sc), TOL32)
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (1, 5, 3), (2, 2, 2), (3, 1, 7), (6, 4, 1)])
+@pytest.mark.parametrize("large", [False, True])
+@pytest.mark.parametrize("pairs", [False, True])
+def test_lit_thin_and_tiny_volumes(ctx, dims, large, pairs):
+    # Volumes one or two voxels thick along some axis: every shaded sample
+    # sits at a face there, and the gradient layers of the other axes are
+    # loaded from clamped corners next to those faces (bricks of 4 and the
+    # default shapes; the large-volume path addresses them with plain loads).
+    log(f"lit tiny dims={dims} large={large} pairs={pairs}")
+    rng = np.random.default_rng(sum(dims) * 7 + large + 2 * pairs)
+    nx, ny, nz = dims
+    vol = rng.integers(0, 4096, size=(2, nz, ny, nx)).astype(np.uint16)
+    tfs = [TF(0.05, 0.8, 0.2, 1.0, (0.9, 0.3, 0.1)), TF(0.1, 0.9, -0.2, 0.8, (0.1, 0.6, 0.9))]
+    cam = synth.orbit_camera(dims, 35.0, 25.0, 40.0, 2.5)
+    sc = Scene("lit-tiny", vol, 12, tfs, cam, 40, 30, True, 0.25, 0.99, (0.1, 0.1, 0.2, 0.3),
+               spacing=(1.0, 1.3, 0.7))
+    sc.light = Light((0.3, -0.6, 0.5), 0.3, 0.7)
+    for brick in ((0, 0, 0), (4, 4, 4)):
+        if large:
+            vr.vr_test_large_addressing(ctx.ptr, True)
+        try:
+            v = gpu.make_volume(ctx, sc, brick, row_pairs=pairs)
+        finally:
+            if large:
+                vr.vr_test_large_addressing(ctx.ptr, False)
+        try:
+            rgba, smp = gpu.render(ctx, sc, vr.VR_FP32, vol=v)
+        finally:
+            v.destroy()
+        gpu.compare(rgba, smp, orc.render_all(sc, band_eps=TOL32), TOL32)
