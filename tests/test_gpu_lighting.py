@@ -258,3 +258,44 @@ def test_lit_thin_and_tiny_volumes(ctx, dims, large, pairs):
         finally:
             v.destroy()
         gpu.compare(rgba, smp, orc.render_all(sc, band_eps=TOL32), TOL32)
+
+
+def word_bytes(ch, dtype):
+    w = 1 if ch == 1 else 2 if ch == 2 else 4 if ch <= 4 else 8
+    return w * (2 if dtype == np.uint16 else 1)
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (1, 4, 2), (3, 1, 5), (2, 3, 1)])
+@pytest.mark.parametrize("ch,dtype,bits", [(1, np.uint8, 8), (5, np.uint8, 8), (6, np.uint16, 12)])
+@pytest.mark.parametrize("large", [False, True])
+@pytest.mark.parametrize("lit", [False, True])
+def test_thin_volumes_every_word_size(ctx, dims, ch, dtype, bits, large, lit):
+    # As above for 1-, 8- and 16-byte words (the wide words take the
+    # one-axis-at-a-time gradient), lit and unlit, FP32 and FP16 sampling.
+    log(f"thin dims={dims} ch={ch} large={large} lit={lit}")
+    rng = np.random.default_rng(sum(dims) * 11 + ch + 2 * large + 4 * lit)
+    nx, ny, nz = dims
+    full = (1 << bits) - 1
+    vol = rng.integers(0, full + 1, size=(ch, nz, ny, nx)).astype(dtype)
+    tfs = [TF(float(rng.uniform(0.02, 0.1)), float(rng.uniform(0.6, 0.9)), 0.0,
+              float(rng.uniform(0.5, 1.0)), tuple(float(x) for x in rng.uniform(0.2, 1, 3)))
+           for _ in range(ch)]
+    cam = synth.orbit_camera(dims, 200.0, -30.0, 40.0, 2.5)
+    sc = Scene("thin", vol, bits, tfs, cam, 36, 28, True, 0.3, 0.98)
+    if lit:
+        sc.light = Light((-0.4, 0.2, 0.7), 0.25, 0.75)
+    pairs = word_bytes(ch, dtype) <= (8 if large else 4)
+    for row_pairs in sorted({False, pairs}):
+        if large:
+            vr.vr_test_large_addressing(ctx.ptr, True)
+        try:
+            v = gpu.make_volume(ctx, sc, row_pairs=row_pairs)
+        finally:
+            if large:
+                vr.vr_test_large_addressing(ctx.ptr, False)
+        try:
+            for prec, tol in ((vr.VR_FP32, TOL32), (vr.VR_FP16, TOL16)):
+                rgba, smp = gpu.render(ctx, sc, prec, vol=v)
+                gpu.compare(rgba, smp, orc.render_all(sc, band_eps=tol), tol)
+        finally:
+            v.destroy()
