@@ -238,10 +238,11 @@ vr_status vr_create_volume(vr_ctx* ctx, const vr_volume_desc* desc, void* dev_st
  * and frees; the n_views requests are rendered from it, `reps` timed renders
  * each after two untimed ones, with the transfer functions tfs[0 ..
  * channels - 1] (the requests' vol and frame members are ignored; their
- * outputs receive the renders).  The layout with the least sum of per-view
- * median times is written into desc->brick and desc->row_pairs (the library
- * default layouts are tried first and kept on ties), that sum into *best_ms
- * when best_ms is not NULL.  Synchronous on hip_stream: blocks for about
+ * outputs receive the renders).  Of the layouts whose sum of per-view
+ * median times is within 2 % of the least, the one with the smallest storage
+ * is written into desc->brick and desc->row_pairs (the library default
+ * layouts are tried first and kept on ties), its sum into *best_ms when
+ * best_ms is not NULL.  Synchronous on hip_stream: blocks for about
  * 14 x n_views x (reps + 2) renders; call it at load time, before creating
  * the volume.  Counts each scratch volume against the context's budget while
  * it exists.  VR_ERR_OUT_OF_MEMORY when no candidate fits. */

@@ -3,7 +3,8 @@
 // same image bits; they differ in how many cache lines a wave's taps touch,
 // which depends on the voxel word, the volume's shape and the views.  Each
 // candidate is built from one frame in scratch storage and timed on the
-// caller's views; the fastest is written back into the description.
+// caller's views; the fastest (or, among those within 2 % of it, the one with
+// the smallest storage) is written back into the description.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -88,9 +89,9 @@ vr_status vr_tune_layout(vr_ctx* ctx, vr_volume_desc* desc, const vr_transfer* t
             return hip_fail(e, "event create");
         }
     }
-    int best = -1;
-    float best_t = 0.0f;
     const std::vector<LayoutCandidate> cands = layout_candidates(*desc);
+    std::vector<float> times(cands.size(), -1.0f);      // -1: not a candidate here
+    std::vector<uint64_t> sizes(cands.size(), 0);
     st = VR_OK;
     for (size_t ci = 0; ci < cands.size() && st == VR_OK; ++ci) {
         vr_volume_desc d = *desc;
@@ -99,6 +100,7 @@ vr_status vr_tune_layout(vr_ctx* ctx, vr_volume_desc* desc, const vr_transfer* t
         uint64_t total = 0, frame_bytes = 0;
         if (check_desc(&d) != VR_OK || vr_volume_storage_bytes(&d, &total) != VR_OK) continue;
         if (max_bytes != 0 && total > max_bytes) continue;
+        sizes[ci] = total;
         d.frames = 1;
         if (vr_volume_storage_bytes(&d, &frame_bytes) != VR_OK) continue;
         void* mem = nullptr;
@@ -126,16 +128,24 @@ vr_status vr_tune_layout(vr_ctx* ctx, vr_volume_desc* desc, const vr_transfer* t
         if (st == VR_OK && e != hipSuccess) st = hip_fail(e, "tuning render");
         (void)vr_destroy_volume(vol);
         (void)hipFree(mem);
-        if (st == VR_OK && (best < 0 || sum < best_t)) {
-            best = (int)ci;
-            best_t = sum;
-        }
+        if (st == VR_OK) times[ci] = sum;
     }
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (st != VR_OK) return st;
-    if (best < 0)
+    // The fastest, unless another candidate within 2 % of it (timing noise
+    // between layouts this close) stores the volume in fewer bytes: then the
+    // smallest of those.  Earlier candidates win ties.
+    int fastest = -1;
+    for (size_t ci = 0; ci < cands.size(); ++ci)
+        if (times[ci] >= 0.0f && (fastest < 0 || times[ci] < times[fastest])) fastest = (int)ci;
+    if (fastest < 0)
         return fail(VR_ERR_OUT_OF_MEMORY, "no candidate layout fits the limits or the device");
+    int best = fastest;
+    for (size_t ci = 0; ci < cands.size(); ++ci)
+        if (times[ci] >= 0.0f && times[ci] <= 1.02f * times[fastest] && sizes[ci] < sizes[best])
+            best = (int)ci;
+    const float best_t = times[best];
     std::memcpy(desc->brick, cands[best].brick, sizeof desc->brick);
     desc->row_pairs = cands[best].pairs;
     if (best_ms) *best_ms = best_t;
