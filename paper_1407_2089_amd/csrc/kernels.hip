@@ -239,8 +239,18 @@ __global__ __launch_bounds__(256) void cellmax_kernel(BrickGeom g, const void* _
 // at the natural 88 VGPRs (5 waves).
 constexpr int lit_min_waves(int v, bool lit, bool clear) {
     if (!lit || !clear) return 1;
+    // variant_index(channels, u16, fp16, row pairs, large)
     switch (v) {
-        case 2: case 7: case 19: case 25: case 26: case 31: case 37: case 43: case 72: case 78:
+        case variant_index(3, false, false, false, false):
+        case variant_index(2, true, false, false, false):
+        case variant_index(2, true, true, false, false):
+        case variant_index(2, false, false, true, false):
+        case variant_index(3, false, false, true, false):
+        case variant_index(2, true, false, true, false):
+        case variant_index(2, false, true, true, false):
+        case variant_index(2, true, true, true, false):
+        case variant_index(1, false, false, true, true):
+        case variant_index(1, true, false, true, true):
             return 6;
         default:
             return 1;
