@@ -241,15 +241,12 @@ constexpr int lit_min_waves(int v, bool lit, bool clear) {
     if (!lit || !clear) return 1;
     // variant_index(channels, u16, fp16, row pairs, large)
     switch (v) {
-        case variant_index(3, false, false, false, false):
         case variant_index(2, true, false, false, false):
         case variant_index(2, true, true, false, false):
         case variant_index(2, false, false, true, false):
-        case variant_index(3, false, false, true, false):
         case variant_index(2, true, false, true, false):
         case variant_index(2, false, true, true, false):
         case variant_index(2, true, true, true, false):
-        case variant_index(1, false, false, true, true):
         case variant_index(1, true, false, true, true):
             return 6;
         default:
