@@ -84,3 +84,22 @@ def test_tuned_layout_respects_the_storage_limit(ctx):
     desc, _ = tuned_desc(ctx, sc, max_bytes=limit)
     assert vr.vr_volume_storage_bytes(desc) <= limit
     assert desc.row_pairs == 0  # row pairs store about twice the words
+
+
+def test_tuning_with_no_admissible_layout_fails_cleanly(ctx):
+    sc = scene_for(2, 12, 9, dims=(40, 36, 20))
+    desc, _ = tuned_desc(ctx, sc)  # a working call first
+    c, nz, ny, nx = sc.volume.shape
+    d = vr.vr_volume_desc(nx, ny, nz, c, 1, vr.VR_U16, 12, (vr.C.c_float * 3)(1, 1, 1),
+                          (vr.C.c_float * 3)(0, 0, 0), (vr.C.c_int32 * 3)(0, 0, 0), 0)
+    out, smp = gpu.alloc_out(sc)
+    view = vr.make_request(None, 0, sc.cam, sc.width, sc.height, True, sc.step, sc.term_alpha,
+                           out, sc.background, vr.VR_FP32, smp)
+    with pytest.raises(vr.VrError) as e:
+        vr.vr_tune_layout(ctx.ptr, d, sc.tfs, gpu.to_device(sc.volume), [view], reps=1,
+                          max_bytes=4096)  # below every candidate's storage
+    assert e.value.status == vr.VR_ERR_OUT_OF_MEMORY
+    assert list(d.brick) == [0, 0, 0] and d.row_pairs == 0
+    # the context still works afterwards
+    tuned = gpu.render(ctx, sc, brick=tuple(desc.brick), row_pairs=bool(desc.row_pairs))
+    assert np.isfinite(tuned[0]).all()
