@@ -192,3 +192,40 @@ def test_precision_series_resident_against_oracle(ctx):
         f"every checked pixel against the oracle's own stop: fp32 {worst[vr.VR_FP32]:.3e} "
         f"fp16 {worst[vr.VR_FP16]:.3e}; against the nearest admissible stop: "
         f"fp32 {accept[vr.VR_FP32]:.3e} fp16 {accept[vr.VR_FP16]:.3e}")
+
+
+@pytest.mark.parametrize("lit,prec", [(True, vr.VR_FP32), (False, vr.VR_FP16), (True, vr.VR_FP16)])
+def test_realistic_frame_bench_configurations_against_oracle(ctx, lit, prec):
+    """The realistic stereo pair at its full 1920x1080 per eye, in the
+    configurations bench.py times beside the headline (lit, FP16 sampling),
+    with the layout vr_tune_layout picks there: 2^14 seeded pixels per eye
+    against the oracle."""
+    import torch
+    sc = synth.realistic_scene()
+    if lit:
+        sc.light = synth.Light((0.4, -0.3, -0.8), 0.3, 0.7)
+    c, nz, ny, nx = sc.volume.shape
+    src = torch.from_numpy(sc.volume.view(np.int16)).cuda()
+    out, smp = gpu.alloc_out(sc)
+    desc = vr.vr_volume_desc(nx, ny, nz, c, 1, vr.VR_U16, sc.bits, (vr.C.c_float * 3)(1, 1, 1),
+                             (vr.C.c_float * 3)(0, 0, 0), (vr.C.c_int32 * 3)(0, 0, 0), 0)
+    view = vr.make_request(None, 0, sc.cam, sc.width, sc.height, True, sc.step, sc.term_alpha,
+                           out, sc.background, prec, smp, sc.light)
+    vr.vr_tune_layout(ctx.ptr, desc, sc.tfs, src, [view], reps=3)
+    v = vr.Volume(ctx, (nx, ny, nz), c, 1, vr.VR_U16, sc.bits, brick=tuple(desc.brick),
+                  row_pairs=bool(desc.row_pairs))
+    try:
+        v.upload(0, src)
+        for ch, tf in enumerate(sc.tfs):
+            v.set_transfer(ch, tf)
+        out, smp = gpu.alloc_out(sc)
+        vr.vr_render(ctx.ptr, gpu.request_for(v, sc, out, smp, prec), torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(71 + 2 * lit + prec)
+        pix = rng.choice(sc.width * sc.height, size=1 << 14, replace=False)
+        tol = 4e-3 if prec == vr.VR_FP16 else 1e-3
+        st = check_pixels(sc, out.cpu().numpy(), smp.cpu().numpy(), pix, tol)
+        log(f"realistic 1920x1080 lit={lit} {'fp16' if prec else 'fp32'} layout "
+            f"{list(desc.brick)} pairs={desc.row_pairs}: {st}")
+    finally:
+        v.destroy()
