@@ -295,10 +295,10 @@ def main():
     ap.add_argument("--brick", default="0,0,0", help="brick edge per axis (0,0,0 = default)")
     ap.add_argument("--tile", default="", help="wave_w,wave_h (pixels per wave) of vr_render")
     ap.add_argument("--layout", choices=["auto", "bricks", "pairs"], default="auto",
-                    help="voxel layout of the realistic and tiny frames: auto (default: "
-                         "vr_tune_layout times its candidate layouts on the bench's own view "
-                         "before the timed region), bricks with row pairs (--brick applies), "
-                         "or plain bricks")
+                    help="voxel layout of the realistic, tiny and montage frames: auto "
+                         "(default; vr_tune_layout times its candidate layouts on the bench's "
+                         "own view before the timed region), pairs (row pairs, brick edges "
+                         "from --brick) or bricks (no row pairs, brick edges from --brick)")
     ap.add_argument("--lit", action="store_true",
                     help="light the realistic frame (one directional light, gradients from "
                          "central differences); also times the unlit kernel for the ratio")
