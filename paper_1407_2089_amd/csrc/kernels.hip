@@ -219,6 +219,90 @@ __global__ __launch_bounds__(256) void cellmax_kernel(BrickGeom g, const void* _
     cells[((size_t)cz * g.nc[1] + cy) * g.nc[0] + cx] = pack_word<C, U16>(ch);
 }
 
+// The same table built strip by strip: a block takes one (y, z) row of cells
+// (cy, cz) and sweeps x in tiles of kCellTile voxels.  Its threads first
+// reduce, per channel, the strip's source rows (up to 9 x 9) into column
+// maxima in LDS, four consecutive columns per thread with one 4- or 8-byte
+// load per row (rows whose length is a multiple of 4 voxels keep such loads
+// aligned); then one thread per cell takes the maximum of its 9 columns (x
+// from 8 cx - 1 to 8 cx + 7; columns outside the grid hold 0, which never
+// raises a maximum).  Column xt - 1 of a tile is the previous tile's last.
+// Same values as cellmax_kernel.
+constexpr int kCellTile = 1024;
+template <int C, bool U16>
+__global__ __launch_bounds__(256) void cellmax_strip_kernel(BrickGeom g,
+                                                            const void* __restrict__ src,
+                                                            uint8_t* __restrict__ frame,
+                                                            uint32_t maxval) {
+    using T = typename WordT<C, U16>::T;
+    using S = typename std::conditional<U16, uint16_t, uint8_t>::type;
+    using S4 = typename std::conditional<U16, uint2, uint32_t>::type;  // four voxels
+    __shared__ uint32_t col[C][kCellTile + 1];  // col[c][1 + i]: column xt + i
+    const S* in = reinterpret_cast<const S*>(src);
+    const int cy = (int)blockIdx.x, cz = (int)blockIdx.y;
+    const int M = 1 << g.cshift;
+    const int y0 = max(cy * M - 1, 0), y1 = min(cy * M + M - 1, g.n[1] - 1);
+    const int z0 = max(cz * M - 1, 0), z1 = min(cz * M + M - 1, g.n[2] - 1);
+    const size_t plane = (size_t)g.n[0] * g.n[1];
+    const size_t vol = plane * g.n[2];
+    T* cells = reinterpret_cast<T*>(frame + g.cell_off) + ((size_t)cz * g.nc[1] + cy) * g.nc[0];
+    const int xend = g.nc[0] * M;  // the last cell starts at 8 (nc0 - 1) <= n
+    const int tid = (int)threadIdx.x;
+    if (tid < C) col[tid][0] = 0;  // column -1
+    for (int xt = 0; xt < xend; xt += kCellTile) {
+        // four columns x = xt + 4 t .. xt + 4 t + 3 per thread (kCellTile = 4 x 256)
+        const int x = xt + 4 * tid;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            uint32_t m[4] = {0, 0, 0, 0};
+            if (x + 3 < g.n[0]) {
+                for (int k = z0; k <= z1; ++k) {
+                    const S* p = in + (size_t)c * vol + (size_t)k * plane + x;
+                    for (int j = y0; j <= y1; ++j) {
+                        const S4 w = *reinterpret_cast<const S4*>(p + (size_t)j * g.n[0]);
+                        if constexpr (U16) {
+                            m[0] = max(m[0], w.x & 0xffffu);
+                            m[1] = max(m[1], w.x >> 16);
+                            m[2] = max(m[2], w.y & 0xffffu);
+                            m[3] = max(m[3], w.y >> 16);
+                        } else {
+                            m[0] = max(m[0], w & 0xffu);
+                            m[1] = max(m[1], (w >> 8) & 0xffu);
+                            m[2] = max(m[2], (w >> 16) & 0xffu);
+                            m[3] = max(m[3], w >> 24);
+                        }
+                    }
+                }
+            } else if (x < g.n[0]) {  // the row's ragged end
+                for (int k = z0; k <= z1; ++k) {
+                    const S* p = in + (size_t)c * vol + (size_t)k * plane;
+                    for (int j = y0; j <= y1; ++j)
+                        for (int u = 0; u < 4 && x + u < g.n[0]; ++u)
+                            m[u] = max(m[u], (uint32_t)p[(size_t)j * g.n[0] + x + u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) col[c][1 + 4 * tid + u] = m[u];
+        }
+        __syncthreads();
+        const int c_lo = xt >> g.cshift, c_hi = min(g.nc[0], (xt + kCellTile) >> g.cshift);
+        for (int cx = c_lo + tid; cx < c_hi; cx += (int)blockDim.x) {
+            uint32_t ch[kMaxChannels] = {};
+            const int i0 = cx * M - xt;  // col index of x = 8 cx - 1
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                uint32_t m = 0;
+                for (int i = i0; i <= i0 + M; ++i) m = max(m, col[c][i]);
+                ch[c] = m > maxval ? maxval : m;
+            }
+            cells[cx] = pack_word<C, U16>(ch);
+        }
+        __syncthreads();
+        if (tid < C) col[tid][0] = col[tid][kCellTile];  // column xt + kCellTile - 1
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------ plain render
 // Grid: one single-wave block per (eye, wave_w x wave_h pixel tile).  Blocks
 // of one wave let the dispatcher refill a SIMD as soon as any wave's rays
@@ -379,6 +463,7 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
     const bool gather = g.shift[0] >= 3;  // bricks at least 8 voxels wide
     if (g.nc[1] > 65535 || g.nc[2] > 65535) return hipErrorInvalidValue;
     const dim3 cgrid(((unsigned)g.nc[0] + 255u) / 256u, (unsigned)g.nc[1], (unsigned)g.nc[2]);
+    const dim3 sgrid((unsigned)g.nc[1], (unsigned)g.nc[2]);
 #define VR_RL(C, U)                                                                       \
     if (channels == C && u16 == U) {                                                      \
         if (gather)                                                                       \
@@ -389,7 +474,11 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
                                src, dst, maxval);                                         \
         hipError_t e = hipGetLastError();                                                 \
         if (e != hipSuccess) return e;                                                    \
-        hipLaunchKernelGGL((cellmax_kernel<C, U>), cgrid, dim3(256), 0, s, g, src, dst, maxval); \
+        if (g.n[0] % 4 == 0 && ((uintptr_t)src & 7u) == 0)                                \
+            hipLaunchKernelGGL((cellmax_strip_kernel<C, U>), sgrid, dim3(256), 0, s, g, src, dst, \
+                               maxval);                                                   \
+        else                                                                              \
+            hipLaunchKernelGGL((cellmax_kernel<C, U>), cgrid, dim3(256), 0, s, g, src, dst, maxval); \
         return hipGetLastError();                                                         \
     }
     VR_RL(1, false) VR_RL(2, false) VR_RL(3, false) VR_RL(4, false) VR_RL(5, false)

@@ -216,3 +216,61 @@ def test_batched_and_served_match_plain(ctx):
     finally:
         for v in vols:
             v.destroy()
+
+
+@pytest.mark.parametrize("dims,ch,dtype,bits,brick,pairs", [
+    ((64, 48, 20), 2, np.uint16, 12, (0, 0, 0), False),
+    ((1, 1, 1), 1, np.uint8, 8, (4, 4, 4), False),
+    ((100, 37, 9), 3, np.uint8, 8, (8, 16, 4), True),
+    ((129, 17, 33), 4, np.uint16, 16, (16, 16, 8), False),
+    ((40, 30, 20), 5, np.uint8, 8, (8, 8, 8), False),
+    ((23, 31, 8), 6, np.uint16, 10, (4, 8, 16), False),
+    ((1030, 9, 16), 1, np.uint16, 12, (0, 0, 0), True),
+])
+def test_cell_table_holds_the_channel_maxima(ctx, dims, ch, dtype, bits, brick, pairs):
+    # The table after the bricks, read back from the volume's storage, is
+    # the per-channel maximum over each cell's 9 x 9 x 9 voxels (indices
+    # [8c - 1, 8c + 7] clipped to the grid), values clamped to the bit depth.
+    rng = np.random.default_rng(sum(dims) + ch)
+    nx, ny, nz = dims
+    hi = 1 << (16 if dtype == np.uint16 else 8)
+    data = rng.integers(0, hi, size=(ch, nz, ny, nx)).astype(dtype)
+    data[:, : nz // 2] //= 50   # quiet regions with small maxima
+    sc = Scene("cells", data, bits, [TF()] * ch, None, 1, 1, False, 1.0, 1.0)
+    v = gpu.make_volume(ctx, sc, brick, row_pairs=pairs)
+    try:
+        W = {1: 1, 2: 2, 3: 4, 4: 4, 5: 8, 6: 8}[ch] * (2 if dtype == np.uint16 else 1)
+        B = [int(x) for x in (brick if brick != (0, 0, 0) else default_brick(ch, dtype, pairs))]
+        nb = [(n + 1 + e - 1) // e for n, e in zip(dims, B)]
+        row = 2 * (B[0] + 1) if pairs else B[0] + 1
+        plane = B[1] * row if pairs else (B[1] + 1) * row
+        words = nb[0] * nb[1] * nb[2] * plane * (B[2] + 1)
+        cell_off = (words * W + 255) // 256 * 256
+        nc = [n // 8 + 1 for n in dims]
+        cells = nc[0] * nc[1] * nc[2]
+        off = v.base - v.storage.data_ptr()
+        raw = v.storage[off + cell_off: off + cell_off + cells * W].cpu().numpy()
+        lane = np.uint16 if dtype == np.uint16 else np.uint8
+        table = raw.view(lane).reshape(nc[2], nc[1], nc[0], -1)[..., :ch]
+        full = (1 << bits) - 1
+        clamped = np.minimum(data.astype(np.int64), full)
+        for cz in range(nc[2]):
+            z0, z1 = max(8 * cz - 1, 0), min(8 * cz + 7, nz - 1)
+            for cy in range(nc[1]):
+                y0, y1 = max(8 * cy - 1, 0), min(8 * cy + 7, ny - 1)
+                blk = clamped[:, z0:z1 + 1, y0:y1 + 1, :]
+                for cx in range(nc[0]):
+                    x0, x1 = max(8 * cx - 1, 0), min(8 * cx + 7, nx - 1)
+                    exp = blk[:, :, :, x0:x1 + 1].reshape(ch, -1).max(axis=1) \
+                        if x0 <= x1 and y0 <= y1 and z0 <= z1 else np.zeros(ch)
+                    assert np.array_equal(table[cz, cy, cx].astype(np.int64), exp), \
+                        (cz, cy, cx, table[cz, cy, cx], exp)
+    finally:
+        v.destroy()
+
+
+def default_brick(ch, dtype, pairs):
+    w = {1: 1, 2: 2, 3: 4, 4: 4, 5: 8, 6: 8}[ch] * (2 if dtype == np.uint16 else 1)
+    if pairs:
+        return (16 if w == 1 else 8 if w == 2 else 4, 32 if w == 2 else 16, 8 if w == 2 else 16)
+    return (16 if w == 1 else 8, 8 if w >= 8 else 16, 8)
