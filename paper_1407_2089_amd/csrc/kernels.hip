@@ -182,61 +182,27 @@ __global__ __launch_bounds__(kRelayoutThreads) void relayout_scatter_kernel(
 }
 
 // ------------------------------------------------------- macro-cell maxima
-// One thread per macro cell (grid x over cells along x, y and z one block row
-// per cell): per channel, the largest clamped voxel value over stored
-// coordinates [c M, c M + M] per axis, that is voxel indices
-// [c M - 1, c M + M - 1] clipped to the grid (the zero padding never raises a
-// maximum), packed like a voxel word at the frame's cell table.  A wave's
-// lanes read x runs M voxels apart, so one wave-wide load touches a few
-// consecutive cache lines.
-template <int C, bool U16>
-__global__ __launch_bounds__(256) void cellmax_kernel(BrickGeom g, const void* __restrict__ src,
-                                                      uint8_t* __restrict__ frame, uint32_t maxval) {
-    using T = typename WordT<C, U16>::T;
-    using S = typename std::conditional<U16, uint16_t, uint8_t>::type;
-    const S* in = reinterpret_cast<const S*>(src);
-    const int cx = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const int cy = (int)blockIdx.y, cz = (int)blockIdx.z;
-    if (cx >= g.nc[0]) return;
-    const int M = 1 << g.cshift;
-    const int x0 = max((cx << g.cshift) - 1, 0), x1 = min((cx << g.cshift) + M - 1, g.n[0] - 1);
-    const int y0 = max((cy << g.cshift) - 1, 0), y1 = min((cy << g.cshift) + M - 1, g.n[1] - 1);
-    const int z0 = max((cz << g.cshift) - 1, 0), z1 = min((cz << g.cshift) + M - 1, g.n[2] - 1);
-    const size_t plane = (size_t)g.n[0] * g.n[1];
-    const size_t vol = plane * g.n[2];
-    uint32_t ch[kMaxChannels] = {};
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-        uint32_t m = 0;
-        for (int k = z0; k <= z1; ++k)
-            for (int j = y0; j <= y1; ++j) {
-                const S* row = in + (size_t)c * vol + (size_t)k * plane + (size_t)j * g.n[0];
-                for (int i = x0; i <= x1; ++i) m = max(m, (uint32_t)row[i]);
-            }
-        ch[c] = m > maxval ? maxval : m;
-    }
-    T* cells = reinterpret_cast<T*>(frame + g.cell_off);
-    cells[((size_t)cz * g.nc[1] + cy) * g.nc[0] + cx] = pack_word<C, U16>(ch);
-}
-
-// The same table built strip by strip: a block takes one (y, z) row of cells
+// The frame's macro-cell table: per cell and channel, the largest clamped
+// voxel value over stored coordinates [c M, c M + M] per axis, that is voxel
+// indices [c M - 1, c M + M - 1] clipped to the grid (the zero padding never
+// raises a maximum), packed like a voxel word.  Built strip by strip: a block
+// takes one (y, z) row of cells
 // (cy, cz) and sweeps x in tiles of kCellTile voxels.  Its threads first
 // reduce, per channel, the strip's source rows (up to 9 x 9) into column
 // maxima in LDS, four consecutive columns per thread with one 4- or 8-byte
-// load per row (rows whose length is a multiple of 4 voxels keep such loads
-// aligned); then one thread per cell takes the maximum of its 9 columns (x
-// from 8 cx - 1 to 8 cx + 7; columns outside the grid hold 0, which never
-// raises a maximum).  Column xt - 1 of a tile is the previous tile's last.
-// Same values as cellmax_kernel.
+// load per row (ALIGNED: rows of a multiple of 4 voxels from an 8-byte
+// aligned source), else from two or three aligned dword loads; then one
+// thread per cell takes the maximum of
+// its 9 columns (x from 8 cx - 1 to 8 cx + 7; columns outside the grid hold
+// 0).  Column xt - 1 of a tile is the previous tile's last.
 constexpr int kCellTile = 1024;
-template <int C, bool U16>
+template <int C, bool U16, bool ALIGNED>
 __global__ __launch_bounds__(256) void cellmax_strip_kernel(BrickGeom g,
                                                             const void* __restrict__ src,
                                                             uint8_t* __restrict__ frame,
                                                             uint32_t maxval) {
     using T = typename WordT<C, U16>::T;
     using S = typename std::conditional<U16, uint16_t, uint8_t>::type;
-    using S4 = typename std::conditional<U16, uint2, uint32_t>::type;  // four voxels
     __shared__ uint32_t col[C][kCellTile + 1];  // col[c][1 + i]: column xt + i
     const S* in = reinterpret_cast<const S*>(src);
     const int cy = (int)blockIdx.x, cz = (int)blockIdx.y;
@@ -248,6 +214,7 @@ __global__ __launch_bounds__(256) void cellmax_strip_kernel(BrickGeom g,
     T* cells = reinterpret_cast<T*>(frame + g.cell_off) + ((size_t)cz * g.nc[1] + cy) * g.nc[0];
     const int xend = g.nc[0] * M;  // the last cell starts at 8 (nc0 - 1) <= n
     const int tid = (int)threadIdx.x;
+    const uint8_t* src_end = reinterpret_cast<const uint8_t*>(in + (size_t)C * vol);
     if (tid < C) col[tid][0] = 0;  // column -1
     for (int xt = 0; xt < xend; xt += kCellTile) {
         // four columns x = xt + 4 t .. xt + 4 t + 3 per thread (kCellTile = 4 x 256)
@@ -257,20 +224,50 @@ __global__ __launch_bounds__(256) void cellmax_strip_kernel(BrickGeom g,
             uint32_t m[4] = {0, 0, 0, 0};
             if (x + 3 < g.n[0]) {
                 for (int k = z0; k <= z1; ++k) {
-                    const S* p = in + (size_t)c * vol + (size_t)k * plane + x;
                     for (int j = y0; j <= y1; ++j) {
-                        const S4 w = *reinterpret_cast<const S4*>(p + (size_t)j * g.n[0]);
-                        if constexpr (U16) {
-                            m[0] = max(m[0], w.x & 0xffffu);
-                            m[1] = max(m[1], w.x >> 16);
-                            m[2] = max(m[2], w.y & 0xffffu);
-                            m[3] = max(m[3], w.y >> 16);
+                        const S* p = in + (size_t)c * vol + (size_t)k * plane + (size_t)j * g.n[0] + x;
+                        // the four voxels' bytes: one 4- or 8-byte load where the
+                        // group is aligned to its size; else from the aligned dwords
+                        // around it (a row need not start on a 4-byte boundary); near
+                        // the end of the source, where those dwords would reach past
+                        // it, voxel by voxel
+                        const uintptr_t b = (uintptr_t)p;
+                        const uint32_t* a = reinterpret_cast<const uint32_t*>(b & ~(uintptr_t)3);
+                        const uint32_t o = (uint32_t)(b & 3u);
+                        uint32_t v[4], lo = 0, hi = 0;
+                        bool packed = true;
+                        if constexpr (ALIGNED) {
+                            if constexpr (U16) {
+                                const uint2 q = *reinterpret_cast<const uint2*>(p);
+                                lo = q.x;
+                                hi = q.y;
+                            } else {
+                                lo = *reinterpret_cast<const uint32_t*>(p);
+                            }
+                        } else if ((const uint8_t*)a + (U16 ? 12 : 8) <= src_end) {
+                            const uint32_t d1 = a[1];
+                            lo = __builtin_amdgcn_alignbyte(d1, a[0], o);
+                            if constexpr (U16) hi = __builtin_amdgcn_alignbyte(a[2], d1, o);
                         } else {
-                            m[0] = max(m[0], w & 0xffu);
-                            m[1] = max(m[1], (w >> 8) & 0xffu);
-                            m[2] = max(m[2], (w >> 16) & 0xffu);
-                            m[3] = max(m[3], w >> 24);
+                            packed = false;
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) v[u] = (uint32_t)p[u];
                         }
+                        if (packed) {
+                            if constexpr (U16) {
+                                v[0] = lo & 0xffffu;
+                                v[1] = lo >> 16;
+                                v[2] = hi & 0xffffu;
+                                v[3] = hi >> 16;
+                            } else {
+                                v[0] = lo & 0xffu;
+                                v[1] = (lo >> 8) & 0xffu;
+                                v[2] = (lo >> 16) & 0xffu;
+                                v[3] = lo >> 24;
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) m[u] = max(m[u], v[u]);
                     }
                 }
             } else if (x < g.n[0]) {  // the row's ragged end
@@ -462,8 +459,10 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
     const unsigned gblocks = (unsigned)(blocks64 > 65536 ? 65536 : blocks64);
     const bool gather = g.shift[0] >= 3;  // bricks at least 8 voxels wide
     if (g.nc[1] > 65535 || g.nc[2] > 65535) return hipErrorInvalidValue;
-    const dim3 cgrid(((unsigned)g.nc[0] + 255u) / 256u, (unsigned)g.nc[1], (unsigned)g.nc[2]);
     const dim3 sgrid((unsigned)g.nc[1], (unsigned)g.nc[2]);
+    // rows of a multiple of 4 voxels from an 8-byte aligned source: every
+    // four-voxel group of the cell-table kernel is aligned to its own size
+    const bool aligned = g.n[0] % 4 == 0 && (reinterpret_cast<uintptr_t>(src) & 7u) == 0;
 #define VR_RL(C, U)                                                                       \
     if (channels == C && u16 == U) {                                                      \
         if (gather)                                                                       \
@@ -474,11 +473,12 @@ hipError_t launch_relayout(const BrickGeom& g, int channels, bool u16, int bits,
                                src, dst, maxval);                                         \
         hipError_t e = hipGetLastError();                                                 \
         if (e != hipSuccess) return e;                                                    \
-        if (g.n[0] % 4 == 0 && ((uintptr_t)src & 7u) == 0)                                \
-            hipLaunchKernelGGL((cellmax_strip_kernel<C, U>), sgrid, dim3(256), 0, s, g, src, dst, \
-                               maxval);                                                   \
+        if (aligned)                                                                      \
+            hipLaunchKernelGGL((cellmax_strip_kernel<C, U, true>), sgrid, dim3(256), 0, s, g, src, \
+                               dst, maxval);                                              \
         else                                                                              \
-            hipLaunchKernelGGL((cellmax_kernel<C, U>), cgrid, dim3(256), 0, s, g, src, dst, maxval); \
+            hipLaunchKernelGGL((cellmax_strip_kernel<C, U, false>), sgrid, dim3(256), 0, s, g, \
+                               src, dst, maxval);                                         \
         return hipGetLastError();                                                         \
     }
     VR_RL(1, false) VR_RL(2, false) VR_RL(3, false) VR_RL(4, false) VR_RL(5, false)

@@ -218,19 +218,28 @@ def test_batched_and_served_match_plain(ctx):
             v.destroy()
 
 
-@pytest.mark.parametrize("dims,ch,dtype,bits,brick,pairs", [
-    ((64, 48, 20), 2, np.uint16, 12, (0, 0, 0), False),
-    ((1, 1, 1), 1, np.uint8, 8, (4, 4, 4), False),
-    ((100, 37, 9), 3, np.uint8, 8, (8, 16, 4), True),
-    ((129, 17, 33), 4, np.uint16, 16, (16, 16, 8), False),
-    ((40, 30, 20), 5, np.uint8, 8, (8, 8, 8), False),
-    ((23, 31, 8), 6, np.uint16, 10, (4, 8, 16), False),
-    ((1030, 9, 16), 1, np.uint16, 12, (0, 0, 0), True),
+@pytest.mark.parametrize("dims,ch,dtype,bits,brick,pairs,off", [
+    ((64, 48, 20), 2, np.uint16, 12, (0, 0, 0), False, 0),
+    ((1, 1, 1), 1, np.uint8, 8, (4, 4, 4), False, 0),
+    ((100, 37, 9), 3, np.uint8, 8, (8, 16, 4), True, 0),
+    ((129, 17, 33), 4, np.uint16, 16, (16, 16, 8), False, 0),
+    ((40, 30, 20), 5, np.uint8, 8, (8, 8, 8), False, 0),
+    ((23, 31, 8), 6, np.uint16, 10, (4, 8, 16), False, 0),
+    ((1030, 9, 16), 1, np.uint16, 12, (0, 0, 0), True, 0),
+    # sources that start off a 4-byte boundary, rows of odd length, a row
+    # longer than two 1024-voxel tiles
+    ((101, 19, 11), 1, np.uint8, 8, (0, 0, 0), False, 1),
+    ((101, 19, 11), 3, np.uint8, 8, (8, 8, 8), True, 3),
+    ((77, 13, 10), 2, np.uint16, 12, (0, 0, 0), False, 2),
+    ((2053, 10, 9), 4, np.uint8, 8, (0, 0, 0), False, 2),
+    ((2051, 7, 5), 1, np.uint16, 16, (0, 0, 0), False, 2),
 ])
-def test_cell_table_holds_the_channel_maxima(ctx, dims, ch, dtype, bits, brick, pairs):
+def test_cell_table_holds_the_channel_maxima(ctx, dims, ch, dtype, bits, brick, pairs, off):
     # The table after the bricks, read back from the volume's storage, is
     # the per-channel maximum over each cell's 9 x 9 x 9 voxels (indices
     # [8c - 1, 8c + 7] clipped to the grid), values clamped to the bit depth.
+    # off: the source's byte offset from an aligned allocation.
+    import torch
     rng = np.random.default_rng(sum(dims) + ch)
     nx, ny, nz = dims
     hi = 1 << (16 if dtype == np.uint16 else 8)
@@ -239,6 +248,15 @@ def test_cell_table_holds_the_channel_maxima(ctx, dims, ch, dtype, bits, brick, 
     sc = Scene("cells", data, bits, [TF()] * ch, None, 1, 1, False, 1.0, 1.0)
     v = gpu.make_volume(ctx, sc, brick, row_pairs=pairs)
     try:
+        if off:
+            raw = np.ascontiguousarray(data).view(np.uint8).reshape(-1)
+            buf = torch.zeros(raw.size + off, dtype=torch.uint8, device="cuda")
+            buf[off:] = torch.from_numpy(raw).cuda()
+            src = buf[off:]
+            src = (src.view(torch.int16) if dtype == np.uint16 else src).view(data.shape)
+            assert src.data_ptr() % 4 == off % 4
+            v.upload(0, src)  # rebuilds the bricks and the table from the offset copy
+            torch.cuda.synchronize()
         W = {1: 1, 2: 2, 3: 4, 4: 4, 5: 8, 6: 8}[ch] * (2 if dtype == np.uint16 else 1)
         B = [int(x) for x in (brick if brick != (0, 0, 0) else default_brick(ch, dtype, pairs))]
         nb = [(n + 1 + e - 1) // e for n, e in zip(dims, B)]
