@@ -453,6 +453,7 @@ void make_params(const vr_render_req& r, const vr_transfer* tf_in, ReqParams* P)
     P->width = r.width;
     P->height = r.height;
     P->skip_cells = v.ctx->cell_skip ? 1 : 0;
+    P->half_clamp = d.dtype == VR_U16 && d.bits == 16 ? 1 : 0;  // stored values <= 2^bits - 1
     P->out = r.out_rgba;
     P->samples = r.out_samples;
 }

@@ -76,14 +76,27 @@ typedef uint16_t u16x2_t __attribute__((ext_vector_type(2)));
 // 16-bit values at or above 65520 would round to +inf in FP16; they are
 // clamped to 65504, the largest finite half (a change of at most 31 raw
 // units, within FP16's own rounding step of 32 at that magnitude).
+// The two conversions write the halves of one register: the second converts
+// the high word into the high half and keeps the low half (SDWA), which the
+// compiler's own lowering does with a third instruction that packs two
+// results.  Same rounding (to nearest even) and bits as the plain casts.
+// kClamp = false: values known to stay below 65504 (data of at most 15 bits).
 constexpr uint16_t kHalfMax = 65504;
+template <bool kClamp = true>
 __device__ __forceinline__ half2_t u16x2_to_half2(uint32_t w) {
-    const u16x2_t v = __builtin_elementwise_min(__builtin_bit_cast(u16x2_t, w),
-                                                u16x2_t{kHalfMax, kHalfMax});
-    return half2_t{(_Float16)v.x, (_Float16)v.y};
+    uint32_t x = w;
+    if constexpr (kClamp)
+        x = __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2_t, w),
+                                                                   u16x2_t{kHalfMax, kHalfMax}));
+    uint32_t r;
+    asm("v_cvt_f16_u16_e32 %0, %1\n\t"
+        "v_cvt_f16_u16_sdwa %0, %1 dst_sel:WORD_1 dst_unused:UNUSED_PRESERVE src0_sel:WORD_1"
+        : "=&v"(r)
+        : "v"(x));
+    return __builtin_bit_cast(half2_t, r);
 }
 
-template <int C, bool U16, typename T>
+template <int C, bool U16, bool kClamp = true, typename T>
 __device__ __forceinline__ void unpack_f16(T w, half2_t (&h)[(C + 1) / 2]) {
     if constexpr (!U16) {
         if constexpr (C == 1) {
@@ -95,11 +108,11 @@ __device__ __forceinline__ void unpack_f16(T w, half2_t (&h)[(C + 1) / 2]) {
         }
     } else {
         if constexpr (C == 1) {
-            const uint16_t v = (uint16_t)w < kHalfMax ? (uint16_t)w : kHalfMax;
+            const uint16_t v = !kClamp || (uint16_t)w < kHalfMax ? (uint16_t)w : kHalfMax;
             h[0] = half2_t{(_Float16)v, (_Float16)0.0f};
         } else {
 #pragma unroll
-            for (int q = 0; q < (C + 1) / 2; ++q) h[q] = u16x2_to_half2(part(w, q));
+            for (int q = 0; q < (C + 1) / 2; ++q) h[q] = u16x2_to_half2<kClamp>(part(w, q));
         }
     }
 }
@@ -584,7 +597,7 @@ __device__ __forceinline__ half2_t lerp(half2_t a, half2_t b, half2_t f) {
 // keeps the lerp tree for any channel count: it returns a constant field
 // exactly (a + f (a - a) = a), which the weighted sum does not (its FP32
 // weights sum to 1 only up to rounding).
-template <int C, bool U16, bool F16, bool kLerp = false, typename T>
+template <int C, bool U16, bool F16, bool kLerp = false, bool kClamp16 = true, typename T>
 __device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
     const float fx = t.fx, fy = t.fy, fz = t.fz;
     if constexpr (!F16 && C >= 3 && !kLerp) {
@@ -633,14 +646,14 @@ __device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
     } else {
         constexpr int NP = (C + 1) / 2;
         half2_t a000[NP], a100[NP], a010[NP], a110[NP], a001[NP], a101[NP], a011[NP], a111[NP];
-        unpack_f16<C, U16>(t.w000, a000);
-        unpack_f16<C, U16>(t.w100, a100);
-        unpack_f16<C, U16>(t.w010, a010);
-        unpack_f16<C, U16>(t.w110, a110);
-        unpack_f16<C, U16>(t.w001, a001);
-        unpack_f16<C, U16>(t.w101, a101);
-        unpack_f16<C, U16>(t.w011, a011);
-        unpack_f16<C, U16>(t.w111, a111);
+        unpack_f16<C, U16, kClamp16>(t.w000, a000);
+        unpack_f16<C, U16, kClamp16>(t.w100, a100);
+        unpack_f16<C, U16, kClamp16>(t.w010, a010);
+        unpack_f16<C, U16, kClamp16>(t.w110, a110);
+        unpack_f16<C, U16, kClamp16>(t.w001, a001);
+        unpack_f16<C, U16, kClamp16>(t.w101, a101);
+        unpack_f16<C, U16, kClamp16>(t.w011, a011);
+        unpack_f16<C, U16, kClamp16>(t.w111, a111);
         // The fractions go to FP16 through one explicit conversion (round
         // toward zero, both halves at once).  A plain cast would let the
         // compiler merge a fraction rounded from FP64 to FP32 (large volumes)
@@ -1005,7 +1018,13 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
     auto composite = [&](const Taps<Word>& t, bool on, int j) {
         if (!on || (clear_ok && transparent<C, U16>(t, P.clear))) return;
         float x[C];
-        interpolate<C, U16, F16>(t, x);
+        if constexpr (F16 && U16) {
+            // data of at most 15 bits needs no clamp below the largest half
+            if (P.half_clamp) interpolate<C, U16, F16, false, true>(t, x);
+            else interpolate<C, U16, F16, false, false>(t, x);
+        } else {
+            interpolate<C, U16, F16>(t, x);
+        }
         float shade[C];
         if constexpr (kLit) {
             const R sj = fma_r((R)j, step, half_step);

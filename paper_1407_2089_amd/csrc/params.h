@@ -150,6 +150,8 @@ struct ReqParams {
     float sx_scale, sy_scale; // 2 / W, 2 / H
     int32_t width, height, eyes;
     int32_t skip_cells;     // 1: rays jump over macro cells shown transparent
+    int32_t half_clamp;     // 1: uint16 words may hold values above 65503 (16-bit
+                            // data), which FP16 sampling clamps to the largest half
     float* out;             // [eyes][H][W][4]
     int32_t* samples;       // [eyes][H][W] or null
     // Samples composited, or null: kCountSlots counters kCountStride words

@@ -114,6 +114,23 @@ def test_skip_on_the_realistic_content(ctx):
         assert_same_bits(full_img, skip_img)
 
 
+@pytest.mark.parametrize("ch,bits", [(1, 15), (2, 15), (3, 15), (1, 16), (2, 16)])
+def test_fp16_sampling_at_the_top_of_the_bit_depth(ctx, ch, bits):
+    """Taps at the full scale 2^bits - 1: 15-bit data converts to FP16
+    without the clamp at 65504 that 16-bit data takes; both match the oracle
+    within the FP16 tolerance."""
+    nx, ny, nz = 26, 22, 14
+    vol = scenes.random_volume(72 + ch, (ch, nz, ny, nx), np.uint16, 1 << bits)
+    vol[:, 3:11, 4:18, 5:20] = (1 << bits) - 1
+    tfs = [TF(0.5, 1.0, 0.0, 0.3, tuple(float(x) for x in np.roll((1.0, 0.3, 0.0), c)))
+           for c in range(ch)]
+    cam = synth.orbit_camera((nx, ny, nz), 20.0, 40.0, 45.0)
+    sc = Scene("top", vol, bits, tfs, cam, 40, 30, True, 0.6, 0.995)
+    rgba, smp = gpu.render(ctx, sc, vr.VR_FP16)
+    assert np.isfinite(rgba).all()
+    gpu.compare(rgba, smp, orc.render_all(sc), 4e-3)
+
+
 def test_fp16_sampling_of_saturated_16_bit_taps_is_finite(ctx):
     """16-bit taps at 65535 exceed the largest finite half (65504); FP16
     sampling clamps them and stays within the FP16 tolerance of the oracle.
