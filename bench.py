@@ -6,10 +6,10 @@ pair 1920x1080 per eye, step 1 voxel, early termination at alpha 0.99, FP32.
 One step = one stereo pair (one vr_render launch, both eyes).  Prints one
 JSON line:
   - value: ray-samples/s (composited samples, the method's nominal count,
-    which empty-space skipping leaves unchanged) and stereo frames/s, timed
-    after a warm-up of at least 0.3 s;
-  - roofline: the render kernel's median launch time (HIP events on its
-    stream), its effective sampled bytes (8 taps x channels x bytes per
+    which empty-space skipping leaves unchanged) and stereo frames/s, over
+    K launches back to back after a warm-up of at least 0.3 s;
+  - roofline: the render kernel's average launch time (HIP events on its
+    stream, around each of K further launches), its effective sampled bytes (8 taps x channels x bytes per
     voxel per sample) over that time against the 8 TB/s HBM peak, the
     compulsory-byte fraction (the frame's voxels and the image, once), the
     same launch without the exact skips, and HBM traffic and VALU busy
@@ -413,9 +413,11 @@ def main():
 
     def timed(r, steps, warmup):
         """Warm-up of `warmup` launches and at least 0.3 s (clocks settle),
-        then `steps` launches, each bracketed by events on the launch stream;
-        returns (wall seconds of the timed launches, median and mean kernel
-        ms)."""
+        then `steps` launches back to back between two synchronizations (the
+        wall time), then `steps` more, each bracketed by events on the launch
+        stream (the kernel time; the events' own markers stay out of the
+        wall time); returns (wall seconds of the timed launches, median and
+        mean kernel ms)."""
         for _ in range(warmup):
             vr.vr_render(ctx.ptr, r, stream)
         t_end = time.perf_counter() + 0.3
@@ -423,16 +425,19 @@ def main():
             for _ in range(20):
                 vr.vr_render(ctx.ptr, r, stream)
             torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        for _ in range(steps):
+            vr.vr_render(ctx.ptr, r, stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
         for k in range(steps):
             ev[k][0].record(stream)
             vr.vr_render(ctx.ptr, r, stream)
             ev[k][1].record(stream)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
         ms = [a.elapsed_time(b) for a, b in ev]
         return wall, float(np.median(ms)), float(np.mean(ms))
 
