@@ -65,10 +65,14 @@ __device__ __forceinline__ void unpack_f32(T w, float (&x)[C]) {
 // is placed under the FP16 pattern 0x64.. (the value 1024 + b), then 1024 is
 // subtracted from both halves at once.  uint16 channels convert with the
 // FP16 rounding of the value (exact up to 2048).
+// kBiased: the values 1024 + b themselves, for a caller that subtracts the
+// bias where it needs it (the difference of two such values is already exact).
+constexpr half2_t kByteBias = {(_Float16)1024.0f, (_Float16)1024.0f};
+template <bool kBiased = false>
 __device__ __forceinline__ half2_t bytes_to_half2(uint32_t w, uint32_t sel) {
     const uint32_t v = __builtin_amdgcn_perm(0x64646464u, w, sel);
-    const half2_t bias = {(_Float16)1024.0f, (_Float16)1024.0f};
-    return __builtin_bit_cast(half2_t, v) - bias;
+    if constexpr (kBiased) return __builtin_bit_cast(half2_t, v);
+    else return __builtin_bit_cast(half2_t, v) - kByteBias;
 }
 
 typedef uint16_t u16x2_t __attribute__((ext_vector_type(2)));
@@ -96,7 +100,8 @@ __device__ __forceinline__ half2_t u16x2_to_half2(uint32_t w) {
     return __builtin_bit_cast(half2_t, r);
 }
 
-template <int C, bool U16, bool kClamp = true, typename T>
+// kBiased (uint8, two channels or more): pairs of 1024 + b, see bytes_to_half2.
+template <int C, bool U16, bool kClamp = true, bool kBiased = false, typename T>
 __device__ __forceinline__ void unpack_f16(T w, half2_t (&h)[(C + 1) / 2]) {
     if constexpr (!U16) {
         if constexpr (C == 1) {
@@ -104,7 +109,8 @@ __device__ __forceinline__ void unpack_f16(T w, half2_t (&h)[(C + 1) / 2]) {
         } else {
 #pragma unroll
             for (int q = 0; q < (C + 1) / 2; ++q)  // bytes 0, 1 or 2, 3 of part q / 2
-                h[q] = bytes_to_half2(part(w, q >> 1), (q & 1) ? 0x04030402u : 0x04010400u);
+                h[q] = bytes_to_half2<kBiased>(part(w, q >> 1),
+                                               (q & 1) ? 0x04030402u : 0x04010400u);
         }
     } else {
         if constexpr (C == 1) {
@@ -645,15 +651,20 @@ __device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
         }
     } else {
         constexpr int NP = (C + 1) / 2;
+        // uint8 pairs stay biased (1024 + b) into the x lerps: the difference
+        // of two biased taps is the exact difference of the bytes, so only
+        // each lerp's base needs the bias removed, and the lerp is the one of
+        // the unbiased taps bit for bit.
+        constexpr bool kB = !U16 && C >= 2;
         half2_t a000[NP], a100[NP], a010[NP], a110[NP], a001[NP], a101[NP], a011[NP], a111[NP];
-        unpack_f16<C, U16, kClamp16>(t.w000, a000);
-        unpack_f16<C, U16, kClamp16>(t.w100, a100);
-        unpack_f16<C, U16, kClamp16>(t.w010, a010);
-        unpack_f16<C, U16, kClamp16>(t.w110, a110);
-        unpack_f16<C, U16, kClamp16>(t.w001, a001);
-        unpack_f16<C, U16, kClamp16>(t.w101, a101);
-        unpack_f16<C, U16, kClamp16>(t.w011, a011);
-        unpack_f16<C, U16, kClamp16>(t.w111, a111);
+        unpack_f16<C, U16, kClamp16, kB>(t.w000, a000);
+        unpack_f16<C, U16, kClamp16, kB>(t.w100, a100);
+        unpack_f16<C, U16, kClamp16, kB>(t.w010, a010);
+        unpack_f16<C, U16, kClamp16, kB>(t.w110, a110);
+        unpack_f16<C, U16, kClamp16, kB>(t.w001, a001);
+        unpack_f16<C, U16, kClamp16, kB>(t.w101, a101);
+        unpack_f16<C, U16, kClamp16, kB>(t.w011, a011);
+        unpack_f16<C, U16, kClamp16, kB>(t.w111, a111);
         // The fractions go to FP16 through one explicit conversion (round
         // toward zero, both halves at once).  A plain cast would let the
         // compiler merge a fraction rounded from FP64 to FP32 (large volumes)
@@ -665,10 +676,18 @@ __device__ __forceinline__ void interpolate(const Taps<T>& t, float (&x)[C]) {
         const half2_t hz = __builtin_bit_cast(half2_t, __builtin_amdgcn_cvt_pkrtz(fz, fz));
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-            half2_t c00 = lerp(a000[q], a100[q], hx);
-            half2_t c10 = lerp(a010[q], a110[q], hx);
-            half2_t c01 = lerp(a001[q], a101[q], hx);
-            half2_t c11 = lerp(a011[q], a111[q], hx);
+            half2_t c00, c10, c01, c11;
+            if constexpr (kB) {
+                c00 = __builtin_elementwise_fma(hx, a100[q] - a000[q], a000[q] - kByteBias);
+                c10 = __builtin_elementwise_fma(hx, a110[q] - a010[q], a010[q] - kByteBias);
+                c01 = __builtin_elementwise_fma(hx, a101[q] - a001[q], a001[q] - kByteBias);
+                c11 = __builtin_elementwise_fma(hx, a111[q] - a011[q], a011[q] - kByteBias);
+            } else {
+                c00 = lerp(a000[q], a100[q], hx);
+                c10 = lerp(a010[q], a110[q], hx);
+                c01 = lerp(a001[q], a101[q], hx);
+                c11 = lerp(a011[q], a111[q], hx);
+            }
             half2_t c0 = lerp(c00, c10, hy);
             half2_t c1 = lerp(c01, c11, hy);
             half2_t v = lerp(c0, c1, hz);
