@@ -186,15 +186,14 @@ __global__ __launch_bounds__(kRelayoutThreads) void relayout_scatter_kernel(
 // voxel value over stored coordinates [c M, c M + M] per axis, that is voxel
 // indices [c M - 1, c M + M - 1] clipped to the grid (the zero padding never
 // raises a maximum), packed like a voxel word.  Built strip by strip: a block
-// takes one (y, z) row of cells
-// (cy, cz) and sweeps x in tiles of kCellTile voxels.  Its threads first
-// reduce, per channel, the strip's source rows (up to 9 x 9) into column
-// maxima in LDS, four consecutive columns per thread with one 4- or 8-byte
-// load per row (ALIGNED: rows of a multiple of 4 voxels from an 8-byte
-// aligned source), else from two or three aligned dword loads; then one
-// thread per cell takes the maximum of
-// its 9 columns (x from 8 cx - 1 to 8 cx + 7; columns outside the grid hold
-// 0).  Column xt - 1 of a tile is the previous tile's last.
+// takes one (y, z) row of cells (cy, cz) and sweeps x in tiles of kCellTile
+// voxels.  Its threads first reduce, per channel, the strip's source rows
+// (up to 9 x 9) into column maxima in LDS, four consecutive columns per
+// thread with one 4- or 8-byte load per row (ALIGNED: rows of a multiple of
+// 4 voxels from an 8-byte aligned source), else from two or three aligned
+// dword loads; then one thread per cell takes the maximum of its 9 columns
+// (x from 8 cx - 1 to 8 cx + 7; columns outside the grid hold 0).  Column
+// xt - 1 of a tile is the previous tile's last.
 constexpr int kCellTile = 1024;
 template <int C, bool U16, bool ALIGNED>
 __global__ __launch_bounds__(256) void cellmax_strip_kernel(BrickGeom g,
