@@ -322,12 +322,9 @@ constexpr int lit_min_waves(int v, bool lit, bool clear) {
     // variant_index(channels, u16, fp16, row pairs, large)
     switch (v) {
         case variant_index(2, true, false, false, false):
-        case variant_index(2, true, true, false, false):
         case variant_index(2, false, false, true, false):
         case variant_index(2, true, false, true, false):
         case variant_index(2, false, true, true, false):
-        case variant_index(2, true, true, true, false):
-        case variant_index(1, true, false, true, true):
             return 6;
         default:
             return 1;

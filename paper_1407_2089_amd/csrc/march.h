@@ -1107,6 +1107,51 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
 #pragma unroll
         for (int a = 0; a < 3; ++a) c[a] = corner(S, fma_r(sj, d[a], pe[a]), a) >> cs;
     };
+    // The last sample from k on whose low corner lies in cell c (the cell of
+    // sample k): the exit estimate, checked with the fetch's own arithmetic.
+    auto cell_last = [&](int k, const uint32_t (&c)[3]) -> int {
+        R jx = (R)n;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (d[ax] != (R)0) {
+                const R bound = (R)((d[ax] > (R)0 ? c[ax] + 1u : c[ax]) << cs);
+                const R t = fma_r(bound, ex_mul[ax], ex_add[ax]);
+                jx = t < jx ? t : jx;
+            }
+        }
+        int jl = jx > (R)k ? (int)ceil_r(jx) - 1 : k;
+        jl = jl < k ? k : (jl > n - 1 ? n - 1 : jl);
+        if (jl > k) {
+            uint32_t e[3];
+            cell_of(jl, e);
+            if (e[0] != c[0] || e[1] != c[1] || e[2] != c[2]) jl = k;
+        }
+        return jl;
+    };
+    // The first sample at or after lo, up to k, whose low corner lies in cell
+    // c (the cell of sample k): the entry estimate, checked the same way (a
+    // failed check keeps sample k alone).
+    auto cell_first = [&](int k, const uint32_t (&c)[3], int lo) -> int {
+        R jx = (R)lo;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (d[ax] != (R)0) {
+                const R bound = (R)((d[ax] > (R)0 ? c[ax] : c[ax] + 1u) << cs);
+                const R t = fma_r(bound, ex_mul[ax], ex_add[ax]);
+                jx = t > jx ? t : jx;
+            }
+        }
+        int jf = jx < (R)k ? (int)ceil_r(jx) : k;
+        jf = jf > k ? k : (jf < lo ? lo : jf);
+#pragma unroll
+        for (int tries = 0; tries < 2 && jf < k; ++tries) {
+            uint32_t e[3];
+            cell_of(jf, e);
+            if (e[0] == c[0] && e[1] == c[1] && e[2] == c[2]) return jf;
+            ++jf;  // the estimate's sample lies on the cell's face, just outside
+        }
+        return k;
+    };
     int count = n;
     int kend = cells_on ? 0 : n;  // samples below kend lie in a non-transparent cell
     if (n > 0) {
@@ -1116,15 +1161,42 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
             // Lit: one sample per iteration, no taps in flight across
             // iterations (the shading's loads need the registers: 6 waves
             // per SIMD instead of 4, measured 7 % faster than the pipeline
-            // below), and no macro cells (lanes that jump apart shade in
-            // more iterations, measured slower).
-            bool live;
-            do {
+            // below), and macro cells only before the first and after the
+            // last cell that is not transparent (jumps between those let the
+            // lanes drift apart, and they shade in more iterations: measured
+            // slower, 0.215 against 0.190 ms on the realistic frame).
+            // The leading and trailing empty space is skipped over
+            // transparent macro cells (exact, as below): the lane walks every
+            // sample from the first cell that is not transparent to the end
+            // of the last one.
+            int kstop = n;
+            if (clear_ok && P.skip_cells != 0) {
+                bool more = true;
+                while (more) {
+                    uint32_t c[3];
+                    cell_of(k, c);
+                    const Word w = load_cell<Word>(P.g, S, c);
+                    more = cell_clear<C, U16>(w, P.clear);
+                    if (more) k = cell_last(k, c) + 1;
+                    more = more && k < n;
+                }
+                more = k < n;
+                while (more) {
+                    uint32_t c[3];
+                    cell_of(kstop - 1, c);
+                    const Word w = load_cell<Word>(P.g, S, c);
+                    more = cell_clear<C, U16>(w, P.clear);
+                    if (more) kstop = cell_first(kstop - 1, c, k);
+                    more = more && kstop > k;
+                }
+            }
+            bool live = k < kstop;
+            while (live) {
                 composite(fetch_at(k), true, k);
                 ++k;
                 if (A >= tau) count = k;
-                live = k < n && A < tau;
-            } while (live);
+                live = k < kstop && A < tau;
+            }
         } else if (!cells_on) {
             // Without macro cells (a frame with nothing to skip, or the test
             // switched off): the same software pipeline over pairs of
@@ -1164,22 +1236,7 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
                     uint32_t c[3];
                     cell_of(k, c);
                     const Word w = load_cell<Word>(P.g, S, c);
-                    R jx = (R)n;
-#pragma unroll
-                    for (int ax = 0; ax < 3; ++ax) {
-                        if (d[ax] != (R)0) {
-                            const R bound = (R)((d[ax] > (R)0 ? c[ax] + 1u : c[ax]) << cs);
-                            const R t = fma_r(bound, ex_mul[ax], ex_add[ax]);
-                            jx = t < jx ? t : jx;
-                        }
-                    }
-                    int jl = jx > (R)k ? (int)ceil_r(jx) - 1 : k;
-                    jl = jl < k ? k : (jl > n - 1 ? n - 1 : jl);
-                    if (jl > k) {
-                        uint32_t e[3];
-                        cell_of(jl, e);
-                        if (e[0] != c[0] || e[1] != c[1] || e[2] != c[2]) jl = k;
-                    }
+                    const int jl = cell_last(k, c);
                     if (cell_clear<C, U16>(w, P.clear)) k = jl + 1;
                     else kend = jl + 1;
                 }
