@@ -232,7 +232,7 @@ def choose_layout(args, ctx, dims, channels, dtype, bits, src, tfs, views, strea
     ms = vr.vr_tune_layout(ctx.ptr, desc, tfs, src, views, reps=10, stream=stream)
     return (tuple(desc.brick), bool(desc.row_pairs),
             f"vr_tune_layout on this view ({ms:.4f} ms median per launch, "
-            f"{time.time() - t0:.1f} s of tuning)")
+            f"{time.time() - t0:.2f} s of tuning)")
 
 
 def tiny(args):
