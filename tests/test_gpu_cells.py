@@ -145,15 +145,67 @@ def test_lit_render(ctx):
     gpu.compare(both[0], both[1], orc.render_all(sc), 1e-3)
 
 
+LIGHT = synth.Light((0.3, -0.5, 0.8), 0.3, 0.7)
+
+
+@pytest.mark.parametrize("axis", range(6))
+def test_lit_axis_aligned_ortho_views(ctx, axis):
+    """Lit rays skip only their leading and trailing transparent cells; along
+    the axes (direction components of 0, sample corners on cell faces) the
+    image and the counts are those of the full walk."""
+    nx, ny, nz = 45, 38, 29
+    vol = sparse_volume(41 + axis, (1, nz, ny, nx), np.uint8, 255)
+    fwd, up = AXES[axis]
+    ctr = np.array([(nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2]) - 60.0 * np.array(fwd)
+    cam = Cam("ortho", tuple(ctr), fwd, up, ortho_height=50.0)
+    sc = Scene("lit-axis", vol, 8, tfs_for(1, 255), cam, 64, 56, False, 1.0, 1.0, light=LIGHT)
+    full, sample_only, both = render_modes(ctx, sc)
+    same_bits(full, sample_only)
+    same_bits(full, both)
+    gpu.compare(both[0], both[1], orc.render_all(sc), 1e-3)
+
+
+@pytest.mark.parametrize("precision", [vr.VR_FP32, vr.VR_FP16])
+@pytest.mark.parametrize("ch,dtype,bits", [(1, np.uint8, 8), (2, np.uint16, 12), (4, np.uint8, 8),
+                                           (5, np.uint8, 8)])
+def test_lit_oblique_stereo_views(ctx, ch, dtype, bits, precision):
+    full_v = (1 << bits) - 1
+    nx, ny, nz = 70, 61, 37
+    vol = sparse_volume(51 + 7 * ch, (ch, nz, ny, nx), dtype, full_v, n_blobs=4)
+    cam = synth.orbit_camera((nx, ny, nz), 123.0, -20.0, 45.0)
+    sc = Scene("lit-oblique", vol, bits, tfs_for(ch, full_v), cam, 88, 64, True, 1.0, 0.99,
+               light=LIGHT)
+    full, sample_only, both = render_modes(ctx, sc, precision)
+    same_bits(full, sample_only)
+    same_bits(full, both)
+    if precision == vr.VR_FP32:
+        gpu.compare(both[0], both[1], orc.render_all(sc), 1e-3)
+
+
+def test_lit_transparent_volume_keeps_counts(ctx):
+    """Every cell transparent: each lit ray's leading skip reaches its exit."""
+    nx, ny, nz = 50, 40, 30
+    vol = sparse_volume(4, (1, nz, ny, nx), np.uint8, 255, n_blobs=0)
+    cam = synth.orbit_camera((nx, ny, nz), 40.0, 25.0, 45.0)
+    sc = Scene("lit-empty", vol, 8, tfs_for(1, 255, lo=0.5), cam, 64, 40, True, 0.6, 1.0,
+               light=LIGHT)
+    full, sample_only, both = render_modes(ctx, sc)
+    same_bits(full, both)
+    gpu.compare(both[0], both[1], orc.render_all(sc), 1e-3)
+    assert np.all(both[0] == 0.0) and both[1].max() > 0
+
+
+@pytest.mark.parametrize("lit", [False, True])
 @pytest.mark.parametrize("ch,dtype,bits", [(2, np.uint16, 12), (5, np.uint8, 8)])
-def test_large_addressing(ctx, ch, dtype, bits):
+def test_large_addressing(ctx, ch, dtype, bits, lit):
     """The FP64 path steps, clamps and floors in double: its cell walk checks
     its own arithmetic."""
     full_v = (1 << bits) - 1
     nx, ny, nz = 58, 49, 30
     vol = sparse_volume(77 + ch, (ch, nz, ny, nx), dtype, full_v)
     cam = synth.orbit_camera((nx, ny, nz), 200.0, 35.0, 45.0)
-    sc = Scene("large", vol, bits, tfs_for(ch, full_v), cam, 64, 48, True, 1.0, 0.99)
+    sc = Scene("large", vol, bits, tfs_for(ch, full_v), cam, 64, 48, True, 1.0, 0.99,
+               light=LIGHT if lit else None)
     vr.vr_test_large_addressing(ctx.ptr, True)
     try:
         v = gpu.make_volume(ctx, sc)
