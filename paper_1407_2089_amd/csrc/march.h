@@ -1012,6 +1012,22 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
     ChanTF tf[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) tf[c] = P.tf[c];
+    // Unlit with one or two channels, the two addends of the transfer
+    // function are held in vector registers: a multiply-add reads at most
+    // one scalar register, so with both its constants scalar each use would
+    // first copy one into a vector register.  (Lit kernels run at a register
+    // cap, and with more channels the registers would cost waves.)
+    float tf_bias[C], tf_omc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        if constexpr (kLit || C > 2) {
+            tf_bias[c] = tf[c].bias;
+            tf_omc[c] = tf[c].one_m_curve;
+        } else {
+            asm("v_mov_b32 %0, %1" : "=v"(tf_bias[c]) : "v"(tf[c].bias));
+            asm("v_mov_b32 %0, %1" : "=v"(tf_omc[c]) : "v"(tf[c].one_m_curve));
+        }
+    }
 
     const typename Variant<V>::Smp S = sampler_for<LARGE>(P);
     R step;
@@ -1054,9 +1070,9 @@ __device__ __forceinline__ void render_pixel(const ReqParams& P, int eye, int px
         float amax = 0.0f, r = 0.0f, gg = 0.0f, bb = 0.0f;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const float u = __builtin_amdgcn_fmed3f(fmaf(x[c], tf[c].scale, tf[c].bias), 0.0f,
+            const float u = __builtin_amdgcn_fmed3f(fmaf(x[c], tf[c].scale, tf_bias[c]), 0.0f,
                                                    1.0f);
-            const float g = u * fmaf(tf[c].curve, u, tf[c].one_m_curve);
+            const float g = u * fmaf(tf[c].curve, u, tf_omc[c]);
             amax = fmaxf(amax, tf[c].alpha_mul * g);
             const float gc = kLit ? g * shade[c] : g;
             r = fmaf(gc, tf[c].rgb[0], r);
